@@ -1,0 +1,181 @@
+"""Oracle model: the equilibrium absorber constraints of one scenario, in plain
+PyTorch CPU float64.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this module;
+only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` use it.
+
+The residuals follow the paper's equations directly:
+
+* material balance, eq. (1), with zero side feeds;
+* reaction equilibrium in activities, eq. (3a), with ideal-liquid activities
+  a_i = x_i (Case study, thermodynamics paragraph) and the Kent-Eisenberg form
+  of ln K_r(T);
+* summations, eq. (4);
+* Raoult's law for water, eq. (9a), and Henry's law for CO2, eq. (9b);
+* stage energy balance, eq. (6), with Q_n = 0 and the ideal-mixture enthalpies
+  of the case study (component enthalpy from a reference value plus the heat
+  capacity integral);
+* the hydraulic superficial-velocity constraint, eq. (10b).
+
+Exact first and second derivatives come from the autograd library
+(``torch.func.jacfwd`` and ``torch.func.hessian``) applied to these residuals,
+so the oracle carries no hand-derived derivative.
+
+Local layout of one stage (21 free variables):
+  0-8   x of MEA, MEAH+, H+, MEACOO-, HCO3-, OH-, CO3--, CO2, H2O
+  9-12  y of CO2, H2O, N2, O2
+  13 L, 14 V, 15 T, 16-20 reaction extents eps_1..eps_5
+The 9 fixed variables (y of the 7 non-volatile species, x of N2 and O2) are
+zero and do not appear.
+
+Row layout of one stage (22 rows):
+  0-10  material balances of the 11 species, eq. (1)
+  11-15 reaction equilibria R1..R5, eq. (3a)
+  16    liquid summation, 17 vapour summation, eq. (4)
+  18    water VLE (9a), 19 CO2 VLE (9b)
+  20    energy balance (6)
+  21    hydraulic inequality (10b), g <= 0
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+NV = 21  # free variables per stage
+NR = 22  # rows per stage (21 MESH equalities + 1 hydraulic inequality)
+NLIQ = 9
+NVAP = 4
+IL, IV, IT, IE = 13, 14, 15, 16
+
+
+class OracleParams:
+    """Constants of params.json as float64 tensors."""
+
+    def __init__(self, p: dict):
+        f = lambda a: torch.tensor(a, dtype=torch.float64)  # noqa: E731
+        self.nu = f(p["nu"])  # (11, 5)
+        self.A, self.B = f(p["lnK_A"]), f(p["lnK_B"])
+        self.C, self.D = f(p["lnK_C"]), f(p["lnK_D"])
+        self.psat_a, self.psat_b = float(p["psat_a"]), float(p["psat_b"])
+        self.lnH298 = float(p["henry_lnH298"])
+        self.kH = float(p["henry_kappa"])
+        self.TH = float(p["henry_Tref"])
+        self.lnrMEA = float(p["henry_ln_ratio_MEA"])
+        self.Tref = float(p["Tref"])
+        self.hL_ref, self.cpL_a, self.cpL_b = f(p["hL_ref"]), f(p["cpL_a"]), f(p["cpL_b"])
+        self.hV_ref, self.cpV_a, self.cpV_b = f(p["hV_ref"]), f(p["cpV_a"]), f(p["cpV_b"])
+        self.R = float(p["R"])
+        self.u_max = float(p["u_max"])
+        self.raw = p
+
+
+def _h(T, href, a, b, Tref):
+    """Component molar enthalpy h(T) = href + int_Tref^T (a + b t) dt, for T (...,)."""
+    T = T[..., None]
+    return href + a * (T - Tref) + 0.5 * b * (T * T - Tref * Tref)
+
+
+def scenario_constraints(Z: torch.Tensor, d: torch.Tensor, feed: torch.Tensor, P: OracleParams) -> torch.Tensor:
+    """All 22 rows of every stage of one scenario.
+
+    Z: (N, 21) free variables, stages bottom (index 0) to top; d: scalar tensor
+    (the diameter); feed: (18,) feed-table row.  Returns (N, 22).
+    """
+    x, y = Z[:, 0:NLIQ], Z[:, NLIQ:NLIQ + NVAP]
+    L, V, T, eps = Z[:, IL], Z[:, IV], Z[:, IT], Z[:, IE:IE + 5]
+    Pabs = feed[17]
+
+    # stream entering each stage from above (liquid) and from below (vapour)
+    L_up = torch.cat([L[1:], feed[6:7]])
+    x_up = torch.cat([x[1:], feed[7:16][None, :]], dim=0)
+    T_up = torch.cat([T[1:], feed[16:17]])
+    V_dn = torch.cat([feed[0:1], V[:-1]])
+    y_dn = torch.cat([feed[1:5][None, :], y[:-1]], dim=0)
+    T_dn = torch.cat([feed[5:6], T[:-1]])
+
+    n = Z.shape[0]
+    zero2 = torch.zeros((n, 2), dtype=Z.dtype)
+    zero7 = torch.zeros((n, 7), dtype=Z.dtype)
+    X = torch.cat([x, zero2], dim=1)  # 11 species, N2 and O2 fixed to 0
+    Xup = torch.cat([x_up, zero2], dim=1)
+    Y = torch.cat([zero7, y], dim=1)  # 11 species, non-volatiles fixed to 0
+    Ydn = torch.cat([zero7, y_dn], dim=1)
+
+    # (1) material balance: out - in - generation
+    mb = L[:, None] * X + V[:, None] * Y - L_up[:, None] * Xup - V_dn[:, None] * Ydn - eps @ P.nu.T
+
+    # (3a) ideal activities a_i = x_i, Kent-Eisenberg ln K_r(T)
+    lnK = P.A + P.B / T[:, None] + P.C * torch.log(T)[:, None] + P.D * T[:, None]
+    rx = torch.log(x) @ P.nu[:NLIQ, :] - lnK
+
+    # (4) summations
+    sl = x.sum(dim=1) - 1.0
+    sv = y.sum(dim=1) - 1.0
+
+    # (9a) Raoult's law for water, (9b) Henry's law for CO2 (c_CO2 read as x_CO2)
+    psat = torch.exp(P.psat_a - P.psat_b / T)
+    vle_w = Pabs * y[:, 1] - x[:, 8] * psat
+    amine = x[:, 0] + x[:, 1] + x[:, 3]
+    xapp_mea = amine / (amine + x[:, 8])
+    lnH = P.lnH298 + P.kH * (1.0 / P.TH - 1.0 / T) + xapp_mea * P.lnrMEA
+    vle_c = Pabs * y[:, 0] - x[:, 7] * torch.exp(lnH)
+
+    # (6) energy balance with ideal-mixture enthalpies, Q = 0
+    hL = lambda xx, TT: (xx * _h(TT, P.hL_ref, P.cpL_a, P.cpL_b, P.Tref)).sum(dim=-1)  # noqa: E731
+    hV = lambda yy, TT: (yy * _h(TT, P.hV_ref, P.cpV_a, P.cpV_b, P.Tref)).sum(dim=-1)  # noqa: E731
+    eb = L * hL(x, T) + V * hV(y, T) - L_up * hL(x_up, T_up) - V_dn * hV(y_dn, T_dn)
+
+    # (10b) hydraulic: volumetric gas flow against the velocity limit
+    hyd = V * P.R * T / Pabs - P.u_max * math.pi * d * d / 4.0
+
+    return torch.cat([mb, rx, sl[:, None], sv[:, None], vle_w[:, None], vle_c[:, None],
+                      eb[:, None], hyd[:, None]], dim=1)
+
+
+def _flat(P, feed, N):
+    def fn(w):
+        Z = w[:-1].reshape(N, NV)
+        return scenario_constraints(Z, w[-1], feed, P).reshape(-1)
+    return fn
+
+
+def constraints(Zall: np.ndarray, d: float, feeds: np.ndarray, P: OracleParams) -> np.ndarray:
+    """c for all scenarios: Zall (S, N, 21), feeds (S, 18) -> (S, N, 22)."""
+    S, N, _ = Zall.shape
+    out = np.empty((S, N, NR))
+    dt = torch.tensor(d, dtype=torch.float64)
+    for w in range(S):
+        out[w] = scenario_constraints(torch.from_numpy(np.ascontiguousarray(Zall[w])), dt,
+                                      torch.from_numpy(feeds[w]), P).numpy()
+    return out
+
+
+def jacobian(Zs: np.ndarray, d: float, feed: np.ndarray, P: OracleParams) -> np.ndarray:
+    """Dense Jacobian of one scenario's 22N rows w.r.t. its 21N variables and d.
+
+    Returns (22N, 21N + 1); the last column is d/dd.
+    """
+    N = Zs.shape[0]
+    w = torch.cat([torch.from_numpy(np.ascontiguousarray(Zs)).reshape(-1), torch.tensor([d], dtype=torch.float64)])
+    return torch.func.jacfwd(_flat(P, torch.from_numpy(feed), N))(w).numpy()
+
+
+def lagrangian_hessian(Zs: np.ndarray, d: float, feed: np.ndarray, lam: np.ndarray, P: OracleParams) -> np.ndarray:
+    """Dense Hessian of sum_j lam_j c_j (one scenario) w.r.t. (Z, d): (21N+1, 21N+1)."""
+    N = Zs.shape[0]
+    f = _flat(P, torch.from_numpy(feed), N)
+    lt = torch.from_numpy(np.ascontiguousarray(lam).reshape(-1))
+    w = torch.cat([torch.from_numpy(np.ascontiguousarray(Zs)).reshape(-1), torch.tensor([d], dtype=torch.float64)])
+    H = torch.func.hessian(lambda v: (lt * f(v)).sum())(w).numpy()
+    return 0.5 * (H + H.T)  # forward-over-reverse AD is symmetric up to rounding
+
+
+def row_hessian(Zs: np.ndarray, d: float, feed: np.ndarray, row: int, P: OracleParams) -> np.ndarray:
+    """Hessian of a single flattened row index of one scenario."""
+    lam = np.zeros(Zs.shape[0] * NR)
+    lam[row] = 1.0
+    return lagrangian_hessian(Zs, d, feed, lam, P)
