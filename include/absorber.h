@@ -1,0 +1,188 @@
+/*
+ * absorber.h -- C ABI of the MI355X (gfx950) interior-point solver for the
+ * scenario-based equilibrium CO2-absorber diameter-minimisation NLP.
+ *
+ * The problem is eq. (10) of the paper: minimise the shared column diameter d
+ * subject to, for every scenario w and stage n, the MESH equations (material
+ * balance (1), reaction equilibrium (3a), summations (4), energy balance (6),
+ * Raoult/Henry VLE (9a)/(9b)) and the hydraulic inequality (10b), with bounds
+ * (10c)-(10d).  Scenarios share only d (problem construction, replicated
+ * scenario structure), so the primal-dual KKT matrix is block-bordered: one
+ * block per scenario plus the d row/column.
+ *
+ * Conventions for every call:
+ *  - S scenarios, N stages (numbered bottom to top), 21 free variables and 22
+ *    rows per stage (see "Layouts").
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch tensors);
+ *    pointers named *_host are host pointers.  The library never frees caller
+ *    memory; the handle owns all of its internal buffers.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    taking a stream are asynchronous on it unless marked "blocking".
+ *  - Every call returns ABS_OK (0) or a negative ABS_ERR_* code; the message of
+ *    the last error of the calling thread is absorber_last_error().
+ *
+ * Layouts (all double precision):
+ *  - primal x: length nx = S*N*21 + 1, x[(w*N + n)*21 + k], d = x[nx-1].
+ *    Local k: 0-8 liquid x of MEA, MEAH+, H+, MEACOO-, HCO3-, OH-, CO3--, CO2,
+ *    H2O; 9-12 vapour y of CO2, H2O, N2, O2; 13 L; 14 V; 15 T; 16-20 reaction
+ *    extents of R1-R5.  The 9 variables fixed to zero per stage (vapour
+ *    fractions of the 7 non-volatiles, liquid N2 and O2) are not stored.
+ *  - rows c / multipliers lambda: length nc = S*N*22, c[(w*N + n)*22 + r].
+ *    r: 0-10 material balances of the 11 species, 11-15 reactions R1-R5,
+ *    16/17 liquid/vapour summation, 18 water VLE, 19 CO2 VLE, 20 energy
+ *    balance, 21 hydraulic row g = V R T / P - u_max pi d^2 / 4 (g <= 0).
+ *  - KKT vectors: length nkkt = S*N*43 + 1, v[(w*N + n)*43 + k]; k 0-20 primal,
+ *    21-41 multipliers of the 21 MESH rows, 42 multiplier of the hydraulic row;
+ *    the d entry last.
+ *  - feeds: host array [S][18]: V0, y0 (CO2, H2O, N2, O2), T_gas, L_in,
+ *    x_in (9 liquid species), T_liq, P_abs.
+ */
+#ifndef ABSORBER_H
+#define ABSORBER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABS_OK 0
+#define ABS_ERR_ARG (-1)       /* bad argument (null pointer, size out of range) */
+#define ABS_ERR_HIP (-2)       /* a HIP runtime call failed */
+#define ABS_ERR_OOM (-3)       /* device allocation failed */
+#define ABS_ERR_STATE (-4)     /* call order violated (e.g. kkt_solve before kkt_factor) */
+#define ABS_ERR_INERTIA (-10)  /* inertia correction exceeded delta_w_max */
+#define ABS_ERR_LS (-11)       /* line search step below alpha_min (no restoration phase) */
+#define ABS_ERR_MAXITER (-12)  /* iteration limit reached */
+#define ABS_ERR_NAN (-13)      /* NaN or Inf in an evaluation */
+#define ABS_ERR_DIVERGE (-14)  /* |x| above 1e20 */
+
+typedef struct absorber_handle absorber_t;
+
+/* Problem constants (the paper prints the model forms; the values are inputs). */
+typedef struct {
+  double nu[11][5];                       /* stoichiometry of R1-R5 (species x reaction) */
+  double lnK_A[5], lnK_B[5], lnK_C[5], lnK_D[5]; /* ln K_r = A + B/T + C ln T + D T */
+  double psat_a, psat_b;                  /* ln Psat[Pa] = a - b / T */
+  double henry_lnH298, henry_kappa, henry_Tref, henry_ln_ratio_MEA;
+  double Tref;                            /* enthalpy reference temperature [K] */
+  double hL_ref[9], cpL_a[9], cpL_b[9];   /* liquid h_i(T) = href + a (T-Tref) + b/2 (T^2-Tref^2) */
+  double hV_ref[4], cpV_a[4], cpV_b[4];   /* vapour (CO2, H2O, N2, O2) */
+  double R, u_max;
+  double x_lo, x_hi, y_lo, y_hi, L_lo, L_hi, V_lo, V_hi, T_lo, T_hi, d_lo, d_hi;
+  double x0[21];                          /* cold-start value of every stage */
+  double d0;                              /* cold-start diameter */
+} absorber_params;
+
+typedef struct {
+  int64_t n_var_total;   /* 30*N*S + 1, counting the fixed variables */
+  int64_t n_var_free;    /* 21*N*S + 1 */
+  int64_t n_eq;          /* 21*N*S MESH equalities */
+  int64_t n_fixed;       /* 9*N*S variable-fixing constraints */
+  int64_t n_ineq;        /* N*S hydraulic inequalities */
+  int64_t nnz_jac;       /* entries of the Jacobian structure */
+  int64_t nnz_hess;      /* entries of the lower-triangle Hessian structure */
+  int64_t kkt_dim;       /* 43*N*S + 1 */
+} absorber_dims;
+
+/* Create a problem instance: N stages, S scenarios, feed table feeds_host[S][18].
+ * Allocates the device state on the current device.  Blocking. */
+int absorber_create(const absorber_params* params, int32_t n_stages, int32_t n_scen,
+                    const double* feeds_host, absorber_t** out);
+void absorber_destroy(absorber_t* h);
+int absorber_get_dims(const absorber_t* h, absorber_dims* out);
+
+/* Write the cold-start point (the same stage vector for every stage, d0) into
+ * x_dev[nx] (unpushed: the interior-point method applies its bound push). */
+int absorber_initial_point(absorber_t* h, double* x_dev, void* stream);
+
+/* Scaling used by kkt_factor / kkt_solve: variables x = D * xt with
+ * var_scale_host[22] = D of the 21 stage locals then of d; rows c~ = cs * c with
+ * row_scale_dev[nc] (NULL: all ones).  Default: no scaling.  Blocking. */
+int absorber_set_scaling(absorber_t* h, const double* var_scale_host, const double* row_scale_dev);
+
+/* Residuals of all rows at x (unscaled), c_dev[nc]: the MESH rows of eq.
+ * (1), (3a), (4), (9a), (9b), (6) and the hydraulic row (10b). */
+int absorber_eval_cons(absorber_t* h, const double* x_dev, double* c_dev, void* stream);
+
+/* Objective f = d (10a): f_host gets d; grad_dev[nx] = e_d.  Blocking. */
+int absorber_eval_obj(absorber_t* h, const double* x_dev, double* f_host, double* grad_dev, void* stream);
+
+/* Jacobian structure: row/col indices (host arrays of length nnz_jac).  Per
+ * stage: the stage's own block, the hydraulic d entry, then (if the stage is
+ * not the top one) the block of the stage above, then (if not the bottom one)
+ * the block of the stage below; stages in (w, n) order.  Blocking. */
+int absorber_jac_structure(const absorber_t* h, int64_t* rows_host, int64_t* cols_host);
+int absorber_eval_jac(absorber_t* h, const double* x_dev, double* vals_dev, void* stream);
+
+/* Lower-triangle structure of the Lagrangian Hessian: 48 entries per stage in
+ * (w, n) order (the Hessian is block diagonal by stage), then the (d, d)
+ * entry.  Blocking. */
+int absorber_hess_structure(const absorber_t* h, int64_t* rows_host, int64_t* cols_host);
+/* Values of obj_factor * grad^2 f + sum_j lambda_j grad^2 c_j (grad^2 f = 0). */
+int absorber_eval_hess(absorber_t* h, const double* x_dev, const double* lambda_dev, double obj_factor,
+                       double* vals_dev, void* stream);
+
+/* Factorise the slack-reduced primal-dual KKT matrix in the scaled variables
+ *   [[W~ + diag(sigma_x) + dw I,  J~^T                                  ],
+ *    [J~,                         -diag(dc (MESH rows), 1/(sigma_s+dw)+dc)]]
+ * where J~ = diag(cs) J D and W~ = D (sum_j lambda_j cs_j grad^2 c_j) D at x
+ * (original units), lambda_dev[nc] the multipliers of the scaled rows,
+ * sigma_x_dev[nx] (scaled variables, entry nx-1 belongs to d) and
+ * sigma_s_dev[S*N].  Each scenario block is factorised by a block LDL^T over
+ * its stages with Bunch-Kaufman pivoting inside every stage tile, and the d row
+ * by the Schur complement S_d.  inertia_host[3] = (n+, n-, n0) of the whole
+ * matrix (Haynsworth: sum of the blocks' inertias plus the sign of S_d).  The
+ * factors stay in the handle for kkt_solve.  Blocking. */
+int absorber_kkt_factor(absorber_t* h, const double* x_dev, const double* lambda_dev,
+                        const double* sigma_x_dev, const double* sigma_s_dev, double delta_w,
+                        double delta_c, int64_t* inertia_host, void* stream);
+
+/* Solve with the last factorisation: sol_dev[nkkt] = K^{-1} rhs_dev[nkkt],
+ * iteratively refined on the whole bordered system until the componentwise
+ * backward error stops improving (at most 10 rounds).  rel_resid_host gets
+ * ||K sol - rhs||_inf / ||rhs||_inf.  Blocking. */
+int absorber_kkt_solve(absorber_t* h, const double* rhs_dev, double* sol_dev, double* rel_resid_host,
+                       void* stream);
+
+/* Interior-point options; absorber_ipm_default_options fills the defaults. */
+typedef struct {
+  double tol;               /* scaled optimality error E_0 (1e-8) */
+  int32_t max_iter;         /* 500 */
+  int32_t warm_start;       /* 0: cold start; 1: x0/y0 given, small mu0 and bound push */
+  double mu_init;           /* 0.1 */
+  double warm_mu_init;      /* 1e-6 */
+  double bound_push;        /* 1e-2 (kappa_1 = kappa_2) */
+  double warm_bound_push;   /* 1e-8 */
+  double nlp_scaling_max_gradient; /* 100 */
+  int32_t print_level;      /* 0 silent, 1 one line per iteration to stderr */
+  int32_t use_graph;        /* reserved */
+} absorber_ipm_options;
+
+typedef struct {
+  int32_t status;           /* ABS_OK or an ABS_ERR_* code */
+  int32_t iterations;
+  double E0;                /* final scaled optimality error */
+  double inf_pr, inf_du, compl_;
+  double d;                 /* optimal diameter */
+  double seconds;           /* wall time of the solve */
+  int32_t n_inertia_corrections;
+  int32_t n_factorizations;
+  double max_lin_resid;     /* largest relative linear residual of the KKT solves */
+} absorber_ipm_result;
+
+void absorber_ipm_default_options(absorber_ipm_options* opts);
+
+/* Run the interior-point method to E_0 <= tol.  x0_dev[nx] (original units) and
+ * lambda0_dev[nc] may be NULL (cold start).  On return x_out_dev[nx] and
+ * lambda_out_dev[nc] (may be NULL) hold the final iterate.  Blocking. */
+int absorber_ipm_solve(absorber_t* h, const absorber_ipm_options* opts, const double* x0_dev,
+                       const double* lambda0_dev, double* x_out_dev, double* lambda_out_dev,
+                       absorber_ipm_result* result);
+
+const char* absorber_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABSORBER_H */

@@ -1,0 +1,280 @@
+"""ctypes binding of libabsorber.so: one Python method per C entry point.
+
+Device arrays are passed as raw pointers (``tensor.data_ptr()`` of contiguous
+float64 CUDA tensors); every computation happens in the HIP library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabsorber.so")
+
+ABS_OK = 0
+ERRORS = {
+    -1: "ABS_ERR_ARG", -2: "ABS_ERR_HIP", -3: "ABS_ERR_OOM", -4: "ABS_ERR_STATE",
+    -10: "ABS_ERR_INERTIA", -11: "ABS_ERR_LS", -12: "ABS_ERR_MAXITER", -13: "ABS_ERR_NAN",
+    -14: "ABS_ERR_DIVERGE",
+}
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_int64_p = ctypes.POINTER(ctypes.c_int64)
+
+
+class AbsorberError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class AbsorberParams(ctypes.Structure):
+    _fields_ = [
+        ("nu", ctypes.c_double * 5 * 11),
+        ("lnK_A", ctypes.c_double * 5), ("lnK_B", ctypes.c_double * 5),
+        ("lnK_C", ctypes.c_double * 5), ("lnK_D", ctypes.c_double * 5),
+        ("psat_a", ctypes.c_double), ("psat_b", ctypes.c_double),
+        ("henry_lnH298", ctypes.c_double), ("henry_kappa", ctypes.c_double),
+        ("henry_Tref", ctypes.c_double), ("henry_ln_ratio_MEA", ctypes.c_double),
+        ("Tref", ctypes.c_double),
+        ("hL_ref", ctypes.c_double * 9), ("cpL_a", ctypes.c_double * 9), ("cpL_b", ctypes.c_double * 9),
+        ("hV_ref", ctypes.c_double * 4), ("cpV_a", ctypes.c_double * 4), ("cpV_b", ctypes.c_double * 4),
+        ("R", ctypes.c_double), ("u_max", ctypes.c_double),
+        ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double), ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
+        ("L_lo", ctypes.c_double), ("L_hi", ctypes.c_double), ("V_lo", ctypes.c_double), ("V_hi", ctypes.c_double),
+        ("T_lo", ctypes.c_double), ("T_hi", ctypes.c_double), ("d_lo", ctypes.c_double), ("d_hi", ctypes.c_double),
+        ("x0", ctypes.c_double * 21), ("d0", ctypes.c_double),
+    ]
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_var_total", "n_var_free", "n_eq", "n_fixed", "n_ineq",
+                                               "nnz_jac", "nnz_hess", "kkt_dim")]
+
+
+class IpmOptions(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+        ("mu_init", ctypes.c_double), ("warm_mu_init", ctypes.c_double), ("bound_push", ctypes.c_double),
+        ("warm_bound_push", ctypes.c_double), ("nlp_scaling_max_gradient", ctypes.c_double),
+        ("print_level", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+    ]
+
+
+class IpmResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("E0", ctypes.c_double),
+        ("inf_pr", ctypes.c_double), ("inf_du", ctypes.c_double), ("compl_", ctypes.c_double),
+        ("d", ctypes.c_double), ("seconds", ctypes.c_double), ("n_inertia_corrections", ctypes.c_int32),
+        ("n_factorizations", ctypes.c_int32), ("max_lin_resid", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libabsorber.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_15420_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "absorber_create": (ctypes.c_int, [ctypes.POINTER(AbsorberParams), i32, i32, c_double_p,
+                                               ctypes.POINTER(vp)]),
+            "absorber_destroy": (None, [vp]),
+            "absorber_get_dims": (ctypes.c_int, [vp, ctypes.POINTER(Dims)]),
+            "absorber_initial_point": (ctypes.c_int, [vp, vp, vp]),
+            "absorber_set_scaling": (ctypes.c_int, [vp, c_double_p, vp]),
+            "absorber_eval_cons": (ctypes.c_int, [vp, vp, vp, vp]),
+            "absorber_eval_obj": (ctypes.c_int, [vp, vp, c_double_p, vp, vp]),
+            "absorber_jac_structure": (ctypes.c_int, [vp, c_int64_p, c_int64_p]),
+            "absorber_eval_jac": (ctypes.c_int, [vp, vp, vp, vp]),
+            "absorber_hess_structure": (ctypes.c_int, [vp, c_int64_p, c_int64_p]),
+            "absorber_eval_hess": (ctypes.c_int, [vp, vp, vp, dbl, vp, vp]),
+            "absorber_kkt_factor": (ctypes.c_int, [vp, vp, vp, vp, vp, dbl, dbl, c_int64_p, vp]),
+            "absorber_kkt_solve": (ctypes.c_int, [vp, vp, vp, c_double_p, vp]),
+            "absorber_ipm_default_options": (None, [ctypes.POINTER(IpmOptions)]),
+            "absorber_ipm_solve": (ctypes.c_int, [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp,
+                                                  ctypes.POINTER(IpmResult)]),
+            "absorber_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != ABS_OK:
+        raise AbsorberError(rc, lib().absorber_last_error().decode())
+    return rc
+
+
+def params_struct(p: dict) -> AbsorberParams:
+    """Fill the C parameter struct from the problem-data dict (params.json)."""
+    s = AbsorberParams()
+    for i in range(11):
+        for r in range(5):
+            s.nu[i][r] = p["nu"][i][r]
+    for f in ("lnK_A", "lnK_B", "lnK_C", "lnK_D"):
+        for r in range(5):
+            getattr(s, f)[r] = p[f][r]
+    for f in ("psat_a", "psat_b", "henry_lnH298", "henry_kappa", "henry_Tref", "henry_ln_ratio_MEA", "Tref",
+              "R", "u_max"):
+        setattr(s, f, float(p[f]))
+    for f in ("hL_ref", "cpL_a", "cpL_b"):
+        for i in range(9):
+            getattr(s, f)[i] = p[f][i]
+    for f in ("hV_ref", "cpV_a", "cpV_b"):
+        for j in range(4):
+            getattr(s, f)[j] = p[f][j]
+    b = p["bounds"]
+    s.x_lo, s.x_hi = b["x"]
+    s.y_lo, s.y_hi = b["y"]
+    s.L_lo, s.L_hi = b["L"]
+    s.V_lo, s.V_hi = b["V"]
+    s.T_lo, s.T_hi = b["T"]
+    s.d_lo, s.d_hi = b["d"]
+    ip = p["initial_point"]
+    z = list(ip["x"]) + list(ip["y"]) + [ip["L"], ip["V"], ip["T"]] + [ip["eps"]] * 5
+    for k in range(21):
+        s.x0[k] = float(z[k])
+    s.d0 = float(ip["d"])
+    return s
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64/int tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Absorber:
+    """Handle of one problem instance (S scenarios, N stages) on the current GPU."""
+
+    def __init__(self, params: dict, n_stages: int, feeds: np.ndarray):
+        feeds = np.ascontiguousarray(feeds, dtype=np.float64)
+        if feeds.ndim != 2 or feeds.shape[1] != 18:
+            raise ValueError("feeds must be (S, 18)")
+        self._p = params_struct(params)
+        h = ctypes.c_void_p()
+        _check(lib().absorber_create(ctypes.byref(self._p), int(n_stages), int(feeds.shape[0]),
+                                     feeds.ctypes.data_as(c_double_p), ctypes.byref(h)))
+        self.h = h
+        self.N, self.S = int(n_stages), int(feeds.shape[0])
+        d = self.dims()
+        self.nx = d["n_var_free"]
+        self.nc = self.N * self.S * 22
+        self.nkkt = d["kkt_dim"]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().absorber_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dims(self) -> dict:
+        d = Dims()
+        _check(lib().absorber_get_dims(self.h, ctypes.byref(d)))
+        return {k: getattr(d, k) for k, _ in d._fields_}
+
+    def initial_point(self, x, stream=None):
+        _check(lib().absorber_initial_point(self.h, _ptr(x), _stream(stream)))
+
+    def set_scaling(self, var_scale=None, row_scale=None):
+        vs = None
+        if var_scale is not None:
+            arr = np.ascontiguousarray(var_scale, dtype=np.float64)
+            if arr.size != 22:
+                raise ValueError("var_scale must have 22 entries")
+            self._vs = arr
+            vs = arr.ctypes.data_as(c_double_p)
+        _check(lib().absorber_set_scaling(self.h, vs, _ptr(row_scale)))
+
+    def eval_cons(self, x, c, stream=None):
+        _check(lib().absorber_eval_cons(self.h, _ptr(x), _ptr(c), _stream(stream)))
+
+    def eval_obj(self, x, grad=None, stream=None):
+        f = ctypes.c_double()
+        _check(lib().absorber_eval_obj(self.h, _ptr(x), ctypes.byref(f), _ptr(grad), _stream(stream)))
+        return f.value
+
+    def jac_structure(self):
+        n = self.dims()["nnz_jac"]
+        rows, cols = np.empty(n, np.int64), np.empty(n, np.int64)
+        _check(lib().absorber_jac_structure(self.h, rows.ctypes.data_as(c_int64_p), cols.ctypes.data_as(c_int64_p)))
+        return rows, cols
+
+    def eval_jac(self, x, vals, stream=None):
+        _check(lib().absorber_eval_jac(self.h, _ptr(x), _ptr(vals), _stream(stream)))
+
+    def hess_structure(self):
+        n = self.dims()["nnz_hess"]
+        rows, cols = np.empty(n, np.int64), np.empty(n, np.int64)
+        _check(lib().absorber_hess_structure(self.h, rows.ctypes.data_as(c_int64_p),
+                                             cols.ctypes.data_as(c_int64_p)))
+        return rows, cols
+
+    def eval_hess(self, x, lam, vals, obj_factor=1.0, stream=None):
+        _check(lib().absorber_eval_hess(self.h, _ptr(x), _ptr(lam), float(obj_factor), _ptr(vals),
+                                        _stream(stream)))
+
+    def kkt_factor(self, x, lam, sigma_x, sigma_s, delta_w=0.0, delta_c=0.0, stream=None):
+        inert = np.zeros(3, np.int64)
+        _check(lib().absorber_kkt_factor(self.h, _ptr(x), _ptr(lam), _ptr(sigma_x), _ptr(sigma_s),
+                                         float(delta_w), float(delta_c), inert.ctypes.data_as(c_int64_p),
+                                         _stream(stream)))
+        return tuple(int(v) for v in inert)
+
+    def kkt_solve(self, rhs, sol, stream=None):
+        rel = ctypes.c_double()
+        _check(lib().absorber_kkt_solve(self.h, _ptr(rhs), _ptr(sol), ctypes.byref(rel), _stream(stream)))
+        return rel.value
+
+    @staticmethod
+    def default_options(**kw) -> IpmOptions:
+        o = IpmOptions()
+        lib().absorber_ipm_default_options(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def ipm_solve(self, opts: IpmOptions | None = None, x0=None, lam0=None, x_out=None, lam_out=None,
+                  check=False) -> IpmResult:
+        """Run the interior-point method; returns the result struct (status in .status)."""
+        o = opts if opts is not None else self.default_options()
+        r = IpmResult()
+        rc = lib().absorber_ipm_solve(self.h, ctypes.byref(o), _ptr(x0), _ptr(lam0), _ptr(x_out), _ptr(lam_out),
+                                      ctypes.byref(r))
+        if check:
+            _check(rc)
+        return r
+
+
+def absorber_create(params: dict, n_stages: int, feeds: np.ndarray) -> Absorber:
+    return Absorber(params, n_stages, feeds)

@@ -1,0 +1,456 @@
+// C ABI of the absorber library: handle management, structures, evaluation and
+// the KKT factorise/solve entry points.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace absorber {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+struct StructSink {
+  std::vector<JacEntry>* own;
+  std::vector<JacEntry>* up;
+  std::vector<JacEntry>* down;
+  int d_index = -1;
+  void operator()(int r, int blk, int col, double) {
+    JacEntry e{(int8_t)r, (int8_t)blk, (int8_t)col};
+    if (blk == BLK_OWN || blk == BLK_D) {
+      if (blk == BLK_D) d_index = (int)own->size();
+      own->push_back(e);
+    } else if (blk == BLK_UP) {
+      up->push_back(e);
+    } else {
+      down->push_back(e);
+    }
+  }
+};
+
+int coupling_slot_of(int local) {  // inverse of coupling_index, -1 if not a coupling index
+  for (int a = 0; a < NC; ++a)
+    if (coupling_index(a) == local) return a;
+  return -1;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// Build the Jacobian structure (by running the same emission code as the
+// device kernels on a dummy interior point) and the frontal gather table.
+static int build_tables(Handle& h) {
+  double z[NV];
+  for (int k = 0; k < NV; ++k) z[k] = 0.1 + 0.01 * k;
+  z[IT] = 320.0;
+  double feed[NF];
+  for (int i = 0; i < NF; ++i) feed[i] = 0.1;
+  feed[16] = feed[5] = 320.0;
+  feed[17] = 1e5;
+  Inflow f;
+  make_inflow(z, z, feed, f);
+  StructSink ss{&h.jac_own, &h.jac_up, &h.jac_down};
+  stage_jacobian(h.mp, z, f, 1e5, 1.0, true, true, ss);
+  h.jac_d_index = ss.d_index;
+  if ((int)h.jac_own.size() != NJO || (int)h.jac_up.size() != NJU || (int)h.jac_down.size() != NJD) {
+    set_error("unexpected Jacobian structure (the stoichiometry must have the pattern of R1-R5)");
+    return ABS_ERR_ARG;
+  }
+  hess_positions(h.hpos);
+  // gather table: up to three LDS source indices per frontal position
+  std::vector<int> cnt(FR * 64, 0), tab(FR * 64, 0);
+  bool overflow = false;
+  auto put = [&](int i, int j, int src) {
+    const int p = i * 64 + j;
+    if (cnt[p] >= 3) {
+      overflow = true;
+      return;
+    }
+    tab[p] |= src << (10 * cnt[p]);
+    ++cnt[p];
+  };
+  auto put2 = [&](int i, int j, int src) {
+    put(i, j, src);
+    if (i != j) put(j, i, src);
+  };
+  for (int e = 0; e < NJO; ++e) {
+    const JacEntry& je = h.jac_own[e];
+    if (je.blk == BLK_D) {
+      put2(NK - 1, FR_B, SRC_BRD);
+      continue;
+    }
+    const int lr = je.row < NE ? NV + je.row : NK - 1;
+    put2(lr, je.col, SRC_REC + REC_OWN + e);
+  }
+  for (int e = 0; e < NJU; ++e) {
+    const JacEntry& je = h.jac_up[e];
+    const int a = coupling_slot_of(je.col);
+    put2(NK + a, NV + je.row, SRC_REC + REC_UP + e);
+  }
+  for (int e = 0; e < NJD; ++e) {
+    const JacEntry& je = h.jac_down[e];
+    const int a = coupling_slot_of(NV + je.row);
+    put2(NK + a, je.col, SRC_DOWN1 + e);
+  }
+  for (int e = 0; e < NH; ++e) put2(h.hpos[e].r, h.hpos[e].c, SRC_REC + REC_H + e);
+  for (int k = 0; k < NV; ++k) put(k, k, SRC_DIAGX + k);
+  for (int r = 0; r < NE; ++r) put(NV + r, NV + r, SRC_DC);
+  put(NK - 1, NK - 1, SRC_DHYD);
+  for (int k = 0; k < NK; ++k) put2(FR_R, k, SRC_RHS + k);
+  for (int a = 0; a < NC; ++a) {
+    for (int b = 0; b < NC; ++b) put(coupling_index(b), coupling_index(a), SRC_CTB + a * (NC + 2) + b);
+    put2(FR_R, coupling_index(a), SRC_CTB + a * (NC + 2) + NC);
+    put2(FR_B, coupling_index(a), SRC_CTB + a * (NC + 2) + NC + 1);
+  }
+  for (int e = 0; e < NJU; ++e)
+    if (coupling_slot_of(h.jac_up[e].col) < 0) overflow = true;
+  for (int e = 0; e < NJD; ++e)
+    if (coupling_slot_of(NV + h.jac_down[e].row) < 0) overflow = true;
+  if (overflow) {
+    set_error("internal: frontal gather table does not fit the stage structure");
+    return ABS_ERR_ARG;
+  }
+  HIP_TRY(dalloc(&h.gather, tab.size()));
+  HIP_TRY(hipMemcpy(h.gather, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+  std::vector<int> jt;
+  for (auto& e : h.jac_own) jt.push_back(e.row | (e.col << 8) | (e.blk << 16));
+  for (auto& e : h.jac_up) jt.push_back(e.row | (e.col << 8) | (e.blk << 16));
+  for (auto& e : h.jac_down) jt.push_back(e.row | (e.col << 8) | (e.blk << 16));
+  HIP_TRY(dalloc(&h.jtab, jt.size()));
+  HIP_TRY(hipMemcpy(h.jtab, jt.data(), jt.size() * sizeof(int), hipMemcpyHostToDevice));
+  return ABS_OK;
+}
+
+int initial_point(Handle& h, double* x_dev, hipStream_t st) {
+  std::vector<double> x0((size_t)h.nx);
+  for (long long t = 0; t < (long long)h.N * h.S; ++t)
+    for (int k = 0; k < NV; ++k) x0[t * NV + k] = h.x0[k];
+  x0[h.nx - 1] = h.x0[NV];
+  HIP_TRY(hipMemcpyAsync(x_dev, x0.data(), sizeof(double) * h.nx, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return ABS_OK;
+}
+
+static void free_handle(Handle& h) {
+  void* ptrs[] = {h.feeds, h.gather, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
+                  h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.redbuf};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h.scal_h) (void)hipHostFree(h.scal_h);
+  if (h.redbuf_h) (void)hipHostFree(h.redbuf_h);
+}
+
+// (re)allocate the scaled row-scale vector as ones
+static int reset_row_scale(Handle& h) {
+  std::vector<double> ones((size_t)h.nc, 1.0);
+  HIP_TRY(hipMemcpy(h.cs, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+  return ABS_OK;
+}
+
+}  // namespace absorber
+
+using namespace absorber;
+
+extern "C" {
+
+const char* absorber_last_error(void) { return g_last_error.c_str(); }
+
+int absorber_create(const absorber_params* prm, int32_t n_stages, int32_t n_scen, const double* feeds_host,
+                    absorber_t** out) {
+  if (!prm || !feeds_host || !out || n_stages < 1 || n_scen < 1 || n_stages > 4096) {
+    set_error("absorber_create: bad argument");
+    return ABS_ERR_ARG;
+  }
+  auto* H = new (std::nothrow) absorber_handle();
+  if (!H) return ABS_ERR_OOM;
+  Handle& h = H->h;
+  h.N = n_stages;
+  h.S = n_scen;
+  const long long nst = (long long)h.N * h.S;
+  h.nx = nst * NV + 1;
+  h.nc = nst * NR;
+  h.nkkt = nst * NK + 1;
+  ModelParams& mp = h.mp;
+  memcpy(mp.nu, prm->nu, sizeof(mp.nu));
+  for (int k = 0; k < 5; ++k) {
+    mp.A[k] = prm->lnK_A[k];
+    mp.B[k] = prm->lnK_B[k];
+    mp.C[k] = prm->lnK_C[k];
+    mp.D[k] = prm->lnK_D[k];
+  }
+  mp.psat_a = prm->psat_a;
+  mp.psat_b = prm->psat_b;
+  mp.lnH298 = prm->henry_lnH298;
+  mp.kH = prm->henry_kappa;
+  mp.TH = prm->henry_Tref;
+  mp.lnr = prm->henry_ln_ratio_MEA;
+  mp.Tref = prm->Tref;
+  for (int i = 0; i < 9; ++i) {
+    mp.hL_ref[i] = prm->hL_ref[i];
+    mp.cpL_a[i] = prm->cpL_a[i];
+    mp.cpL_b[i] = prm->cpL_b[i];
+  }
+  for (int j = 0; j < 4; ++j) {
+    mp.hV_ref[j] = prm->hV_ref[j];
+    mp.cpV_a[j] = prm->cpV_a[j];
+    mp.cpV_b[j] = prm->cpV_b[j];
+  }
+  mp.R = prm->R;
+  mp.u_max = prm->u_max;
+  for (int k = 0; k < NV; ++k) {
+    h.xL[k] = -INFINITY;
+    h.xU[k] = INFINITY;
+  }
+  for (int i = 0; i < 9; ++i) {
+    h.xL[IX + i] = prm->x_lo;
+    h.xU[IX + i] = prm->x_hi;
+  }
+  for (int j = 0; j < 4; ++j) {
+    h.xL[IY + j] = prm->y_lo;
+    h.xU[IY + j] = prm->y_hi;
+  }
+  h.xL[IL] = prm->L_lo;
+  h.xU[IL] = prm->L_hi;
+  h.xL[IV] = prm->V_lo;
+  h.xU[IV] = prm->V_hi;
+  h.xL[IT] = prm->T_lo;
+  h.xU[IT] = prm->T_hi;
+  h.dL = prm->d_lo;
+  h.dU = prm->d_hi;
+  for (int k = 0; k < NV; ++k) h.sc.D[k] = 1.0;
+  h.sc.Dd = 1.0;
+  h.feeds_h.assign(feeds_host, feeds_host + (size_t)h.S * NF);
+  static_assert(sizeof(absorber_params) > 0, "");
+  for (int k = 0; k < NV; ++k) h.x0[k] = prm->x0[k];
+  h.x0[NV] = prm->d0;
+  int rc = ABS_OK;
+  auto fail = [&](int code) {
+    free_handle(h);
+    delete H;
+    return code;
+  };
+#define ALLOC(ptr, n)                                                     \
+  do {                                                                    \
+    if (dalloc(&(ptr), (size_t)(n)) != hipSuccess) {                      \
+      set_error("absorber_create: device allocation failed (" #ptr ")"); \
+      return fail(ABS_ERR_OOM);                                           \
+    }                                                                     \
+  } while (0)
+  ALLOC(h.feeds, (size_t)h.S * NF);
+  ALLOC(h.cs, h.nc);
+  ALLOC(h.rec, nst * REC);
+  ALLOC(h.slots, nst * NK * SLOT);
+  ALLOC(h.solr, nst * NK);
+  ALLOC(h.solb, nst * NK);
+  ALLOC(h.inert, (size_t)h.S * 4);
+  ALLOC(h.part, (size_t)h.S * 4);
+  ALLOC(h.scal, 1);
+  ALLOC(h.diagx, h.nx);
+  ALLOC(h.diags, nst);
+  ALLOC(h.kres, h.nkkt);
+  ALLOC(h.kcor, h.nkkt);
+  ALLOC(h.kden, 3 * nst + 8);
+  h.red_cap = (int)std::max<long long>(64 * 1024, 9 * ((std::max<long long>(h.nx, std::max(h.nc, h.nkkt)) + 255) / 256) + 64);
+  ALLOC(h.redbuf, h.red_cap);
+#undef ALLOC
+  if (hipHostMalloc((void**)&h.scal_h, sizeof(DevScalars), 0) != hipSuccess ||
+      hipHostMalloc((void**)&h.redbuf_h, sizeof(double) * h.red_cap, 0) != hipSuccess) {
+    set_error("absorber_create: pinned host allocation failed");
+    return fail(ABS_ERR_OOM);
+  }
+  if (hipMemcpy(h.feeds, feeds_host, sizeof(double) * (size_t)h.S * NF, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(ABS_ERR_HIP);
+  if ((rc = build_tables(h)) != ABS_OK) return fail(rc);
+  if ((rc = reset_row_scale(h)) != ABS_OK) return fail(rc);
+  if (hipMemset(h.rec, 0, sizeof(double) * nst * REC) != hipSuccess) return fail(ABS_ERR_HIP);
+  *out = H;
+  return ABS_OK;
+}
+
+void absorber_destroy(absorber_t* H) {
+  if (!H) return;
+  free_handle(H->h);
+  delete H;
+}
+
+int absorber_get_dims(const absorber_t* H, absorber_dims* out) {
+  if (!H || !out) {
+    set_error("absorber_get_dims: bad argument");
+    return ABS_ERR_ARG;
+  }
+  const Handle& h = H->h;
+  const long long nst = (long long)h.N * h.S;
+  out->n_var_total = 30 * nst + 1;
+  out->n_var_free = 21 * nst + 1;
+  out->n_eq = 21 * nst;
+  out->n_fixed = 9 * nst;
+  out->n_ineq = nst;
+  out->nnz_jac = (long long)h.S * ((long long)h.N * NJO + (long long)(h.N - 1) * (NJU + NJD));
+  out->nnz_hess = nst * NH + 1;
+  out->kkt_dim = nst * NK + 1;
+  return ABS_OK;
+}
+
+int absorber_initial_point(absorber_t* H, double* x_dev, void* stream) {
+  if (!H || !x_dev) {
+    set_error("absorber_initial_point: bad argument");
+    return ABS_ERR_ARG;
+  }
+  return initial_point(H->h, x_dev, (hipStream_t)stream);
+}
+
+int absorber_set_scaling(absorber_t* H, const double* var_scale_host, const double* row_scale_dev) {
+  if (!H) {
+    set_error("absorber_set_scaling: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = H->h;
+  for (int k = 0; k < NV; ++k) h.sc.D[k] = var_scale_host ? var_scale_host[k] : 1.0;
+  h.sc.Dd = var_scale_host ? var_scale_host[NV] : 1.0;
+  if (row_scale_dev) {
+    HIP_TRY(hipMemcpy(h.cs, row_scale_dev, sizeof(double) * h.nc, hipMemcpyDeviceToDevice));
+  } else {
+    return reset_row_scale(h);
+  }
+  return ABS_OK;
+}
+
+int absorber_eval_cons(absorber_t* H, const double* x_dev, double* c_dev, void* stream) {
+  if (!H || !x_dev || !c_dev) {
+    set_error("absorber_eval_cons: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = H->h;
+  Scaling one{};
+  for (int k = 0; k < NV; ++k) one.D[k] = 1.0;
+  one.Dd = 1.0;
+  HIP_TRY(launch_eval_ext(h, x_dev, 0, one, nullptr, nullptr, 0, c_dev, (hipStream_t)stream));
+  return ABS_OK;
+}
+
+int absorber_eval_obj(absorber_t* H, const double* x_dev, double* f_host, double* grad_dev, void* stream) {
+  if (!H || !x_dev) {
+    set_error("absorber_eval_obj: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = H->h;
+  hipStream_t st = (hipStream_t)stream;
+  if (f_host) {
+    HIP_TRY(hipMemcpyAsync(f_host, x_dev + h.nx - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  if (grad_dev) {
+    HIP_TRY(hipMemsetAsync(grad_dev, 0, sizeof(double) * (h.nx - 1), st));
+    const double one = 1.0;
+    HIP_TRY(hipMemcpyAsync(grad_dev + h.nx - 1, &one, sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return ABS_OK;
+}
+
+int absorber_jac_structure(const absorber_t* H, int64_t* rows, int64_t* cols) {
+  if (!H || !rows || !cols) {
+    set_error("absorber_jac_structure: bad argument");
+    return ABS_ERR_ARG;
+  }
+  const Handle& h = H->h;
+  long long k = 0;
+  const long long dcol = h.nx - 1;
+  for (int w = 0; w < h.S; ++w)
+    for (int n = 0; n < h.N; ++n) {
+      const long long t = (long long)w * h.N + n;
+      for (auto& e : h.jac_own) {
+        rows[k] = t * NR + e.row;
+        cols[k] = e.blk == BLK_D ? dcol : t * NV + e.col;
+        ++k;
+      }
+      if (n < h.N - 1)
+        for (auto& e : h.jac_up) {
+          rows[k] = t * NR + e.row;
+          cols[k] = (t + 1) * NV + e.col;
+          ++k;
+        }
+      if (n > 0)
+        for (auto& e : h.jac_down) {
+          rows[k] = t * NR + e.row;
+          cols[k] = (t - 1) * NV + e.col;
+          ++k;
+        }
+    }
+  return ABS_OK;
+}
+
+int absorber_eval_jac(absorber_t* H, const double* x_dev, double* vals_dev, void* stream) {
+  if (!H || !x_dev || !vals_dev) {
+    set_error("absorber_eval_jac: bad argument");
+    return ABS_ERR_ARG;
+  }
+  HIP_TRY(launch_jac_coo(H->h, x_dev, vals_dev, (hipStream_t)stream));
+  return ABS_OK;
+}
+
+int absorber_hess_structure(const absorber_t* H, int64_t* rows, int64_t* cols) {
+  if (!H || !rows || !cols) {
+    set_error("absorber_hess_structure: bad argument");
+    return ABS_ERR_ARG;
+  }
+  const Handle& h = H->h;
+  long long k = 0;
+  for (long long t = 0; t < (long long)h.N * h.S; ++t)
+    for (int e = 0; e < NH; ++e) {
+      rows[k] = t * NV + h.hpos[e].r;
+      cols[k] = t * NV + h.hpos[e].c;
+      ++k;
+    }
+  rows[k] = cols[k] = h.nx - 1;
+  return ABS_OK;
+}
+
+int absorber_eval_hess(absorber_t* H, const double* x_dev, const double* lambda_dev, double obj_factor,
+                       double* vals_dev, void* stream) {
+  (void)obj_factor;  // the objective d is linear
+  if (!H || !x_dev || !lambda_dev || !vals_dev) {
+    set_error("absorber_eval_hess: bad argument");
+    return ABS_ERR_ARG;
+  }
+  HIP_TRY(launch_hess_coo(H->h, x_dev, lambda_dev, vals_dev, (hipStream_t)stream));
+  return ABS_OK;
+}
+
+int absorber_kkt_factor(absorber_t* H, const double* x_dev, const double* lambda_dev, const double* sigma_x_dev,
+                        const double* sigma_s_dev, double delta_w, double delta_c, int64_t* inertia_host,
+                        void* stream) {
+  if (!H || !x_dev || !lambda_dev || !sigma_x_dev || !sigma_s_dev || !(delta_w >= 0) || !(delta_c >= 0)) {
+    set_error("absorber_kkt_factor: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = H->h;
+  hipStream_t st = (hipStream_t)stream;
+  // the record is evaluated at x in original units with the handle's scaling
+  HIP_TRY(launch_eval(h, x_dev, 0, lambda_dev, 1, h.kres, st));
+  HIP_TRY(hipMemcpyAsync(h.diagx, sigma_x_dev, sizeof(double) * h.nx, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h.diags, sigma_s_dev, sizeof(double) * (h.nx - 1) / NV, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(launch_factor(h, h.diagx, h.diags, delta_w, delta_c, nullptr, st));
+  HIP_TRY(launch_schur(h, h.diagx + (h.nx - 1), delta_w, nullptr, 0, nullptr, st));
+  HIP_TRY(hipMemcpyAsync(h.scal_h, h.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (inertia_host) {
+    inertia_host[0] = h.scal_h->npos;
+    inertia_host[1] = h.scal_h->nneg;
+    inertia_host[2] = h.scal_h->nzero;
+  }
+  return ABS_OK;
+}
+
+}  // extern "C"

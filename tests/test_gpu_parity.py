@@ -1,0 +1,185 @@
+"""GPU path against the CPU oracle, through the C ABI.
+
+Evaluation: hand-derived residuals and derivatives (HIP) against the oracle's
+residuals and autograd derivatives.  Linear algebra: the GPU block LDL^T with
+the Schur complement on d against the oracle's dense Bunch-Kaufman per
+scenario.  Tolerances: see each test.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from absorber_inputs import CONFIGS, feed_table
+from oracle import model as M
+from oracle.kkt import BorderedKKT, scenario_kkt
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _random_states(S, N, seed):
+    rng = np.random.default_rng(seed)
+    Z = np.empty((S, N, M.NV))
+    Z[..., 0:9] = rng.uniform(0.01, 0.3, (S, N, 9))
+    Z[..., 9:13] = rng.uniform(0.05, 0.5, (S, N, 4))
+    Z[..., M.IL] = rng.uniform(30, 60, (S, N))
+    Z[..., M.IV] = rng.uniform(5, 15, (S, N))
+    Z[..., M.IT] = rng.uniform(300, 350, (S, N))
+    Z[..., M.IE:] = rng.uniform(-1, 1, (S, N, 5))
+    return Z, float(rng.uniform(0.3, 2.0))
+
+
+@pytest.fixture(scope="module")
+def small(params):
+    from paper_2607_15420_amd import Absorber
+    N, S = 4, 3
+    feeds = CONFIGS["C1"].feeds(params)[:S]
+    h = Absorber(params, N, feeds)
+    Z, d = _random_states(S, N, 11)
+    x = np.concatenate([Z.reshape(-1), [d]])
+    yield h, params, feeds, N, S, Z, d, x
+    h.close()
+
+
+def test_eval_cons(small):
+    h, params, feeds, N, S, Z, d, x = small
+    P = M.OracleParams(params)
+    c = torch.empty(h.nc, dtype=torch.float64, device=DEV)
+    h.eval_cons(_t(x), c)
+    torch.cuda.synchronize()
+    cg = c.cpu().numpy().reshape(S, N, M.NR)
+    co = M.constraints(Z, d, feeds, P)
+    # magnitude of the terms of each row: |J| |x| + |c|
+    for w in range(S):
+        J = M.jacobian(Z[w], d, feeds[w], P)
+        mag = np.abs(J) @ np.abs(np.r_[Z[w].reshape(-1), d]) + np.abs(co[w].reshape(-1))
+        err = np.abs(cg[w].reshape(-1) - co[w].reshape(-1))
+        assert (err <= 1e-13 * mag + 1e-300).all(), err.max()
+
+
+def test_eval_jac(small):
+    h, params, feeds, N, S, Z, d, x = small
+    P = M.OracleParams(params)
+    rows, cols = h.jac_structure()
+    vals = torch.empty(rows.size, dtype=torch.float64, device=DEV)
+    h.eval_jac(_t(x), vals)
+    torch.cuda.synchronize()
+    v = vals.cpu().numpy()
+    nzs = N * M.NV
+    for w in range(S):
+        Jo = M.jacobian(Z[w], d, feeds[w], P)  # (22N, 21N+1)
+        Jg = np.zeros_like(Jo)
+        sel = (rows >= w * N * M.NR) & (rows < (w + 1) * N * M.NR)
+        r = rows[sel] - w * N * M.NR
+        cc = cols[sel]
+        cl = np.where(cc == h.nx - 1, nzs, cc - w * nzs)
+        assert ((cl >= 0) & (cl <= nzs)).all()
+        np.add.at(Jg, (r, cl), v[sel])
+        scale = np.abs(Jo).max(axis=1, keepdims=True)
+        assert np.abs(Jg - Jo).max() <= 1e-13 * scale.max()
+        assert (np.abs(Jg - Jo) <= 1e-13 * scale).all()
+        # nothing of the oracle's Jacobian lies outside the structure
+        mask = np.zeros_like(Jo, dtype=bool)
+        mask[r, cl] = True
+        assert np.all(Jo[~mask] == 0.0)
+
+
+def test_eval_hess(small):
+    h, params, feeds, N, S, Z, d, x = small
+    P = M.OracleParams(params)
+    lam = np.random.default_rng(5).normal(size=(S, N, M.NR))
+    rows, cols = h.hess_structure()
+    vals = torch.empty(rows.size, dtype=torch.float64, device=DEV)
+    h.eval_hess(_t(x), _t(lam.reshape(-1)), vals)
+    torch.cuda.synchronize()
+    v = vals.cpu().numpy()
+    nzs = N * M.NV
+    hdd = 0.0
+    for w in range(S):
+        Ho = M.lagrangian_hessian(Z[w], d, feeds[w], lam[w], P)
+        hdd += Ho[-1, -1]
+        Hg = np.zeros((nzs, nzs))
+        sel = (rows < h.nx - 1) & (rows >= w * nzs) & (rows < (w + 1) * nzs)
+        r, cc = rows[sel] - w * nzs, cols[sel] - w * nzs
+        assert (r >= cc).all()
+        Hg[r, cc] = v[sel]
+        Hg = Hg + np.tril(Hg, -1).T
+        scale = np.abs(Ho[:-1, :-1]).max()
+        assert np.abs(Hg - Ho[:-1, :-1]).max() <= 1e-13 * scale
+    assert v[-1] == pytest.approx(hdd, rel=1e-13)
+
+
+def _oracle_bordered(params, feeds, N, Z, d, lam_s, cs, D, sig_x, sig_s, dw, dc):
+    """The oracle's bordered KKT with the same scaling the GPU handle applies."""
+    P = M.OracleParams(params)
+    S = feeds.shape[0]
+    blocks, borders, kdd = [], [], 0.0
+    for w in range(S):
+        bs = np.r_[np.tile(D[:M.NV], N), D[M.NV]]
+        J = M.jacobian(Z[w], d, feeds[w], P) * cs[w].reshape(-1)[:, None] * bs[None, :]
+        H = M.lagrangian_hessian(Z[w], d, feeds[w], lam_s[w] * cs[w], P) * bs[:, None] * bs[None, :]
+        K, b, hdd = scenario_kkt(J, H, sig_x[w * N * M.NV:(w + 1) * N * M.NV], sig_s[w], dw, dc, N)
+        blocks.append(K)
+        borders.append(b)
+        kdd += hdd
+    kdd += sig_x[-1] + dw
+    return BorderedKKT(blocks, borders, kdd)
+
+
+def _to_oracle_order(v, S, N):
+    """KKT vector [S][N][43] + d  ->  per-scenario [x (21N), yc (21N), yd (N)] lists and d."""
+    a = v[:-1].reshape(S, N, M.NK if hasattr(M, "NK") else 43)
+    out = []
+    for w in range(S):
+        out.append(np.concatenate([a[w, :, :21].reshape(-1), a[w, :, 21:42].reshape(-1), a[w, :, 42]]))
+    return out, v[-1]
+
+
+@pytest.mark.parametrize("dw,dc", [(0.0, 0.0), (1e-3, 1e-8)])
+def test_kkt_factor_and_solve(small, dw, dc):
+    h, params, feeds, N, S, Z, d, x = small
+    rng = np.random.default_rng(17)
+    P = M.OracleParams(params)
+    # scaling like the interior-point method: variables by magnitude, rows by gradient
+    D = np.r_[np.abs(Z[0, 0]) + 0.1, 1.0]
+    cs = np.empty((S, N, M.NR))
+    for w in range(S):
+        bs = np.r_[np.tile(D[:M.NV], N), D[M.NV]]
+        J = M.jacobian(Z[w], d, feeds[w], P) * bs[None, :]
+        cs[w] = np.minimum(1.0, 100.0 / np.abs(J).max(axis=1)).reshape(N, M.NR)
+    lam_s = rng.normal(scale=0.1, size=(S, N, M.NR))
+    sig_x = rng.uniform(0.1, 10.0, S * N * M.NV + 1)
+    sig_s = rng.uniform(0.5, 5.0, (S, N))
+    h.set_scaling(D, _t(cs.reshape(-1)))
+    inert = h.kkt_factor(_t(x), _t(lam_s.reshape(-1)), _t(sig_x), _t(sig_s.reshape(-1)), dw, dc)
+    F = _oracle_bordered(params, feeds, N, Z, d, lam_s, cs, D, sig_x, sig_s, dw, dc)
+    assert inert == F.inertia
+    rhs = rng.normal(size=h.nkkt)
+    sol = torch.empty(h.nkkt, dtype=torch.float64, device=DEV)
+    rel = h.kkt_solve(_t(rhs), sol)
+    assert rel <= 1e-10
+    rs, rd = _to_oracle_order(rhs, S, N)
+    xs, xd = F.solve(rs, rd)
+    gs, gd = _to_oracle_order(sol.cpu().numpy(), S, N)
+    ref = max(np.abs(np.concatenate(xs)).max(), abs(xd))
+    assert abs(gd - xd) <= 1e-9 * ref
+    for a, b in zip(gs, xs):
+        assert np.abs(a - b).max() <= 1e-9 * ref
+    h.set_scaling(None, None)
+
+
+def test_kkt_solve_before_factor_is_an_error(params):
+    from paper_2607_15420_amd import Absorber, AbsorberError
+    h = Absorber(params, 2, CONFIGS["C1"].feeds(params)[:1])
+    rhs = torch.zeros(h.nkkt, dtype=torch.float64, device=DEV)
+    with pytest.raises(AbsorberError):
+        h.kkt_solve(rhs, torch.empty_like(rhs))
+    h.close()
