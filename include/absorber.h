@@ -180,6 +180,20 @@ int absorber_ipm_solve(absorber_t* h, const absorber_ipm_options* opts, const do
                        const double* lambda0_dev, double* x_out_dev, double* lambda_out_dev,
                        absorber_ipm_result* result);
 
+/* Per-kernel-class timing with HIP events recorded on the stream each kernel is
+ * launched on.  Classes: 0 block LDL^T factorisation (with its fused solve),
+ * 1 solve with stored factors, 2 stage evaluation, 3 bordered residual.
+ * absorber_profile_enable(h, mask) resets the counters and times the classes
+ * whose bit is set in mask (bit k = class k; it adds a stream synchronisation
+ * after each timed launch); mask 0 stops timing. */
+typedef struct {
+  double ms[4];        /* summed kernel time per class */
+  int64_t calls[4];    /* launches per class */
+  int64_t bytes_factor_slots; /* bytes of pivot columns one factorisation writes */
+} absorber_profile;
+int absorber_profile_enable(absorber_t* h, int32_t mask);
+int absorber_profile_get(const absorber_t* h, absorber_profile* out);
+
 const char* absorber_last_error(void);
 
 #ifdef __cplusplus

@@ -76,6 +76,12 @@ class IpmResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 4), ("calls", ctypes.c_int64 * 4), ("bytes_factor_slots", ctypes.c_int64)]
+
+
+PROFILE_CLASSES = ("factor", "solve", "eval", "residual")
+
 _lib = None
 
 
@@ -105,6 +111,8 @@ def lib():
             "absorber_ipm_default_options": (None, [ctypes.POINTER(IpmOptions)]),
             "absorber_ipm_solve": (ctypes.c_int, [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp,
                                                   ctypes.POINTER(IpmResult)]),
+            "absorber_profile_enable": (ctypes.c_int, [vp, i32]),
+            "absorber_profile_get": (ctypes.c_int, [vp, ctypes.POINTER(Profile)]),
             "absorber_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -243,6 +251,17 @@ class Absorber:
     def eval_hess(self, x, lam, vals, obj_factor=1.0, stream=None):
         _check(lib().absorber_eval_hess(self.h, _ptr(x), _ptr(lam), float(obj_factor), _ptr(vals),
                                         _stream(stream)))
+
+    def profile_enable(self, on=True, mask=0xF):
+        """Time the kernel classes in mask (bit 0 factor, 1 solve, 2 eval, 3 residual)."""
+        _check(lib().absorber_profile_enable(self.h, int(mask) if on else 0))
+
+    def profile(self) -> dict:
+        p = Profile()
+        _check(lib().absorber_profile_get(self.h, ctypes.byref(p)))
+        out = {c: {"ms": p.ms[i], "calls": p.calls[i]} for i, c in enumerate(PROFILE_CLASSES)}
+        out["bytes_factor_slots"] = p.bytes_factor_slots
+        return out
 
     def kkt_factor(self, x, lam, sigma_x, sigma_s, delta_w=0.0, delta_c=0.0, stream=None):
         inert = np.zeros(3, np.int64)

@@ -143,7 +143,25 @@ int initial_point(Handle& h, double* x_dev, hipStream_t st) {
   return ABS_OK;
 }
 
+void prof_begin(Handle& h, hipStream_t st) {
+  if (h.prof) (void)hipEventRecord(h.ev0, st);
+}
+
+void prof_end(Handle& h, int cls, hipStream_t st) {
+  if (!(h.prof & (1 << cls))) return;
+  (void)hipEventRecord(h.ev1, st);
+  if (hipEventSynchronize(h.ev1) == hipSuccess) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h.ev0, h.ev1) == hipSuccess) {
+      h.prof_ms[cls] += ms;
+      h.prof_calls[cls] += 1;
+    }
+  }
+}
+
 static void free_handle(Handle& h) {
+  if (h.ev0) (void)hipEventDestroy(h.ev0);
+  if (h.ev1) (void)hipEventDestroy(h.ev1);
   void* ptrs[] = {h.feeds, h.gather, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.redbuf};
   for (void* p : ptrs)
@@ -309,6 +327,38 @@ int absorber_initial_point(absorber_t* H, double* x_dev, void* stream) {
     return ABS_ERR_ARG;
   }
   return initial_point(H->h, x_dev, (hipStream_t)stream);
+}
+
+int absorber_profile_enable(absorber_t* H, int32_t on) {
+  if (!H) {
+    set_error("absorber_profile_enable: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = H->h;
+  if (on && !h.ev0) {
+    HIP_TRY(hipEventCreate(&h.ev0));
+    HIP_TRY(hipEventCreate(&h.ev1));
+  }
+  for (int k = 0; k < 4; ++k) {
+    h.prof_ms[k] = 0.0;
+    h.prof_calls[k] = 0;
+  }
+  h.prof = on;
+  return ABS_OK;
+}
+
+int absorber_profile_get(const absorber_t* H, absorber_profile* out) {
+  if (!H || !out) {
+    set_error("absorber_profile_get: bad argument");
+    return ABS_ERR_ARG;
+  }
+  const Handle& h = H->h;
+  for (int k = 0; k < 4; ++k) {
+    out->ms[k] = h.prof_ms[k];
+    out->calls[k] = h.prof_calls[k];
+  }
+  out->bytes_factor_slots = (int64_t)h.N * h.S * NK * SLOT * (int64_t)sizeof(double);
+  return ABS_OK;
 }
 
 int absorber_set_scaling(absorber_t* H, const double* var_scale_host, const double* row_scale_dev) {

@@ -97,9 +97,17 @@ struct Handle {
   double last_diag_d = 0;
   double x0[NV + 1];                         // cold-start stage vector and diameter
   long long n_factor = 0, n_solve = 0;       // launch counters
+  // optional per-class kernel timing (HIP events on the launch stream)
+  int prof = 0;  // bit mask of the profiled kernel classes
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double prof_ms[4] = {0, 0, 0, 0};
+  long long prof_calls[4] = {0, 0, 0, 0};
 };
 
 void set_error(const std::string& msg);
+// bracket a launch with profiling events (no-ops unless profiling is enabled)
+void prof_begin(Handle& h, hipStream_t st);
+void prof_end(Handle& h, int cls, hipStream_t st);
 int initial_point(Handle& h, double* x_dev, hipStream_t st);
 
 #define HIP_TRY(expr)                                                                   \

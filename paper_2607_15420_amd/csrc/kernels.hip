@@ -787,8 +787,10 @@ hipError_t launch_eval(Handle& h, const double* x, int scaled, const double* y, 
 hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling& sc, const double* cs,
                            const double* y, int full, double* c_out, hipStream_t st) {
   const long long nst = (long long)h.N * h.S;
+  prof_begin(h, st);
   hipLaunchKernelGGL(k_eval, dim3(grid_for(nst, 128)), dim3(128), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp, h.N,
                      h.S, full, c_out, h.rec);
+  prof_end(h, 2, st);
   return hipGetLastError();
 }
 
@@ -815,12 +817,14 @@ hipError_t launch_hess_coo(Handle& h, const double* x, const double* lam, double
 
 hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, double dw, double dc,
                          const double* rhs, hipStream_t st) {
+  prof_begin(h, st);
   if (rhs)
     hipLaunchKernelGGL(k_factor<1>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, dw, dc, h.N,
                        h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
   else
     hipLaunchKernelGGL(k_factor<0>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, dw, dc, h.N,
                        h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
+  prof_end(h, 0, st);
   h.fdw = dw;
   h.fdc = dc;
   h.factored = true;
@@ -829,8 +833,10 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, do
 }
 
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
+  prof_begin(h, st);
   hipLaunchKernelGGL(k_solve, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.N, h.S, h.jac_d_index, h.solr,
                      h.part);
+  prof_end(h, 1, st);
   ++h.n_solve;
   return hipGetLastError();
 }
@@ -852,8 +858,10 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   double* dpart = h.kden;
   double* dabs = h.kden + nst;
   double* omg = h.kden + 2 * nst;
+  prof_begin(h, st);
   hipLaunchKernelGGL(k_residual, dim3(grid_for(nst, 64)), dim3(64), 0, st, h.rec, h.jtab, diagx, diags, dw, dc, sol,
                      rhs, h.N, h.S, h.jac_d_index, res, dpart, dabs, omg);
+  prof_end(h, 3, st);
   hipLaunchKernelGGL(k_residual_d, dim3(1), dim3(256), 0, st, dpart, dabs, nst, h.scal, sol, rhs, nkk, res,
                      omega_out + 1);
   hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, st, omg, nst, omega_out);
