@@ -32,6 +32,7 @@ import scipy.linalg.lapack as lapack
 from .model import NR, NV
 
 ZERO_PIVOT = 1e-20  # |eigenvalue| of an equilibrated pivot block counted as zero
+OMEGA_STOP = 1e-13  # refinement stops at this componentwise backward error (or when it stalls)
 
 
 def scenario_kkt(J: np.ndarray, H: np.ndarray, sig_x: np.ndarray, sig_s: np.ndarray,
@@ -154,7 +155,7 @@ class BorderedKKT:
     def solve(self, rs, rd: float, refine: int = 10):
         """Solve with per-scenario right-hand sides rs (list) and the d entry rd,
         refining on the whole bordered system until the componentwise backward
-        error stops improving."""
+        error is at most OMEGA_STOP or stops improving."""
         xs, xd = self._solve_once(rs, rd)
         best = None
         for _ in range(refine):
@@ -163,7 +164,7 @@ class BorderedKKT:
                 xs, xd = best[1], best[2]
                 break
             best = (omega, xs, xd)
-            if omega <= 1e-16:
+            if omega <= OMEGA_STOP:
                 break
             cs, cd = self._solve_once(res, resd)
             xs, xd = [x + c for x, c in zip(xs, cs)], xd + cd

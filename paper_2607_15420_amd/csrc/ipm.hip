@@ -497,7 +497,7 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
   double rn = 0.0;
   int rc = absmax(h, rhs, h.nkkt, &rn, st);
   if (rc) return rc;
-  double* om_d = h.kden + 3 * ((long long)h.N * h.S);  // two doubles of scratch after the partials
+  double* om_d = h.kden + 3 * ((long long)h.N * h.S);  // two doubles after the residual block partials
   double best_om = INFINITY, best_rel = INFINITY;
   bool have_best = false;
   for (int it = 0; it <= 10; ++it) {
@@ -515,7 +515,7 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     }
     best_om = omega;
     best_rel = relr;
-    if (omega <= 1e-16 || it == 10) break;
+    if (omega <= 1e-13 || it == 10) break;  // same stop rule as the reference solve
     HIP_TRY(hipMemcpyAsync(h.kcor, sol, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
     have_best = true;
     HIP_TRY(launch_solve(h, h.kres, st));

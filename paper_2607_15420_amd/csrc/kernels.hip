@@ -225,29 +225,246 @@ __global__ void k_hess_dd(const double* __restrict__ lam, ModelParams p, long lo
 // coupling unknowns of stage n+1, 59 the right-hand side r, 60 the border b
 // (both carried as symmetric extra rows and columns).  Eliminating the 43 own
 // pivots leaves in rows/cols 43-60 the contribution to stage n+1's block and
-// right-hand sides.
+// right-hand sides.  The pivot loop uses no LDS: column entries reach every
+// lane through v_readlane (uniform operands), the pivot row is selected by a
+// uniform switch, and the diagonal is kept up to date per lane.
 struct WaveLDS {
   double src[NSRC];
-  double cb0[WAVE];
-  double cb1[WAVE];
   double xr[WAVE];
   double xb[WAVE];
 };
 
-__device__ __forceinline__ void bcast_col(const double (&v)[FR], int k, double* buf) {
-  if (lane_id() == k) {
-#pragma unroll
-    for (int i = 0; i < FR; ++i) buf[i] = v[i];
-  }
-  __syncthreads();
+// value of lane l (l uniform) broadcast to the wave
+__device__ __forceinline__ double rdl(double v, int l) {
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ bool row_active(uint64_t act, int i, int p0, int p1) {
-  return i < NK ? ((((act >> i) & 1ull) != 0ull) && i != p0 && i != p1) : true;
+// register i of this lane for a uniform i < NK
+__device__ __forceinline__ double rowsel(const double (&v)[FR], int p) {
+  switch (p) {
+#define ABS_CASE(i) \
+  case i:           \
+    return v[i];
+    ABS_CASE(0) ABS_CASE(1) ABS_CASE(2) ABS_CASE(3) ABS_CASE(4) ABS_CASE(5) ABS_CASE(6) ABS_CASE(7)
+    ABS_CASE(8) ABS_CASE(9) ABS_CASE(10) ABS_CASE(11) ABS_CASE(12) ABS_CASE(13) ABS_CASE(14) ABS_CASE(15)
+    ABS_CASE(16) ABS_CASE(17) ABS_CASE(18) ABS_CASE(19) ABS_CASE(20) ABS_CASE(21) ABS_CASE(22) ABS_CASE(23)
+    ABS_CASE(24) ABS_CASE(25) ABS_CASE(26) ABS_CASE(27) ABS_CASE(28) ABS_CASE(29) ABS_CASE(30) ABS_CASE(31)
+    ABS_CASE(32) ABS_CASE(33) ABS_CASE(34) ABS_CASE(35) ABS_CASE(36) ABS_CASE(37) ABS_CASE(38) ABS_CASE(39)
+    ABS_CASE(40) ABS_CASE(41) ABS_CASE(42)
+#undef ABS_CASE
+    default:
+      return 0.0;
+  }
+}
+
+// Wave maximum of a non-negative double with its lane: the lane is packed into
+// the 6 lowest mantissa bits (as 63 - lane, so ties go to the lowest lane) and
+// the 64-bit patterns, ordered like the values, are max-reduced with DPP row
+// shifts and row broadcasts; lane 63 ends with the maximum.
+#define ABS_DPP_MAX_U64(v, ctrl, rm, bm)                                                \
+  do {                                                                                 \
+    const unsigned lo_ = (unsigned)(v), hi_ = (unsigned)((v) >> 32);                   \
+    const unsigned olo_ = __builtin_amdgcn_update_dpp(0u, lo_, ctrl, rm, bm, false);   \
+    const unsigned ohi_ = __builtin_amdgcn_update_dpp(0u, hi_, ctrl, rm, bm, false);   \
+    const unsigned long long o_ = ((unsigned long long)ohi_ << 32) | olo_;              \
+    (v) = o_ > (v) ? o_ : (v);                                                          \
+  } while (0)
+
+__device__ __forceinline__ double wave_max_lane(double a, int lane, int& idx) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(a);
+  b = (b & ~63ull) | (unsigned long long)(63 - lane);
+  ABS_DPP_MAX_U64(b, 0x111, 0xf, 0xf);  // row_shr:1
+  ABS_DPP_MAX_U64(b, 0x112, 0xf, 0xf);  // row_shr:2
+  ABS_DPP_MAX_U64(b, 0x114, 0xf, 0xf);  // row_shr:4
+  ABS_DPP_MAX_U64(b, 0x118, 0xf, 0xf);  // row_shr:8
+  ABS_DPP_MAX_U64(b, 0x142, 0xa, 0xf);  // row_bcast:15
+  ABS_DPP_MAX_U64(b, 0x143, 0xc, 0xf);  // row_bcast:31
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), 63);
+  const unsigned long long m = ((unsigned long long)hi << 32) | lo;
+  idx = 63 - (int)(m & 63ull);
+  return __longlong_as_double((long long)(m & ~63ull));
+}
+
+// Eliminate the 43 own pivots of one stage (Bunch-Kaufman inside the stage);
+// stores one pivot column per slot (rows still active, code, d or 2x2 block,
+// 1/d).  The matrix is symmetric, so the pivot candidates' columns are read
+// as rows (register p of every lane) with a uniform switch.
+__device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restrict__ sb, long long& npos,
+                                                long long& nneg, long long& nzero) {
+  int lane = lane_id();
+  __asm__ volatile("" : "+v"(lane));
+  const double alpha = (1.0 + sqrt(17.0)) * 0.125;
+  uint64_t act = (1ull << NK) - 1ull;
+  int slot = 0;
+  while (act) {
+    const int k = __builtin_ctzll(act);
+    const bool own_act = lane < NK && ((act >> lane) & 1ull);
+    const double rowk = rowsel(v, k);  // F[k][lane] = F[lane][k]
+    const double akk = fabs(rdl(rowk, k));
+    int r;
+    const double lam = wave_max_lane(own_act && lane != k ? fabs(rowk) : 0.0, lane, r);
+    int ptype = 1;  // 1: 1x1 at k, 2: 1x1 at r, 3: 2x2 (k, r)
+    double rowr = 0.0;
+    if (!(akk >= alpha * lam) && lam > 0.0) {
+      rowr = rowsel(v, r);
+      int r2;
+      const double sig = wave_max_lane(own_act && lane != r ? fabs(rowr) : 0.0, lane, r2);
+      if (akk * sig >= alpha * lam * lam) ptype = 1;
+      else if (fabs(rdl(rowr, r)) >= alpha * sig) ptype = 2;
+      else ptype = 3;
+    }
+    const bool in_col = lane < FR && (lane >= NK || ((act >> lane) & 1ull));
+    const bool two = ptype == 3;
+    const int p0 = ptype == 2 ? r : k;
+    const int p1 = two ? r : p0;
+    const double rk = ptype == 2 ? rowr : rowk;  // F[p0][lane]
+    const double rr = two ? rowr : 0.0;          // F[p1][lane]
+    const bool ca = in_col && lane != p0 && lane != p1;
+    double t1 = 0.0, t2 = 0.0;
+    bool zero = false;
+    if (!two) {
+      const double d = rdl(rk, p0);
+      const double dinv = d == 0.0 ? 0.0 : 1.0 / d;
+      double sv = ca ? rk : 0.0;
+      if (lane == FR) sv = (double)(p0 + 64 * (d == 0.0 ? 0 : 1));
+      else if (lane == FR + 1) sv = d;
+      else if (lane > FR + 1) sv = dinv;
+      sb[slot * SLOT + lane] = sv;
+      slot += 1;
+      if (d == 0.0) {
+        ++nzero;
+        zero = true;
+      } else {
+        if (d > 0.0) ++npos;
+        else ++nneg;
+        t1 = ca ? rk * dinv : 0.0;
+      }
+    } else {
+      const double e11 = rdl(rk, p0), e12 = rdl(rk, p1), e22 = rdl(rr, p1);
+      const double det = e11 * e22 - e12 * e12;
+      double s0 = ca ? rk : 0.0, s1 = ca ? rr : 0.0;
+      if (lane == FR) {
+        s0 = (double)(p0 + 64 * 2);
+        s1 = (double)(p1 + 64 * 3);
+      } else if (lane == FR + 1) {
+        s0 = e11;
+        s1 = e22;
+      } else if (lane == FR + 2) {
+        s0 = e12;
+        s1 = e12;
+      }
+      sb[slot * SLOT + lane] = s0;
+      sb[(slot + 1) * SLOT + lane] = s1;
+      slot += 2;
+      if (det < 0.0) {
+        ++npos;
+        ++nneg;
+      } else if (det > 0.0) {
+        if (e11 + e22 > 0.0) npos += 2;
+        else nneg += 2;
+      } else {
+        nzero += 2;
+        zero = true;
+      }
+      if (!zero) {
+        const double idet = 1.0 / det;
+        const double i11 = e22 * idet, i12 = -e12 * idet, i22 = e11 * idet;
+        t1 = ca ? i11 * rk + i12 * rr : 0.0;
+        t2 = ca ? i12 * rk + i22 * rr : 0.0;
+      }
+    }
+    act &= ~((1ull << p0) | (1ull << p1));
+    if (zero) continue;
+    // rows already eliminated are updated too: they are never read again
+#pragma unroll
+    for (int i = 0; i < FR; ++i) {
+      double x = fma(-rdl(rk, i), t1, v[i]);
+      if (two) x = fma(-rdl(rr, i), t2, x);
+      v[i] = x;
+      if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Backward sweep of one stage for two right-hand sides.  The stage's pivot
+// columns are gathered into registers in pivot order (lane s holds slot s;
+// reg[q] = its entry at the row eliminated q-th), so that each step is a
+// static-register update.  zr/zb enter as y (forward values by slot) and the
+// solutions of the stage above (LDS, by stage-local index; read at the 16
+// coupling indices) are applied first.
+// On return lane s holds the solution of pivot s in xr_s/xb_s and p_s its index.
+__device__ __forceinline__ void backward_stage(const double* __restrict__ sb, double zr, double zb,
+                                               const double* xcr, const double* xcb, bool two,
+                                               double& xr_s, double& xb_s, int& p_s) {
+  int lane = lane_id();
+  __asm__ volatile("" : "+v"(lane));
+  const int ls = lane < NK ? lane : 0;
+  const double code_l = sb[ls * SLOT + FR];
+  const double a_l = sb[ls * SLOT + FR + 1];   // d, or e11 / e22 of a 2x2 pair
+  const double b_l = sb[ls * SLOT + FR + 2];   // 1/d, or e12
+  p_s = ((int)code_l) & 63;
+  double reg[NK];
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    const int pq = ((int)rdl(code_l, q)) & 63;
+    reg[q] = sb[ls * SLOT + pq];
+    if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    const double c = sb[ls * SLOT + NK + a];
+    zr = fma(-c, xcr[coupling_index(a)], zr);
+    if (two) zb = fma(-c, xcb[coupling_index(a)], zb);
+  }
+  xr_s = 0.0;
+  xb_s = 0.0;
+  bool skip = false;
+#pragma unroll
+  for (int s = NK - 1; s >= 0; --s) {
+    if (skip) {
+      skip = false;
+      continue;
+    }
+    const int code = (int)rdl(code_l, s);
+    const int type = code >> 6;
+    if (s > 0 && type == 3) {
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int s0 = s > 0 ? s - 1 : 0;
+      const double e11 = rdl(a_l, s0), e12 = rdl(b_l, s0), e22 = rdl(a_l, s);
+      const double idet = 1.0 / (e11 * e22 - e12 * e12);
+      const double zk = rdl(zr, s0), zq = rdl(zr, s);
+      const double xk = (e22 * zk - e12 * zq) * idet, xq = (e11 * zq - e12 * zk) * idet;
+      zr = fma(-reg[s0], xk, fma(-reg[s], xq, zr));
+      if (lane == s0) xr_s = xk;
+      if (lane == s) xr_s = xq;
+      if (two) {
+        const double wk = rdl(zb, s0), wq = rdl(zb, s);
+        const double yk = (e22 * wk - e12 * wq) * idet, yq = (e11 * wq - e12 * wk) * idet;
+        zb = fma(-reg[s0], yk, fma(-reg[s], yq, zb));
+        if (lane == s0) xb_s = yk;
+        if (lane == s) xb_s = yq;
+      }
+      skip = true;
+    } else {
+      const double dinv = rdl(b_l, s);
+      const double x = type ? rdl(zr, s) * dinv : 0.0;
+      zr = fma(-reg[s], x, zr);
+      if (lane == s) xr_s = x;
+      if (two) {
+        const double y = type ? rdl(zb, s) * dinv : 0.0;
+        zb = fma(-reg[s], y, zb);
+        if (lane == s) xb_s = y;
+      }
+    }
+  }
 }
 
 template <int WITH_RHS>
-__global__ __launch_bounds__(WAVE) void k_factor(const double* __restrict__ rec, const int* __restrict__ gather,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void k_factor(const double* __restrict__ rec, const int* __restrict__ gather,
                                                  const double* __restrict__ rhs, const double* __restrict__ diagx,
                                                  const double* __restrict__ diags, double dw, double dc, int N, int S,
                                                  int jd, double* __restrict__ slots, double* __restrict__ solr,
@@ -257,14 +474,13 @@ __global__ __launch_bounds__(WAVE) void k_factor(const double* __restrict__ rec,
   const int w = blockIdx.x;
   if (w >= S) return;
   const int lane = lane_id();
-  const double alpha = (1.0 + sqrt(17.0)) * 0.125;
   for (int i = lane; i < NC * (NC + 2); i += WAVE) L.src[SRC_CTB + i] = 0.0;
   if (lane == 0) L.src[SRC_ZERO] = 0.0;
   long long npos = 0, nneg = 0, nzero = 0;
-  double v[FR];
   for (int n = 0; n < N; ++n) {
     const long long t = (long long)w * N + n;
     const double* R = rec + t * REC;
+    double v[FR];
     for (int i = lane; i < REC; i += WAVE) L.src[SRC_REC + i] = R[i];
     if (lane < NJD) L.src[SRC_DOWN1 + lane] = (n < N - 1) ? rec[(t + 1) * REC + REC_DOWN + lane] : 0.0;
     if (lane < NK) L.src[SRC_RHS + lane] = WITH_RHS ? rhs[t * NK + lane] : 0.0;
@@ -275,101 +491,17 @@ __global__ __launch_bounds__(WAVE) void k_factor(const double* __restrict__ rec,
       L.src[SRC_DHYD] = -(1.0 / (diags[t] + dw) + dc);
     }
     __syncthreads();
+    // keep the table loads inside the stage loop (hoisting them would pin ~120 registers)
+    const int* gt = gather;
+    __asm__ volatile("" : "+s"(gt));
 #pragma unroll
     for (int i = 0; i < FR; ++i) {
-      const int g = gather[i * WAVE + lane];
+      const int g = gt[i * WAVE + lane];
       v[i] = L.src[g & 1023] + L.src[(g >> 10) & 1023] + L.src[(g >> 20) & 1023];
+      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    double* sb = slots + t * NK * SLOT;
-    uint64_t act = (1ull << NK) - 1ull;
-    int slot = 0;
-    while (act) {
-      const int k = __builtin_ctzll(act);
-      bcast_col(v, k, L.cb0);
-      const double ck = lane < FR ? L.cb0[lane] : 0.0;
-      const double akk = fabs(L.cb0[k]);
-      int r;
-      const bool oa = lane < NK && ((act >> lane) & 1ull) && lane != k;
-      const double lam = wave_argmax(oa ? fabs(ck) : 0.0, r);
-      int ptype;  // 1: 1x1 at k, 2: 1x1 at r, 3: 2x2 (k, r)
-      if (akk >= alpha * lam || lam == 0.0) {
-        ptype = 1;
-      } else {
-        bcast_col(v, r, L.cb1);
-        const double cr = lane < FR ? L.cb1[lane] : 0.0;
-        int r2;
-        const bool ob = lane < NK && ((act >> lane) & 1ull) && lane != r;
-        const double sig = wave_argmax(ob ? fabs(cr) : 0.0, r2);
-        if (akk * sig >= alpha * lam * lam) ptype = 1;
-        else if (fabs(L.cb1[r]) >= alpha * sig) ptype = 2;
-        else ptype = 3;
-      }
-      if (ptype != 3) {
-        const int p = ptype == 1 ? k : r;
-        const double* buf = ptype == 1 ? L.cb0 : L.cb1;
-        const double d = buf[p];
-        const double cj = lane < FR ? buf[lane] : 0.0;
-        const bool ra = lane < FR && row_active(act, lane, p, -1);
-        // store the pivot column (rows still active, the pivot row cleared)
-        double sv;
-        if (lane < FR) sv = ra ? cj : 0.0;
-        else if (lane == FR) sv = (double)(p + 64 * (d == 0.0 ? 0 : 1));
-        else if (lane == FR + 1) sv = d;
-        else sv = 0.0;
-        sb[slot * SLOT + lane] = sv;
-        if (d == 0.0) {
-          ++nzero;
-        } else {
-          if (d > 0.0) ++npos; else ++nneg;
-          const double t1 = ra ? cj / d : 0.0;
-#pragma unroll
-          for (int i = 0; i < FR; ++i)
-            if (row_active(act, i, p, -1)) v[i] -= buf[i] * t1;
-        }
-        act &= ~(1ull << p);
-        slot += 1;
-      } else {
-        const double e11 = L.cb0[k], e12 = L.cb0[r], e22 = L.cb1[r];
-        const double det = e11 * e22 - e12 * e12;
-        const double c0 = lane < FR ? L.cb0[lane] : 0.0;
-        const double c1 = lane < FR ? L.cb1[lane] : 0.0;
-        const bool ra = lane < FR && row_active(act, lane, k, r);
-        double s0, s1;
-        if (lane < FR) {
-          s0 = ra ? c0 : 0.0;
-          s1 = ra ? c1 : 0.0;
-        } else if (lane == FR) {
-          s0 = (double)(k + 64 * 2);
-          s1 = (double)(r + 64 * 3);
-        } else if (lane == FR + 1) {
-          s0 = e11;
-          s1 = e22;
-        } else {
-          s0 = e12;
-          s1 = e12;
-        }
-        sb[slot * SLOT + lane] = s0;
-        sb[(slot + 1) * SLOT + lane] = s1;
-        if (det < 0.0) {
-          ++npos;
-          ++nneg;
-        } else if (det > 0.0) {
-          if (e11 + e22 > 0.0) npos += 2; else nneg += 2;
-        } else {
-          nzero += 2;
-        }
-        const double i11 = e22 / det, i12 = -e12 / det, i22 = e11 / det;
-        const double t1 = ra ? i11 * c0 + i12 * c1 : 0.0;
-        const double t2 = ra ? i12 * c0 + i22 * c1 : 0.0;
-#pragma unroll
-        for (int i = 0; i < FR; ++i)
-          if (row_active(act, i, k, r)) v[i] -= L.cb0[i] * t1 + L.cb1[i] * t2;
-        act &= ~((1ull << k) | (1ull << r));
-        slot += 2;
-      }
-      __syncthreads();
-    }
+    eliminate_stage(v, slots + t * NK * SLOT, npos, nneg, nzero);
     // contribution block to stage n+1 (rows/cols 43..60 of the coupling lanes)
     if (lane >= NK && lane < NK + NC) {
       const int a = lane - NK;
@@ -379,70 +511,32 @@ __global__ __launch_bounds__(WAVE) void k_factor(const double* __restrict__ rec,
     __syncthreads();
   }
   // ---------------- backward substitution over the stages, top to bottom
-  double xr = 0.0, xb = 0.0, sigb = 0.0, sigr = 0.0, wdd = 0.0;
+  L.xr[lane] = 0.0;  // solution of the stage above (none above the top stage)
+  L.xb[lane] = 0.0;
+  __syncthreads();
+  double sigb = 0.0, sigr = 0.0, wdd = 0.0;
   for (int n = N - 1; n >= 0; --n) {
     const long long t = (long long)w * N + n;
     const double* sb = slots + t * NK * SLOT;
+    const int ls = lane < NK ? lane : 0;
+    const double yr = sb[ls * SLOT + FR_R], yb = sb[ls * SLOT + FR_B];
+    double xr_s, xb_s;
+    int p_s;
+    backward_stage(sb, yr, yb, L.xr, L.xb, true, xr_s, xb_s, p_s);
+    __syncthreads();
     if (lane < NK) {
-      xr = 0.0;
-      xb = 0.0;
+      solr[t * NK + p_s] = xr_s;
+      solb[t * NK + p_s] = xb_s;
+      L.xr[p_s] = xr_s;
+      L.xb[p_s] = xb_s;
     }
-    for (int s = NK - 1; s >= 0; --s) {
-      const double c = sb[s * SLOT + lane];
-      const int code = (int)__shfl(c, FR, WAVE);
-      const int type = code >> 6, p = code & 63;
-      const double cr = lane < FR_R ? c : 0.0;
-      if (type == 1 || type == 0) {
-        const double yr = __shfl(c, FR_R, WAVE), yb = __shfl(c, FR_B, WAVE);
-        const double d = __shfl(c, FR + 1, WAVE);
-        const double pr = wave_sum(cr * xr), pb = wave_sum(cr * xb);
-        if (lane == p) {
-          xr = type ? (yr - pr) / d : 0.0;
-          xb = type ? (yb - pb) / d : 0.0;
-        }
-      } else {  // type 3: second column of a 2x2 pair, its first column is slot s-1
-        const double c0 = sb[(s - 1) * SLOT + lane];
-        const int code0 = (int)__shfl(c0, FR, WAVE);
-        const int pk = code0 & 63;
-        const double e11 = __shfl(c0, FR + 1, WAVE), e12 = __shfl(c0, FR + 2, WAVE);
-        const double e22 = __shfl(c, FR + 1, WAVE);
-        const double c0r = lane < FR_R ? c0 : 0.0;
-        const double ykr = __shfl(c0, FR_R, WAVE) - wave_sum(c0r * xr);
-        const double ykb = __shfl(c0, FR_B, WAVE) - wave_sum(c0r * xb);
-        const double yrr = __shfl(c, FR_R, WAVE) - wave_sum(cr * xr);
-        const double yrb = __shfl(c, FR_B, WAVE) - wave_sum(cr * xb);
-        const double det = e11 * e22 - e12 * e12;
-        if (lane == pk) {
-          xr = (e22 * ykr - e12 * yrr) / det;
-          xb = (e22 * ykb - e12 * yrb) / det;
-        }
-        if (lane == p) {
-          xr = (e11 * yrr - e12 * ykr) / det;
-          xb = (e11 * yrb - e12 * ykb) / det;
-        }
-        s -= 1;
-      }
-    }
-    if (lane < NK) {
-      solr[t * NK + lane] = xr;
-      solb[t * NK + lane] = xb;
-    }
+    __syncthreads();
     if (lane == NK - 1) {
       const double b = rec[t * REC + jd];
-      sigb += b * xb;
-      sigr += b * xr;
+      sigb += b * L.xb[NK - 1];
+      sigr += b * L.xr[NK - 1];
       wdd += rec[t * REC + REC_WDD];
     }
-    // coupling values for stage n-1: this stage's solution at its 16 coupling indices
-    L.xr[lane] = xr;
-    L.xb[lane] = xb;
-    __syncthreads();
-    if (lane >= NK && lane < NK + NC) {
-      const int src = coupling_index(lane - NK);
-      xr = L.xr[src];
-      xb = L.xb[src];
-    }
-    __syncthreads();
   }
   if (lane == NK - 1) {
     part[(long long)w * 4 + 0] = sigb;
@@ -462,7 +556,7 @@ __global__ __launch_bounds__(WAVE) void k_factor(const double* __restrict__ rec,
 __global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
                                                 const double* __restrict__ rhs, int N, int S, int jd,
                                                 double* __restrict__ solr, double* __restrict__ part) {
-  __shared__ double sh[2 * WAVE];
+  __shared__ double sh[WAVE];
   const int w = blockIdx.x;
   if (w >= S) return;
   const int lane = lane_id();
@@ -470,80 +564,59 @@ __global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, 
   for (int n = 0; n < N; ++n) {
     const long long t = (long long)w * N + n;
     const double* sb = slots + t * NK * SLOT;
-    // right-hand side of this stage plus the contribution of the stage below
     sh[lane] = 0.0;
     __syncthreads();
     if (lane >= NK && lane < NK + NC) sh[coupling_index(lane - NK)] = ctb;
     __syncthreads();
     double r = (lane < NK ? rhs[t * NK + lane] + sh[lane] : 0.0);
+    double ys = 0.0;  // lane s keeps the forward value of slot s
+    double c = sb[lane];
     for (int s = 0; s < NK; ++s) {
-      const double c = sb[s * SLOT + lane];
-      const int code = (int)__shfl(c, FR, WAVE);
+      const double cn = s + 1 < NK ? sb[(s + 1) * SLOT + lane] : 0.0;  // prefetch the next column
+      const int code = (int)rdl(c, FR);
       const int type = code >> 6, p = code & 63;
       const double cr = lane < FR_R ? c : 0.0;
-      if (type == 1) {
-        const double d = __shfl(c, FR + 1, WAVE);
-        const double yp = __shfl(r, p, WAVE);
-        if (lane == p) solr[t * NK + p] = yp;  // forward value, consumed by the backward sweep
-        r -= cr * (yp / d);
-      } else if (type == 0) {
-        const double yp = __shfl(r, p, WAVE);
-        if (lane == p) solr[t * NK + p] = yp;
-      } else if (type == 2) {
-        const double c1 = sb[(s + 1) * SLOT + lane];
-        const int q = ((int)__shfl(c1, FR, WAVE)) & 63;
-        const double e11 = __shfl(c, FR + 1, WAVE), e12 = __shfl(c, FR + 2, WAVE);
-        const double e22 = __shfl(c1, FR + 1, WAVE);
-        const double yk = __shfl(r, p, WAVE), yq = __shfl(r, q, WAVE);
-        if (lane == p) solr[t * NK + p] = yk;
-        if (lane == q) solr[t * NK + q] = yq;
-        const double det = e11 * e22 - e12 * e12;
-        const double t1 = (e22 * yk - e12 * yq) / det, t2 = (e11 * yq - e12 * yk) / det;
-        const double c1r = lane < FR_R ? c1 : 0.0;
-        r -= cr * t1 + c1r * t2;
+      if (type == 2) {
+        const int q = ((int)rdl(cn, FR)) & 63;
+        const double e11 = rdl(c, FR + 1), e12 = rdl(c, FR + 2), e22 = rdl(cn, FR + 1);
+        const double yk = rdl(r, p), yq = rdl(r, q);
+        if (lane == s) ys = yk;
+        if (lane == s + 1) ys = yq;
+        const double idet = 1.0 / (e11 * e22 - e12 * e12);
+        const double t1 = (e22 * yk - e12 * yq) * idet, t2 = (e11 * yq - e12 * yk) * idet;
+        const double c1r = lane < FR_R ? cn : 0.0;
+        r = fma(-cr, t1, fma(-c1r, t2, r));
         s += 1;
+        c = s + 1 < NK ? sb[(s + 1) * SLOT + lane] : 0.0;
+        continue;
       }
+      const double yp = rdl(r, p);
+      if (lane == s) ys = yp;
+      if (type == 1) r = fma(-cr, yp * rdl(c, FR + 2), r);
+      c = cn;
     }
+    if (lane < NK) solr[t * NK + lane] = ys;  // forward values in slot order
     ctb = (lane >= NK && lane < NK + NC) ? r : 0.0;
     __syncthreads();
   }
   // backward sweep
-  double x = 0.0, sig = 0.0;
+  sh[lane] = 0.0;
+  __syncthreads();
+  double sig = 0.0;
   for (int n = N - 1; n >= 0; --n) {
     const long long t = (long long)w * N + n;
     const double* sb = slots + t * NK * SLOT;
-    if (lane < NK) x = 0.0;
-    for (int s = NK - 1; s >= 0; --s) {
-      const double c = sb[s * SLOT + lane];
-      const int code = (int)__shfl(c, FR, WAVE);
-      const int type = code >> 6, p = code & 63;
-      const double cr = lane < FR_R ? c : 0.0;
-      if (type == 1 || type == 0) {
-        const double d = __shfl(c, FR + 1, WAVE);
-        const double pr = wave_sum(cr * x);
-        const double yp = solr[t * NK + p];
-        if (lane == p) x = type ? (yp - pr) / d : 0.0;
-      } else {
-        const double c0 = sb[(s - 1) * SLOT + lane];
-        const int pk = ((int)__shfl(c0, FR, WAVE)) & 63;
-        const double e11 = __shfl(c0, FR + 1, WAVE), e12 = __shfl(c0, FR + 2, WAVE);
-        const double e22 = __shfl(c, FR + 1, WAVE);
-        const double c0r = lane < FR_R ? c0 : 0.0;
-        const double yk = solr[t * NK + pk] - wave_sum(c0r * x);
-        const double yq = solr[t * NK + p] - wave_sum(cr * x);
-        const double det = e11 * e22 - e12 * e12;
-        if (lane == pk) x = (e22 * yk - e12 * yq) / det;
-        if (lane == p) x = (e11 * yq - e12 * yk) / det;
-        s -= 1;
-      }
+    const double y = lane < NK ? solr[t * NK + lane] : 0.0;
+    double x_s, unused;
+    int p_s;
+    backward_stage(sb, y, 0.0, sh, sh, false, x_s, unused, p_s);
+    __syncthreads();
+    if (lane < NK) {
+      solr[t * NK + p_s] = x_s;
+      sh[p_s] = x_s;
     }
     __syncthreads();
-    if (lane < NK) solr[t * NK + lane] = x;
-    if (lane == NK - 1) sig += rec[t * REC + jd] * x;
-    sh[lane] = x;
-    __syncthreads();
-    if (lane >= NK && lane < NK + NC) x = sh[coupling_index(lane - NK)];
-    __syncthreads();
+    if (lane == NK - 1) sig += rec[t * REC + jd] * sh[NK - 1];
   }
   if (lane == NK - 1) part[(long long)w * 4 + 1] = sig;
 }
@@ -620,134 +693,161 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
   if (i < n) y[i] += a * x[i];
 }
 
-// Residual of the bordered KKT system for the rows of stage (w, n):
-// res = rhs - K sol; part of the d row (b * sol_hyd) in dpart; per-stage
-// componentwise backward error max_i |res_i| / (|K||sol| + |rhs|)_i in omg.
-__global__ void k_residual(const double* __restrict__ rec, const int* __restrict__ jtab,
-                           const double* __restrict__ diagx, const double* __restrict__ diags, double dw, double dc,
-                           const double* __restrict__ sol, const double* __restrict__ rhs, int N, int S, int jd,
-                           double* __restrict__ res, double* __restrict__ dpart, double* __restrict__ dabs,
-                           double* __restrict__ omg) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)N * S) return;
-  const int n = (int)(t % N);
-  const long long nkk = (long long)N * S * NK;
-  const double* R = rec + t * REC;
-  const double* u = sol + t * NK;
-  double ku[NK], ka[NK];
-#pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    ku[k] = 0.0;
-    ka[k] = 0.0;
-  }
-  // own Jacobian block (rows: duals, cols: primals) and the d entry
-  for (int e = 0; e < NJO; ++e) {
-    const int rc = jtab[e];
-    const int r = rc & 255, col = (rc >> 8) & 255, blk = rc >> 16;
-    const double j = R[REC_OWN + e];
-    const int dr = r < NE ? NV + r : NK - 1;
-    if (blk == BLK_D) {
-      ku[dr] += j * sol[nkk];
-      ka[dr] += fabs(j * sol[nkk]);
-      continue;
+// Residual of the bordered KKT system for the rows of stage (w, n) (one thread
+// per stage, accumulators in LDS, row-major over the block so that the uniform
+// row index of a table entry gives consecutive addresses): res = rhs - K sol.
+// Per block: the sum of b * sol_hyd and of its magnitude (d row) and the
+// largest componentwise backward error |res_i| / (|K||sol| + |rhs|)_i.
+constexpr int RES_BS = 64;
+__global__ __launch_bounds__(RES_BS) void k_residual(const double* __restrict__ rec, const int* __restrict__ jtab,
+                                                     const double* __restrict__ diagx, const double* __restrict__ diags,
+                                                     double dw, double dc, const double* __restrict__ sol,
+                                                     const double* __restrict__ rhs, int N, int S, int jd,
+                                                     double* __restrict__ res, double* __restrict__ bpart) {
+  __shared__ double ku[NK][RES_BS], ka[NK][RES_BS];
+  __shared__ double r0[RES_BS], r1[RES_BS], r2[RES_BS];
+  const int tid = threadIdx.x;
+  const long long t = (long long)blockIdx.x * RES_BS + tid;
+  double dp = 0.0, da = 0.0, om = 0.0;
+  if (t < (long long)N * S) {
+    const int n = (int)(t % N);
+    const long long nkk = (long long)N * S * NK;
+    const double* R = rec + t * REC;
+    const double* u = sol + t * NK;
+#define KU(k) ku[k][tid]
+#define KA(k) ka[k][tid]
+    for (int k = 0; k < NK; ++k) {
+      KU(k) = 0.0;
+      KA(k) = 0.0;
     }
-    ku[dr] += j * u[col];
-    ka[dr] += fabs(j * u[col]);
-    ku[col] += j * u[dr];
-    ka[col] += fabs(j * u[dr]);
-  }
-  if (n < N - 1) {  // this stage's rows against stage n+1's primals
-    for (int e = 0; e < NJU; ++e) {
-      const int rc = jtab[NJO + e];
-      const int r = rc & 255, col = (rc >> 8) & 255;
-      const double j = R[REC_UP + e];
-      ku[NV + r] += j * u[NK + col];
-      ka[NV + r] += fabs(j * u[NK + col]);
+    for (int e = 0; e < NJO; ++e) {  // own block (rows: duals, cols: primals) and the d entry
+      const int rc = jtab[e];
+      const int r = rc & 255, col = (rc >> 8) & 255, blk = rc >> 16;
+      const double j = R[REC_OWN + e];
+      const int dr = r < NE ? NV + r : NK - 1;
+      if (blk == BLK_D) {
+        KU(dr) += j * sol[nkk];
+        KA(dr) += fabs(j * sol[nkk]);
+        continue;
+      }
+      KU(dr) += j * u[col];
+      KA(dr) += fabs(j * u[col]);
+      KU(col) += j * u[dr];
+      KA(col) += fabs(j * u[dr]);
     }
-    const double* R1 = R + REC;  // stage n+1's rows against this stage's primals
-    for (int e = 0; e < NJD; ++e) {
-      const int rc = jtab[NJO + NJU + e];
-      const int r = rc & 255, col = (rc >> 8) & 255;
-      const double j = R1[REC_DOWN + e];
-      ku[col] += j * u[NK + NV + r];
-      ka[col] += fabs(j * u[NK + NV + r]);
+    if (n < N - 1) {
+      for (int e = 0; e < NJU; ++e) {  // this stage's rows against stage n+1's primals
+        const int rc = jtab[NJO + e];
+        const int r = rc & 255, col = (rc >> 8) & 255;
+        const double j = R[REC_UP + e];
+        KU(NV + r) += j * u[NK + col];
+        KA(NV + r) += fabs(j * u[NK + col]);
+      }
+      const double* R1 = R + REC;  // stage n+1's rows against this stage's primals
+      for (int e = 0; e < NJD; ++e) {
+        const int rc = jtab[NJO + NJU + e];
+        const int r = rc & 255, col = (rc >> 8) & 255;
+        const double j = R1[REC_DOWN + e];
+        KU(col) += j * u[NK + NV + r];
+        KA(col) += fabs(j * u[NK + NV + r]);
+      }
     }
-  }
-  if (n > 0) {
-    for (int e = 0; e < NJD; ++e) {  // this stage's rows against stage n-1's primals
-      const int rc = jtab[NJO + NJU + e];
-      const int r = rc & 255, col = (rc >> 8) & 255;
-      const double j = R[REC_DOWN + e];
-      ku[NV + r] += j * u[-NK + col];
-      ka[NV + r] += fabs(j * u[-NK + col]);
+    if (n > 0) {
+      for (int e = 0; e < NJD; ++e) {  // this stage's rows against stage n-1's primals
+        const int rc = jtab[NJO + NJU + e];
+        const int r = rc & 255, col = (rc >> 8) & 255;
+        const double j = R[REC_DOWN + e];
+        KU(NV + r) += j * u[-NK + col];
+        KA(NV + r) += fabs(j * u[-NK + col]);
+      }
+      const double* R0 = R - REC;  // stage n-1's rows against this stage's primals
+      for (int e = 0; e < NJU; ++e) {
+        const int rc = jtab[NJO + e];
+        const int r = rc & 255, col = (rc >> 8) & 255;
+        const double j = R0[REC_UP + e];
+        KU(col) += j * u[-NK + NV + r];
+        KA(col) += fabs(j * u[-NK + NV + r]);
+      }
     }
-    const double* R0 = R - REC;  // stage n-1's rows against this stage's primals
-    for (int e = 0; e < NJU; ++e) {
-      const int rc = jtab[NJO + e];
-      const int r = rc & 255, col = (rc >> 8) & 255;
-      const double j = R0[REC_UP + e];
-      ku[col] += j * u[-NK + NV + r];
-      ka[col] += fabs(j * u[-NK + NV + r]);
+    HessPos pos[NH];
+    hess_positions(pos);
+    for (int e = 0; e < NH; ++e) {
+      const int a = pos[e].r, b = pos[e].c;
+      const double hv = R[REC_H + e];
+      KU(a) += hv * u[b];
+      KA(a) += fabs(hv * u[b]);
+      if (a != b) {
+        KU(b) += hv * u[a];
+        KA(b) += fabs(hv * u[a]);
+      }
     }
-  }
-  // Hessian block
-  HessPos pos[NH];
-  hess_positions(pos);
-  for (int e = 0; e < NH; ++e) {
-    const int a = pos[e].r, b = pos[e].c;
-    const double hv = R[REC_H + e];
-    ku[a] += hv * u[b];
-    ka[a] += fabs(hv * u[b]);
-    if (a != b) {
-      ku[b] += hv * u[a];
-      ka[b] += fabs(hv * u[a]);
+    for (int k = 0; k < NV; ++k) {
+      const double dg = diagx[t * NV + k] + dw;
+      KU(k) += dg * u[k];
+      KA(k) += fabs(dg * u[k]);
     }
+    for (int r = 0; r < NE; ++r) {
+      KU(NV + r) -= dc * u[NV + r];
+      KA(NV + r) += fabs(dc * u[NV + r]);
+    }
+    {
+      const double dh = -(1.0 / (diags[t] + dw) + dc);
+      KU(NK - 1) += dh * u[NK - 1];
+      KA(NK - 1) += fabs(dh * u[NK - 1]);
+    }
+    for (int k = 0; k < NK; ++k) {
+      const double rr = rhs[t * NK + k] - KU(k);
+      res[t * NK + k] = rr;
+      const double den = KA(k) + fabs(rhs[t * NK + k]);
+      const double o = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
+      om = fmax(om, o);
+    }
+#undef KU
+#undef KA
+    dp = R[jd] * u[NK - 1];
+    da = fabs(dp);
   }
-  for (int k = 0; k < NV; ++k) {
-    const double dg = diagx[t * NV + k] + dw;
-    ku[k] += dg * u[k];
-    ka[k] += fabs(dg * u[k]);
+  r0[tid] = dp;
+  r1[tid] = da;
+  r2[tid] = om;
+  __syncthreads();
+  for (int s = RES_BS / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      r0[tid] += r0[tid + s];
+      r1[tid] += r1[tid + s];
+      r2[tid] = fmax(r2[tid], r2[tid + s]);
+    }
+    __syncthreads();
   }
-  for (int r = 0; r < NE; ++r) {
-    ku[NV + r] -= dc * u[NV + r];
-    ka[NV + r] += fabs(dc * u[NV + r]);
+  if (tid == 0) {
+    bpart[blockIdx.x * 3 + 0] = r0[0];
+    bpart[blockIdx.x * 3 + 1] = r1[0];
+    bpart[blockIdx.x * 3 + 2] = r2[0];
   }
-  {
-    const double dh = -(1.0 / (diags[t] + dw) + dc);
-    ku[NK - 1] += dh * u[NK - 1];
-    ka[NK - 1] += fabs(dh * u[NK - 1]);
-  }
-  double om = 0.0;
-  for (int k = 0; k < NK; ++k) {
-    const double rr = rhs[t * NK + k] - ku[k];
-    res[t * NK + k] = rr;
-    const double den = ka[k] + fabs(rhs[t * NK + k]);
-    const double o = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
-    om = fmax(om, o);
-  }
-  omg[t] = om;
-  dpart[t] = R[jd] * u[NK - 1];
-  dabs[t] = fabs(R[jd] * u[NK - 1]);
 }
 
-// d row of the residual: res_d = rhs_d - sum b u_hyd - kdd u_d (one block, fixed order)
-__global__ void k_residual_d(const double* __restrict__ dpart, const double* __restrict__ dabs, long long nst,
-                             const DevScalars* __restrict__ sc, const double* __restrict__ sol,
-                             const double* __restrict__ rhs, long long nkk, double* __restrict__ res,
-                             double* __restrict__ omg_d) {
-  __shared__ double s1[256], s2[256];
-  double a = 0, b = 0;
-  for (long long t = threadIdx.x; t < nst; t += blockDim.x) {
-    a += dpart[t];
-    b += dabs[t];
+// d row of the residual from the block partials (one block, fixed order):
+// res_d = rhs_d - sum b u_hyd - kdd u_d; omega_out[0] = largest backward error
+// of the scenario rows, omega_out[1] = that of the d row
+__global__ void k_residual_d(const double* __restrict__ bpart, int nb, const DevScalars* __restrict__ sc,
+                             const double* __restrict__ sol, const double* __restrict__ rhs, long long nkk,
+                             double* __restrict__ res, double* __restrict__ omega_out) {
+  __shared__ double s1[256], s2[256], s3[256];
+  double a = 0, b = 0, m = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    a += bpart[i * 3 + 0];
+    b += bpart[i * 3 + 1];
+    m = fmax(m, bpart[i * 3 + 2]);
   }
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = b;
+  s3[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
       s1[threadIdx.x] += s1[threadIdx.x + s];
       s2[threadIdx.x] += s2[threadIdx.x + s];
+      s3[threadIdx.x] = fmax(s3[threadIdx.x], s3[threadIdx.x + s]);
     }
     __syncthreads();
   }
@@ -757,21 +857,9 @@ __global__ void k_residual_d(const double* __restrict__ dpart, const double* __r
     const double rr = rhs[nkk] - ku;
     res[nkk] = rr;
     const double den = ka + fabs(rhs[nkk]);
-    *omg_d = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
+    omega_out[0] = s3[0];
+    omega_out[1] = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
   }
-}
-
-__global__ void k_max_reduce(const double* __restrict__ v, long long n, double* __restrict__ out) {
-  __shared__ double sm[256];
-  double a = 0.0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) a = fmax(a, v[i]);
-  sm[threadIdx.x] = a;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = sm[0];
 }
 
 inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -855,16 +943,12 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
                            const double* sol, const double* rhs, double* res, double* omega_out, hipStream_t st) {
   const long long nst = (long long)h.N * h.S;
   const long long nkk = nst * NK;
-  double* dpart = h.kden;
-  double* dabs = h.kden + nst;
-  double* omg = h.kden + 2 * nst;
+  const int nb = (int)grid_for(nst, RES_BS);  // block partials in kden (3 per block)
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(nst, 64)), dim3(64), 0, st, h.rec, h.jtab, diagx, diags, dw, dc, sol,
-                     rhs, h.N, h.S, h.jac_d_index, res, dpart, dabs, omg);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_BS), 0, st, h.rec, h.jtab, diagx, diags, dw, dc, sol, rhs, h.N,
+                     h.S, h.jac_d_index, res, h.kden);
   prof_end(h, 3, st);
-  hipLaunchKernelGGL(k_residual_d, dim3(1), dim3(256), 0, st, dpart, dabs, nst, h.scal, sol, rhs, nkk, res,
-                     omega_out + 1);
-  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, st, omg, nst, omega_out);
+  hipLaunchKernelGGL(k_residual_d, dim3(1), dim3(256), 0, st, h.kden, nb, h.scal, sol, rhs, nkk, res, omega_out);
   return hipGetLastError();
 }
 
