@@ -229,6 +229,7 @@ __global__ void k_hess_dd(const double* __restrict__ lam, ModelParams p, long lo
 // lane through v_readlane (uniform operands), the pivot row is selected by a
 // uniform switch, and the diagonal is kept up to date per lane.
 struct WaveLDS {
+  double bc[WAVE];  // pivot row of the current elimination step (first: reachable by immediate offsets)
   double src[NSRC];
   double xr[WAVE];
   double xb[WAVE];
@@ -292,8 +293,8 @@ __device__ __forceinline__ double wave_max_lane(double a, int lane, int& idx) {
 // stores one pivot column per slot (rows still active, code, d or 2x2 block,
 // 1/d).  The matrix is symmetric, so the pivot candidates' columns are read
 // as rows (register p of every lane) with a uniform switch.
-__device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restrict__ sb, long long& npos,
-                                                long long& nneg, long long& nzero) {
+__device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restrict__ sb, double* bc,
+                                                int& npos, int& nneg, int& nzero) {
   int lane = lane_id();
   __asm__ volatile("" : "+v"(lane));
   const double alpha = (1.0 + sqrt(17.0)) * 0.125;
@@ -338,8 +339,9 @@ __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restr
         ++nzero;
         zero = true;
       } else {
-        if (d > 0.0) ++npos;
-        else ++nneg;
+        const int pos = d > 0.0 ? 1 : 0;  // branch-free: keeps the counters in registers
+        npos += pos;
+        nneg += 1 - pos;
         t1 = ca ? rk * dinv : 0.0;
       }
     } else {
@@ -363,8 +365,9 @@ __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restr
         ++npos;
         ++nneg;
       } else if (det > 0.0) {
-        if (e11 + e22 > 0.0) npos += 2;
-        else nneg += 2;
+        const int pos = e11 + e22 > 0.0 ? 2 : 0;
+        npos += pos;
+        nneg += 2 - pos;
       } else {
         nzero += 2;
         zero = true;
@@ -378,13 +381,31 @@ __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restr
     }
     act &= ~((1ull << p0) | (1ull << p1));
     if (zero) continue;
-    // rows already eliminated are updated too: they are never read again
+    // The pivot row reaches every lane through LDS (all lanes read the same
+    // address, a broadcast).  Rows already eliminated (and p0/p1 themselves)
+    // are updated too: they are never read again.  A 2x2 pivot is applied as
+    // two rank-1 passes (c1 t1^T, then c2 t2^T).
+    for (int pass = 0; pass < (two ? 2 : 1); ++pass) {
+      const double tt = pass ? t2 : t1;
+      bc[lane] = pass ? rr : rk;
+      __syncthreads();
+      // software pipelined: the next eight entries are read while eight rows update
+      double qa[8], qb[8];
 #pragma unroll
-    for (int i = 0; i < FR; ++i) {
-      double x = fma(-rdl(rk, i), t1, v[i]);
-      if (two) x = fma(-rdl(rr, i), t2, x);
-      v[i] = x;
-      if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      for (int j = 0; j < 8; ++j) qa[j] = bc[j];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c < 7) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) qb[j] = bc[8 * (c + 1) + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (8 * c + j < FR) v[8 * c + j] = fma(-qa[j], tt, v[8 * c + j]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) qa[j] = qb[j];
+      }
+      __syncthreads();
     }
   }
 }
@@ -476,7 +497,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void 
   const int lane = lane_id();
   for (int i = lane; i < NC * (NC + 2); i += WAVE) L.src[SRC_CTB + i] = 0.0;
   if (lane == 0) L.src[SRC_ZERO] = 0.0;
-  long long npos = 0, nneg = 0, nzero = 0;
+  int npos = 0, nneg = 0, nzero = 0;
   for (int n = 0; n < N; ++n) {
     const long long t = (long long)w * N + n;
     const double* R = rec + t * REC;
@@ -501,7 +522,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void 
       if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    eliminate_stage(v, slots + t * NK * SLOT, npos, nneg, nzero);
+    eliminate_stage(v, slots + t * NK * SLOT, L.bc, npos, nneg, nzero);
     // contribution block to stage n+1 (rows/cols 43..60 of the coupling lanes)
     if (lane >= NK && lane < NK + NC) {
       const int a = lane - NK;
@@ -545,9 +566,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void 
     part[(long long)w * 4 + 3] = 0.0;
   }
   if (lane == 0) {
-    inert[w * 4 + 0] = (int)npos;
-    inert[w * 4 + 1] = (int)nneg;
-    inert[w * 4 + 2] = (int)nzero;
+    inert[w * 4 + 0] = npos;
+    inert[w * 4 + 1] = nneg;
+    inert[w * 4 + 2] = nzero;
     inert[w * 4 + 3] = 0;
   }
 }
