@@ -591,30 +591,38 @@ __global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, 
     __syncthreads();
     double r = (lane < NK ? rhs[t * NK + lane] + sh[lane] : 0.0);
     double ys = 0.0;  // lane s keeps the forward value of slot s
-    double c = sb[lane];
-    for (int s = 0; s < NK; ++s) {
-      const double cn = s + 1 < NK ? sb[(s + 1) * SLOT + lane] : 0.0;  // prefetch the next column
+    // the stage's 43 pivot columns, all loads in flight at once (lane = row)
+    double col[NK];
+#pragma unroll
+    for (int q = 0; q < NK; ++q) col[q] = sb[q * SLOT + lane];
+    bool skip = false;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+      if (skip) {  // second slot of a 2x2 pivot, applied with the first
+        skip = false;
+        continue;
+      }
+      const double c = col[q];
       const int code = (int)rdl(c, FR);
       const int type = code >> 6, p = code & 63;
       const double cr = lane < FR_R ? c : 0.0;
-      if (type == 2) {
-        const int q = ((int)rdl(cn, FR)) & 63;
+      if (q + 1 < NK && type == 2) {
+        const double cn = col[q + 1 < NK ? q + 1 : q];
+        const int pq = ((int)rdl(cn, FR)) & 63;
         const double e11 = rdl(c, FR + 1), e12 = rdl(c, FR + 2), e22 = rdl(cn, FR + 1);
-        const double yk = rdl(r, p), yq = rdl(r, q);
-        if (lane == s) ys = yk;
-        if (lane == s + 1) ys = yq;
+        const double yk = rdl(r, p), yq = rdl(r, pq);
+        if (lane == q) ys = yk;
+        if (lane == q + 1) ys = yq;
         const double idet = 1.0 / (e11 * e22 - e12 * e12);
         const double t1 = (e22 * yk - e12 * yq) * idet, t2 = (e11 * yq - e12 * yk) * idet;
         const double c1r = lane < FR_R ? cn : 0.0;
         r = fma(-cr, t1, fma(-c1r, t2, r));
-        s += 1;
-        c = s + 1 < NK ? sb[(s + 1) * SLOT + lane] : 0.0;
+        skip = true;
         continue;
       }
       const double yp = rdl(r, p);
-      if (lane == s) ys = yp;
+      if (lane == q) ys = yp;
       if (type == 1) r = fma(-cr, yp * rdl(c, FR + 2), r);
-      c = cn;
     }
     if (lane < NK) solr[t * NK + lane] = ys;  // forward values in slot order
     ctb = (lane >= NK && lane < NK + NC) ? r : 0.0;
