@@ -194,6 +194,106 @@ typedef struct {
 int absorber_profile_enable(absorber_t* h, int32_t mask);
 int absorber_profile_get(const absorber_t* h, absorber_profile* out);
 
+/* ------------------------------------------------------------------------
+ * Warm-start network.  Not part of the paper's method: a multilayer
+ * perceptron  inputs -> [Linear -> GELU(erf)] x n_layers -> Linear -> outputs
+ * that predicts a scenario's converged stage states from its feed, used to
+ * start the interior-point solve near the solution.  GEMM operands are
+ * bfloat16 (round to nearest even) on the matrix cores with float32
+ * accumulation; biases, pre-activations and the optimiser state are float32.
+ *
+ * Parameters (host or device, float32) use one flat layout: for each linear
+ * layer l = 0..n_layers, W_l [out][in] row-major, then b_l [out].
+ * Inputs and targets are float32 row-major [n][n_in] / [n][n_out] in their own
+ * units; the network standardises them with per-column mean and standard
+ * deviation (identity until set or fitted) and returns outputs in the units
+ * of the targets.  Training minimises the mean squared error of the
+ * standardised outputs with Adam (Kingma & Ba 2015) and a cosine learning
+ * rate, over shuffled mini-batches (the last partial batch of an epoch is
+ * dropped).
+ * ------------------------------------------------------------------------ */
+typedef struct absorber_mlp absorber_mlp;
+
+typedef struct {
+  int32_t n_in;       /* input features, 1..32 (3: gas flow, CO2 fraction, gas temperature) */
+  int32_t n_hidden;   /* width of every hidden layer, a multiple of 32 (256) */
+  int32_t n_layers;   /* hidden layers, >= 1 (3) */
+  int32_t n_out;      /* outputs (21 N: one stage vector per stage) */
+  int32_t max_batch;  /* rows per forward chunk and largest training batch, a multiple of 32 (512) */
+} absorber_mlp_config;
+
+typedef struct {
+  int32_t epochs;     /* 300 */
+  int32_t batch;      /* rows per step, a multiple of 32, <= max_batch (512) */
+  double lr;          /* peak learning rate (1e-3) */
+  double beta1, beta2, eps;  /* Adam constants (0.9, 0.999, 1e-8) */
+  uint64_t seed;      /* shuffling seed */
+  int32_t cosine;     /* 1: lr * (1 + cos(pi step / steps)) / 2; 0: constant lr */
+} absorber_mlp_train_options;
+
+typedef struct {
+  double final_loss;  /* mean squared error of the last batch (standardised units) */
+  double seconds;     /* wall time of the training call */
+  int64_t steps;      /* optimiser steps taken */
+} absorber_mlp_train_result;
+
+void absorber_mlp_default_config(absorber_mlp_config* cfg);
+void absorber_mlp_default_train_options(absorber_mlp_train_options* opts);
+/* He-normal weights from seed, zero biases.  Blocking.  ABS_ERR_ARG on a bad
+ * configuration, ABS_ERR_OOM when device memory runs out. */
+int absorber_mlp_create(const absorber_mlp_config* cfg, uint64_t seed, absorber_mlp** out);
+void absorber_mlp_destroy(absorber_mlp* net);
+int absorber_mlp_get_config(const absorber_mlp* net, absorber_mlp_config* out);
+int64_t absorber_mlp_num_params(const absorber_mlp* net);
+/* Copy the flat float32 parameters in (resets the Adam state) or out.  Blocking. */
+int absorber_mlp_set_params(absorber_mlp* net, const float* params_host);
+int absorber_mlp_get_params(const absorber_mlp* net, float* params_host);
+/* Standardisation constants, host arrays of n_in / n_out floats.  Blocking. */
+int absorber_mlp_set_normalization(absorber_mlp* net, const float* in_mean, const float* in_std,
+                                   const float* out_mean, const float* out_std);
+int absorber_mlp_get_normalization(const absorber_mlp* net, float* in_mean, float* in_std, float* out_mean,
+                                   float* out_std);
+/* Set the standardisation from data: column means and standard deviations of
+ * X_dev [n][n_in] and T_dev [n][n_out] (sd floored at 1e-6 (1 + |mean|)). */
+int absorber_mlp_fit_normalization(absorber_mlp* net, const float* X_dev, const float* T_dev, int64_t n,
+                                   void* stream);
+/* Y_dev [n][n_out] = network(X_dev [n][n_in]), any n >= 0 (processed in
+ * chunks of max_batch rows).  The caller must not run two calls on one
+ * network concurrently (they share its activation buffers). */
+int absorber_mlp_forward(absorber_mlp* net, const float* X_dev, int64_t n, float* Y_dev, void* stream);
+/* One mini-batch of n rows (n a multiple of 32, <= max_batch): the gradient of
+ * the mean squared error of the standardised outputs with respect to the flat
+ * parameters into grad_dev [num_params]; the loss into *loss_host (may be
+ * NULL).  Blocking (it reads the loss). */
+int absorber_mlp_loss_grad(absorber_mlp* net, const float* X_dev, const float* T_dev, int64_t n, float* grad_dev,
+                           double* loss_host, void* stream);
+/* One Adam step with gradient grad_dev [num_params] and learning rate lr
+ * (beta1, beta2, eps from opts); also refreshes the bfloat16 weights. */
+int absorber_mlp_adam_step(absorber_mlp* net, const float* grad_dev, const absorber_mlp_train_options* opts,
+                           double lr, void* stream);
+/* Fit the standardisation to the data, then train for opts->epochs epochs on
+ * X_dev [n][n_in], T_dev [n][n_out] (n >= opts->batch).  Blocking, null stream. */
+int absorber_mlp_train(absorber_mlp* net, const float* X_dev, const float* T_dev, int64_t n,
+                       const absorber_mlp_train_options* opts, absorber_mlp_train_result* result);
+
+/* Warm-start encoding of the absorber problem.
+ * features: X_dev [S][3] float = (flue-gas flow, CO2 fraction, temperature) of
+ *   each scenario's feed.
+ * targets: T_dev [S][21 N] float from a primal vector x_dev[nx]: per stage
+ *   vector, ln of the 13 mole fractions (floored at 1e-30), the other 8
+ *   entries as they are (the d entry is not encoded).
+ * point: the inverse of targets for predicted Y_dev [S][21 N], written to
+ *   x0_dev[nx]; d = (1 + d_margin) * the largest hydraulic diameter
+ *   sqrt(4 V R T / (pi u_max P)) of the decoded stages (d_margin >= 0).
+ * warm_start: features -> network -> point, with caller workspaces
+ *   X_work_dev [S][3] and Y_work_dev [S][21 N]; the network must have n_in = 3
+ *   and n_out = 21 N.  All four are asynchronous on stream. */
+int absorber_warm_features(absorber_t* h, float* X_dev, void* stream);
+int absorber_warm_targets(absorber_t* h, const double* x_dev, float* T_dev, void* stream);
+int absorber_warm_point(absorber_t* h, const float* Y_dev, double d_margin, double* x0_dev, void* stream);
+int absorber_warm_start(absorber_t* h, absorber_mlp* net, float* X_work_dev, float* Y_work_dev, double d_margin,
+                        double* x0_dev, void* stream);
+
 const char* absorber_last_error(void);
 
 #ifdef __cplusplus

@@ -14,6 +14,8 @@ from .binding import (  # noqa: F401
     AbsorberError,
     IpmOptions,
     IpmResult,
+    Mlp,
+    MlpTrainOptions,
     absorber_create,
     lib,
     params_struct,

@@ -23,6 +23,7 @@ ERRORS = {
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int64_p = ctypes.POINTER(ctypes.c_int64)
+c_float_p = ctypes.POINTER(ctypes.c_float)
 
 
 class AbsorberError(RuntimeError):
@@ -80,6 +81,22 @@ class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 4), ("calls", ctypes.c_int64 * 4), ("bytes_factor_slots", ctypes.c_int64)]
 
 
+class MlpConfig(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("n_in", "n_hidden", "n_layers", "n_out", "max_batch")]
+
+
+class MlpTrainOptions(ctypes.Structure):
+    _fields_ = [
+        ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+        ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("cosine", ctypes.c_int32),
+    ]
+
+
+class MlpTrainResult(ctypes.Structure):
+    _fields_ = [("final_loss", ctypes.c_double), ("seconds", ctypes.c_double), ("steps", ctypes.c_int64)]
+
+
 PROFILE_CLASSES = ("factor", "solve", "eval", "residual")
 
 _lib = None
@@ -114,6 +131,26 @@ def lib():
             "absorber_profile_enable": (ctypes.c_int, [vp, i32]),
             "absorber_profile_get": (ctypes.c_int, [vp, ctypes.POINTER(Profile)]),
             "absorber_last_error": (ctypes.c_char_p, []),
+            "absorber_mlp_default_config": (None, [ctypes.POINTER(MlpConfig)]),
+            "absorber_mlp_default_train_options": (None, [ctypes.POINTER(MlpTrainOptions)]),
+            "absorber_mlp_create": (ctypes.c_int, [ctypes.POINTER(MlpConfig), ctypes.c_uint64, ctypes.POINTER(vp)]),
+            "absorber_mlp_destroy": (None, [vp]),
+            "absorber_mlp_get_config": (ctypes.c_int, [vp, ctypes.POINTER(MlpConfig)]),
+            "absorber_mlp_num_params": (i64, [vp]),
+            "absorber_mlp_set_params": (ctypes.c_int, [vp, c_float_p]),
+            "absorber_mlp_get_params": (ctypes.c_int, [vp, c_float_p]),
+            "absorber_mlp_set_normalization": (ctypes.c_int, [vp, c_float_p, c_float_p, c_float_p, c_float_p]),
+            "absorber_mlp_get_normalization": (ctypes.c_int, [vp, c_float_p, c_float_p, c_float_p, c_float_p]),
+            "absorber_mlp_fit_normalization": (ctypes.c_int, [vp, vp, vp, i64, vp]),
+            "absorber_mlp_forward": (ctypes.c_int, [vp, vp, i64, vp, vp]),
+            "absorber_mlp_loss_grad": (ctypes.c_int, [vp, vp, vp, i64, vp, c_double_p, vp]),
+            "absorber_mlp_adam_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(MlpTrainOptions), dbl, vp]),
+            "absorber_mlp_train": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(MlpTrainOptions),
+                                                  ctypes.POINTER(MlpTrainResult)]),
+            "absorber_warm_features": (ctypes.c_int, [vp, vp, vp]),
+            "absorber_warm_targets": (ctypes.c_int, [vp, vp, vp, vp]),
+            "absorber_warm_point": (ctypes.c_int, [vp, vp, dbl, vp, vp]),
+            "absorber_warm_start": (ctypes.c_int, [vp, vp, vp, vp, dbl, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -275,6 +312,22 @@ class Absorber:
         _check(lib().absorber_kkt_solve(self.h, _ptr(rhs), _ptr(sol), ctypes.byref(rel), _stream(stream)))
         return rel.value
 
+    def warm_features(self, X, stream=None):
+        """X: float32 (S, 3) device tensor <- (gas flow, CO2 fraction, gas temperature) per scenario."""
+        _check(lib().absorber_warm_features(self.h, _ptr(X), _stream(stream)))
+
+    def warm_targets(self, x, T, stream=None):
+        """T: float32 (S, 21 N) <- network encoding of the primal vector x (float64, nx)."""
+        _check(lib().absorber_warm_targets(self.h, _ptr(x), _ptr(T), _stream(stream)))
+
+    def warm_point(self, Y, x0, d_margin=1e-3, stream=None):
+        """x0 (float64, nx) <- decoded stage vectors Y (float32, (S, 21 N)) and the starting diameter."""
+        _check(lib().absorber_warm_point(self.h, _ptr(Y), float(d_margin), _ptr(x0), _stream(stream)))
+
+    def warm_start(self, net: "Mlp", X_work, Y_work, x0, d_margin=1e-3, stream=None):
+        _check(lib().absorber_warm_start(self.h, net.h, _ptr(X_work), _ptr(Y_work), float(d_margin), _ptr(x0),
+                                         _stream(stream)))
+
     @staticmethod
     def default_options(**kw) -> IpmOptions:
         o = IpmOptions()
@@ -297,3 +350,78 @@ class Absorber:
 
 def absorber_create(params: dict, n_stages: int, feeds: np.ndarray) -> Absorber:
     return Absorber(params, n_stages, feeds)
+
+
+class Mlp:
+    """Warm-start network on the current GPU (see absorber.h)."""
+
+    def __init__(self, n_in=3, n_hidden=256, n_layers=3, n_out=210, max_batch=512, seed=0):
+        c = MlpConfig()
+        lib().absorber_mlp_default_config(ctypes.byref(c))
+        c.n_in, c.n_hidden, c.n_layers, c.n_out, c.max_batch = n_in, n_hidden, n_layers, n_out, max_batch
+        h = ctypes.c_void_p()
+        _check(lib().absorber_mlp_create(ctypes.byref(c), int(seed), ctypes.byref(h)))
+        self.h, self.cfg = h, c
+        self.n_params = int(lib().absorber_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().absorber_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def default_train_options(**kw) -> MlpTrainOptions:
+        o = MlpTrainOptions()
+        lib().absorber_mlp_default_train_options(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(lib().absorber_mlp_set_params(self.h, a.ctypes.data_as(c_float_p)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.n_params, np.float32)
+        _check(lib().absorber_mlp_get_params(self.h, a.ctypes.data_as(c_float_p)))
+        return a
+
+    def set_normalization(self, in_mean, in_std, out_mean, out_std):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (in_mean, in_std, out_mean, out_std)]
+        self._norm = arrs
+        _check(lib().absorber_mlp_set_normalization(self.h, *[a.ctypes.data_as(c_float_p) for a in arrs]))
+
+    def get_normalization(self):
+        arrs = [np.empty(n, np.float32) for n in (self.cfg.n_in, self.cfg.n_in, self.cfg.n_out, self.cfg.n_out)]
+        _check(lib().absorber_mlp_get_normalization(self.h, *[a.ctypes.data_as(c_float_p) for a in arrs]))
+        return arrs
+
+    def fit_normalization(self, X, T, stream=None):
+        _check(lib().absorber_mlp_fit_normalization(self.h, _ptr(X), _ptr(T), int(X.shape[0]), _stream(stream)))
+
+    def forward(self, X, Y, stream=None):
+        _check(lib().absorber_mlp_forward(self.h, _ptr(X), int(X.shape[0]), _ptr(Y), _stream(stream)))
+
+    def loss_grad(self, X, T, grad, stream=None) -> float:
+        loss = ctypes.c_double()
+        _check(lib().absorber_mlp_loss_grad(self.h, _ptr(X), _ptr(T), int(X.shape[0]), _ptr(grad),
+                                            ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def adam_step(self, grad, lr, opts: MlpTrainOptions | None = None, stream=None):
+        o = opts if opts is not None else self.default_train_options()
+        _check(lib().absorber_mlp_adam_step(self.h, _ptr(grad), ctypes.byref(o), float(lr), _stream(stream)))
+
+    def train(self, X, T, opts: MlpTrainOptions | None = None) -> MlpTrainResult:
+        o = opts if opts is not None else self.default_train_options()
+        r = MlpTrainResult()
+        _check(lib().absorber_mlp_train(self.h, _ptr(X), _ptr(T), int(X.shape[0]), ctypes.byref(o), ctypes.byref(r)))
+        return r

@@ -1,0 +1,157 @@
+// Warm start of the interior-point solve from the network's prediction of
+// every scenario's converged stage states.
+//
+// Because each scenario's MESH block is square in its own states (the paper's
+// problem (10): the states of a scenario are fixed by its feeds, only the
+// hydraulic rows and the objective involve d), a scenario's optimal states do
+// not depend on the other scenarios, and a network trained on single-scenario
+// solutions predicts them for any scenario set.  The encoding of a stage
+// vector for the network: mole fractions (liquid 0-8, vapour 9-12) by their
+// natural logarithm, flows, temperature and extents as they are.  The
+// starting diameter is the largest hydraulic diameter of the predicted states
+// times (1 + margin), so every hydraulic row starts feasible.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace absorber {
+namespace {
+
+constexpr int WB = 256;
+constexpr int NLOG = 13;            // stage-local entries encoded by their logarithm
+constexpr double LOG_FLOOR = 1e-30;
+
+__global__ void k_features(const double* __restrict__ feeds, int S, float* __restrict__ X) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= S) return;
+  const double* F = feeds + (long long)w * NF;
+  X[w * 3 + 0] = (float)F[0];  // flue-gas flow
+  X[w * 3 + 1] = (float)F[1];  // CO2 fraction of the flue gas
+  X[w * 3 + 2] = (float)F[5];  // flue-gas temperature
+}
+
+__global__ void k_targets(const double* __restrict__ x, long long n, float* __restrict__ T) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = (int)(i % NV);
+  const double v = x[i];
+  T[i] = (float)(k < NLOG ? log(fmax(v, LOG_FLOOR)) : v);
+}
+
+// decode the predicted stage vectors; per-block maxima of the hydraulic diameter
+__global__ void k_decode(const float* __restrict__ Y, const double* __restrict__ feeds, ModelParams p, int N,
+                         long long nst, double* __restrict__ x0, double* __restrict__ part) {
+  __shared__ double sm[WB];
+  const long long t = (long long)blockIdx.x * WB + threadIdx.x;
+  double dh = 0.0;
+  if (t < nst) {
+    const float* y = Y + t * NV;
+    double* z = x0 + t * NV;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) z[k] = k < NLOG ? exp((double)y[k]) : (double)y[k];
+    const double P = feeds[(t / N) * NF + 17];
+    const double V = z[IV], T = z[IT];
+    const double a = 4.0 * V * p.R * T / (M_PI * p.u_max * P);
+    dh = a > 0.0 ? sqrt(a) : 0.0;
+  }
+  sm[threadIdx.x] = dh;
+  __syncthreads();
+  for (int s = WB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_decode_d(const double* __restrict__ part, int nb, double margin, double* __restrict__ d0) {
+  __shared__ double sm[WB];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += WB) m = fmax(m, part[i]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = WB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *d0 = (1.0 + margin) * sm[0];
+}
+
+inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+}  // namespace absorber
+
+using absorber::Handle;
+using absorber::NV;
+using absorber::set_error;
+
+extern "C" {
+
+int absorber_warm_features(absorber_t* ah, float* X_dev, void* stream) {
+  if (!ah || !X_dev) {
+    set_error("absorber_warm_features: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = ah->h;
+  hipLaunchKernelGGL(absorber::k_features, dim3(absorber::nblk(h.S, 256)), dim3(256), 0, (hipStream_t)stream,
+                     h.feeds, h.S, X_dev);
+  HIP_TRY(hipGetLastError());
+  return ABS_OK;
+}
+
+int absorber_warm_targets(absorber_t* ah, const double* x_dev, float* T_dev, void* stream) {
+  if (!ah || !x_dev || !T_dev) {
+    set_error("absorber_warm_targets: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = ah->h;
+  const long long n = h.nx - 1;
+  hipLaunchKernelGGL(absorber::k_targets, dim3(absorber::nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x_dev,
+                     n, T_dev);
+  HIP_TRY(hipGetLastError());
+  return ABS_OK;
+}
+
+int absorber_warm_point(absorber_t* ah, const float* Y_dev, double d_margin, double* x0_dev, void* stream) {
+  if (!ah || !Y_dev || !x0_dev || !(d_margin >= 0.0)) {
+    set_error("absorber_warm_point: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = ah->h;
+  const long long nst = (long long)h.N * h.S;
+  const int nb = (int)absorber::nblk(nst, absorber::WB);
+  if (nb > h.red_cap) {
+    set_error("absorber_warm_point: problem too large for the reduction buffer");
+    return ABS_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(absorber::k_decode, dim3(nb), dim3(absorber::WB), 0, st, Y_dev, h.feeds, h.mp, h.N, nst, x0_dev,
+                     h.redbuf);
+  hipLaunchKernelGGL(absorber::k_decode_d, dim3(1), dim3(absorber::WB), 0, st, h.redbuf, nb, d_margin,
+                     x0_dev + (h.nx - 1));
+  HIP_TRY(hipGetLastError());
+  return ABS_OK;
+}
+
+int absorber_warm_start(absorber_t* ah, absorber_mlp* net, float* X_work_dev, float* Y_work_dev, double d_margin,
+                        double* x0_dev, void* stream) {
+  if (!ah || !net || !X_work_dev || !Y_work_dev || !x0_dev) {
+    set_error("absorber_warm_start: bad argument");
+    return ABS_ERR_ARG;
+  }
+  absorber_mlp_config cfg;
+  int rc = absorber_mlp_get_config(net, &cfg);
+  if (rc) return rc;
+  if (cfg.n_in != 3 || cfg.n_out != NV * ah->h.N) {
+    set_error("absorber_warm_start: the network needs 3 inputs and 21 N outputs");
+    return ABS_ERR_ARG;
+  }
+  rc = absorber_warm_features(ah, X_work_dev, stream);
+  if (!rc) rc = absorber_mlp_forward(net, X_work_dev, ah->h.S, Y_work_dev, stream);
+  if (!rc) rc = absorber_warm_point(ah, Y_work_dev, d_margin, x0_dev, stream);
+  return rc;
+}
+
+}  // extern "C"
