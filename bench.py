@@ -92,6 +92,62 @@ def cpu_baseline(params, feeds, N, iters_gpu, n_scen_sample, n_iter_sample):
     }
 
 
+def warm_leg(params, steps: int, epochs: int):
+    """Warm start at 10 stages x 5000 scenarios (seed 3): the network is trained
+    on the converged states of the 20000 training scenarios (seed 4), then the
+    warm-started solve (feature extraction + inference + IPM, cold fallback) is
+    timed against the cold-started solve of the same instance."""
+    import torch
+    from absorber_inputs import CONFIGS, feed_table, perturbations
+    from absorber_inputs.scenarios import TRAIN_SET
+    from paper_2607_15420_amd import Absorber, Mlp
+
+    dev = "cuda:0"
+    N = TRAIN_SET.n_stages
+    t0 = time.perf_counter()
+    htr = Absorber(params, N, TRAIN_SET.feeds(params))
+    xtr = torch.empty(htr.nx, dtype=torch.float64, device=dev)
+    rtr = htr.ipm_solve(x_out=xtr)
+    Xtr = torch.empty((TRAIN_SET.n_scen, 3), dtype=torch.float32, device=dev)
+    Ttr = torch.empty((TRAIN_SET.n_scen, 21 * N), dtype=torch.float32, device=dev)
+    htr.warm_features(Xtr)
+    htr.warm_targets(xtr, Ttr)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    htr.close()
+    net = Mlp(3, 256, 3, 21 * N, max_batch=512, seed=0)
+    tr = net.train(Xtr, Ttr, net.default_train_options(epochs=epochs, batch=512, lr=1e-3))
+    w = CONFIGS["C4"]
+    h = Absorber(params, w.n_stages, w.feeds(params))
+    opts = Absorber.default_options()
+    h.ipm_solve(opts)  # warm-up of both paths
+    h.warm_solve(net, opts)
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    for _ in range(steps):
+        rc = h.ipm_solve(opts)
+    torch.cuda.synchronize()
+    cold_s = (time.perf_counter() - tc) / steps
+    tw = time.perf_counter()
+    for _ in range(steps):
+        rw, used = h.warm_solve(net, opts)
+    torch.cuda.synchronize()
+    warm_s = (time.perf_counter() - tw) / steps
+    h.close()
+    net.close()
+    return {
+        "workload": f"{w.name}: {w.n_stages} stages x {w.n_scen} scenarios, feeds +-{int(w.amplitude * 100)}%, "
+                    f"seed {w.seed}; network 3-256-256-256-{21 * N}, bf16 MFMA, trained on the converged "
+                    f"states of {TRAIN_SET.n_scen} scenarios (seed {TRAIN_SET.seed})",
+        "cold_s": cold_s, "warm_s": warm_s, "speedup": cold_s / warm_s,
+        "cold_iterations": rc.iterations, "warm_iterations": rw.iterations, "warm_used": used,
+        "cold_converged": rc.status == 0 and rc.E0 <= 1e-8, "warm_converged": rw.status == 0 and rw.E0 <= 1e-8,
+        "warm_E0": rw.E0, "d_cold": rc.d, "d_warm": rw.d,
+        "datagen_s": t_data, "datagen_iterations": rtr.iterations, "train_s": tr.seconds, "train_steps": tr.steps,
+        "train_epochs": epochs, "train_final_loss": tr.final_loss,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +157,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-scen", type=int, default=16)
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--warm-epochs", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the scenario "
@@ -181,9 +239,11 @@ def main():
         "context": {"paper_h200_s": 33.3, "paper_ipopt_ma57_1thread_s": 695.5,
                     "paper_hardware": "1x H200 / Xeon 8568Y+ 1 thread; other model constants and data"},
     }
+    h.close()
+    if not args.no_warm:
+        out["warm_start"] = warm_leg(params, args.steps, args.warm_epochs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, feeds, N, r.iterations, args.cpu_scen, args.cpu_iters)
-    h.close()
     print(json.dumps(out), flush=True)
 
 

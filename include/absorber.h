@@ -293,6 +293,14 @@ int absorber_warm_targets(absorber_t* h, const double* x_dev, float* T_dev, void
 int absorber_warm_point(absorber_t* h, const float* Y_dev, double d_margin, double* x0_dev, void* stream);
 int absorber_warm_start(absorber_t* h, absorber_mlp* net, float* X_work_dev, float* Y_work_dev, double d_margin,
                         double* x0_dev, void* stream);
+/* Warm-started solve with cold-start fallback: warm_start (workspaces owned by
+ * the handle, allocated on the first call), then absorber_ipm_solve with
+ * opts->warm_start = 1 and the least-squares multiplier estimate; if that does
+ * not reach opts->tol, a cold-started solve from the paper's initial point.
+ * *used_warm (may be NULL) is 1 when the warm solve succeeded.  result->seconds
+ * covers the whole call and result->iterations both solves.  Blocking. */
+int absorber_warm_solve(absorber_t* h, absorber_mlp* net, const absorber_ipm_options* opts, double d_margin,
+                        double* x_out_dev, double* lambda_out_dev, absorber_ipm_result* result, int32_t* used_warm);
 
 const char* absorber_last_error(void);
 

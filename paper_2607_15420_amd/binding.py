@@ -151,6 +151,8 @@ def lib():
             "absorber_warm_targets": (ctypes.c_int, [vp, vp, vp, vp]),
             "absorber_warm_point": (ctypes.c_int, [vp, vp, dbl, vp, vp]),
             "absorber_warm_start": (ctypes.c_int, [vp, vp, vp, vp, dbl, vp, vp]),
+            "absorber_warm_solve": (ctypes.c_int, [vp, vp, ctypes.POINTER(IpmOptions), dbl, vp, vp,
+                                                   ctypes.POINTER(IpmResult), ctypes.POINTER(ctypes.c_int32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -327,6 +329,15 @@ class Absorber:
     def warm_start(self, net: "Mlp", X_work, Y_work, x0, d_margin=1e-3, stream=None):
         _check(lib().absorber_warm_start(self.h, net.h, _ptr(X_work), _ptr(Y_work), float(d_margin), _ptr(x0),
                                          _stream(stream)))
+
+    def warm_solve(self, net: "Mlp", opts: IpmOptions | None = None, d_margin=1e-3, x_out=None, lam_out=None):
+        """Warm-started solve with cold fallback; returns (result, used_warm)."""
+        o = opts if opts is not None else self.default_options()
+        r = IpmResult()
+        used = ctypes.c_int32()
+        _check(lib().absorber_warm_solve(self.h, net.h, ctypes.byref(o), float(d_margin), _ptr(x_out), _ptr(lam_out),
+                                         ctypes.byref(r), ctypes.byref(used)))
+        return r, bool(used.value)
 
     @staticmethod
     def default_options(**kw) -> IpmOptions:

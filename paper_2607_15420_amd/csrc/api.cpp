@@ -163,7 +163,8 @@ static void free_handle(Handle& h) {
   if (h.ev0) (void)hipEventDestroy(h.ev0);
   if (h.ev1) (void)hipEventDestroy(h.ev1);
   void* ptrs[] = {h.feeds, h.gather, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
-                  h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.redbuf};
+                  h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.redbuf,
+                  h.warm_X, h.warm_Y, h.warm_x0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);

@@ -96,6 +96,9 @@ struct Handle {
   bool factored = false;
   double last_diag_d = 0;
   double x0[NV + 1];                         // cold-start stage vector and diameter
+  float* warm_X = nullptr;                   // warm-start workspaces (allocated on first use)
+  float* warm_Y = nullptr;
+  double* warm_x0 = nullptr;
   long long n_factor = 0, n_solve = 0;       // launch counters
   // optional per-class kernel timing (HIP events on the launch stream)
   int prof = 0;  // bit mask of the profiled kernel classes

@@ -14,6 +14,8 @@
 
 #include <math.h>
 
+#include <chrono>
+
 #include "internal.h"
 
 namespace absorber {
@@ -151,6 +153,37 @@ int absorber_warm_start(absorber_t* ah, absorber_mlp* net, float* X_work_dev, fl
   rc = absorber_warm_features(ah, X_work_dev, stream);
   if (!rc) rc = absorber_mlp_forward(net, X_work_dev, ah->h.S, Y_work_dev, stream);
   if (!rc) rc = absorber_warm_point(ah, Y_work_dev, d_margin, x0_dev, stream);
+  return rc;
+}
+
+int absorber_warm_solve(absorber_t* ah, absorber_mlp* net, const absorber_ipm_options* opts, double d_margin,
+                        double* x_out_dev, double* lambda_out_dev, absorber_ipm_result* result, int32_t* used_warm) {
+  if (!ah || !net || !opts || !result) {
+    set_error("absorber_warm_solve: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = ah->h;
+  if (!h.warm_X) {
+    HIP_TRY(hipMalloc((void**)&h.warm_X, sizeof(float) * 3 * (size_t)h.S));
+    HIP_TRY(hipMalloc((void**)&h.warm_Y, sizeof(float) * (size_t)NV * h.N * h.S));
+    HIP_TRY(hipMalloc((void**)&h.warm_x0, sizeof(double) * (size_t)h.nx));
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc = absorber_warm_start(ah, net, h.warm_X, h.warm_Y, d_margin, h.warm_x0, h.stream);
+  if (rc) return rc;
+  absorber_ipm_options ow = *opts;
+  ow.warm_start = 1;
+  rc = absorber_ipm_solve(ah, &ow, h.warm_x0, nullptr, x_out_dev, lambda_out_dev, result);
+  const bool ok = rc == ABS_OK && result->status == ABS_OK;
+  if (used_warm) *used_warm = ok ? 1 : 0;
+  if (!ok) {  // cold-start fallback
+    absorber_ipm_options oc = *opts;
+    oc.warm_start = 0;
+    const int it_warm = result->iterations;
+    rc = absorber_ipm_solve(ah, &oc, nullptr, nullptr, x_out_dev, lambda_out_dev, result);
+    result->iterations += it_warm;
+  }
+  result->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return rc;
 }
 

@@ -202,10 +202,14 @@ def test_warm_start_solve(params):
     xw = torch.empty(h.nx, dtype=torch.float64, device=DEV)
     rw = h.ipm_solve(Absorber.default_options(warm_start=1), x0=x0, x_out=xw)
     rc = h.ipm_solve(Absorber.default_options())
+    rs, used = h.warm_solve(net)  # library entry: warm start with cold fallback
     dstar, _, _, ok = simulate.closed_form_diameter(Fte, N, params)
     assert ok.all()
     assert rw.status == 0 and rw.E0 <= 1e-8, (rw.as_dict(), tr.final_loss)
     assert abs(rw.d - dstar) / dstar <= 1e-6
     assert rw.iterations < rc.iterations, (rw.iterations, rc.iterations)
+    assert used and rs.status == 0 and rs.iterations == rw.iterations
+    assert abs(rs.d - dstar) / dstar <= 1e-6
+    print(f"warm {rw.iterations} iterations, cold {rc.iterations}; train loss {tr.final_loss:.2e}")
     h.close()
     net.close()
