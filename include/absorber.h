@@ -157,6 +157,10 @@ typedef struct {
   double nlp_scaling_max_gradient; /* 100 */
   int32_t print_level;      /* 0 silent, 1 one line per iteration to stderr */
   int32_t use_graph;        /* reserved */
+  int32_t feasibility_restart; /* 1: a problem that stops without converging (line search, inertia,
+                                  iteration limit) is solved again from its simulated states
+                                  (absorber_simulate, d at 1.001 x its hydraulic minimum) with the
+                                  warm-start options; 0: report the failure (default 1) */
 } absorber_ipm_options;
 
 typedef struct {
@@ -169,9 +173,42 @@ typedef struct {
   int32_t n_inertia_corrections;
   int32_t n_factorizations;
   double max_lin_resid;     /* largest relative linear residual of the KKT solves */
+  int32_t feasibility_restarts; /* 1 if the result comes from the feasibility restart */
 } absorber_ipm_result;
 
 void absorber_ipm_default_options(absorber_ipm_options* opts);
+
+/* A batch of P independent problems in one handle (the batched form): problem
+ * p has n_stages[p] stages and n_scen[p] scenarios; feeds_host holds the
+ * scenarios of problem 0, then problem 1, ... ([sum n_scen][18]).  Layouts:
+ * the primal vector is the stage vectors of all problems' scenarios in that
+ * order ([sum N_p S_p][21]) followed by the P diameters d_0..d_{P-1}; the rows
+ * [sum N_p S_p][22].  absorber_batch_solve runs the interior-point method on
+ * all problems at once, each with its own barrier parameter, filter, step
+ * sizes and regularisation (one launch per kernel over all problems), and
+ * fills results[P].  Only absorber_batch_solve, absorber_eval_cons,
+ * absorber_initial_point, absorber_get_dims and the warm-start calls accept a
+ * batch handle; the other calls return ABS_ERR_ARG for P > 1. */
+int absorber_create_batch(const absorber_params* params, int32_t n_problems, const int32_t* n_stages,
+                          const int32_t* n_scen, const double* feeds_host, absorber_t** out);
+/* Blocking.  Returns ABS_OK when every problem converged, otherwise the status
+ * of the first problem that did not; x0/lambda0 as for absorber_ipm_solve. */
+int absorber_batch_solve(absorber_t* h, const absorber_ipm_options* opts, const double* x0_dev,
+                         const double* lambda0_dev, double* x_out_dev, double* lambda_out_dev,
+                         absorber_ipm_result* results);
+
+/* Process simulation: for fixed feeds each scenario's MESH equations are a
+ * square system in its stage states (the equilibrium model's degrees of
+ * freedom), solved here by Newton's method for every scenario of every
+ * problem at once (mole fractions stepped in their logarithm, log-steps capped
+ * at 5, backtracking on each scenario's scaled residual).  x_dev [nx]: start
+ * point in, states out; the d entries are set to each problem's hydraulic
+ * minimum max sqrt(4 V R T / (pi u_max P)).  Stops when every scenario's
+ * scaled MESH residual inf-norm is <= tol or after max_iter steps;
+ * converged_host [P] (may be NULL) flags the problems whose scenarios all
+ * converged.  Blocking; invalidates a factorisation from absorber_kkt_factor. */
+int absorber_simulate(absorber_t* h, double* x_dev, double tol, int32_t max_iter, int32_t* converged_host,
+                      int32_t* iterations_host);
 
 /* Run the interior-point method to E_0 <= tol.  x0_dev[nx] (original units) and
  * lambda0_dev[nc] may be NULL (cold start).  On return x_out_dev[nx] and

@@ -40,6 +40,11 @@ from . import model as M
 from .kkt import BorderedKKT, scenario_kkt
 
 SUCCESS, MAX_ITER, LS_FAIL, INERTIA_FAIL, NAN_IN_EVAL, DIVERGING = 0, -12, -11, -10, -13, -14
+# The backtracking stops below the minimum step of the filter line search
+# (Waechter & Biegler 2006, eq. 23); when the directional derivative is huge
+# that bound underflows, so a step below double-precision resolution relative
+# to a unit step also ends it.
+ALPHA_FLOOR = 2.0 ** -52
 
 
 @dataclass
@@ -418,7 +423,10 @@ class OracleIPM:
                 Emu, _, _, _ = self.opt_error(x, s, yc, yd, zL, zU, vU, Jb, cE, dI, mu)
                 if Emu > o.kappa_eps * mu:
                     break
-                mu = max(o.tol / 10.0, min(o.kappa_mu * mu, mu ** o.theta_mu))
+                mu_new = max(o.tol / 10.0, min(o.kappa_mu * mu, mu ** o.theta_mu))
+                if mu_new >= mu:  # already at its floor tol / 10: the update is done
+                    break
+                mu = mu_new
                 tau = max(o.tau_min, 1.0 - mu)
                 filt = []
             # A-4: search direction
@@ -503,7 +511,7 @@ class OracleIPM:
                 if accepted:
                     break
                 alpha *= 0.5
-                if alpha < amin:
+                if alpha < max(amin, ALPHA_FLOOR):
                     break
             if not accepted:
                 status = LS_FAIL

@@ -61,7 +61,7 @@ class IpmOptions(ctypes.Structure):
         ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("warm_start", ctypes.c_int32),
         ("mu_init", ctypes.c_double), ("warm_mu_init", ctypes.c_double), ("bound_push", ctypes.c_double),
         ("warm_bound_push", ctypes.c_double), ("nlp_scaling_max_gradient", ctypes.c_double),
-        ("print_level", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+        ("print_level", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("feasibility_restart", ctypes.c_int32),
     ]
 
 
@@ -71,6 +71,7 @@ class IpmResult(ctypes.Structure):
         ("inf_pr", ctypes.c_double), ("inf_du", ctypes.c_double), ("compl_", ctypes.c_double),
         ("d", ctypes.c_double), ("seconds", ctypes.c_double), ("n_inertia_corrections", ctypes.c_int32),
         ("n_factorizations", ctypes.c_int32), ("max_lin_resid", ctypes.c_double),
+        ("feasibility_restarts", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -114,6 +115,10 @@ def lib():
             "absorber_create": (ctypes.c_int, [ctypes.POINTER(AbsorberParams), i32, i32, c_double_p,
                                                ctypes.POINTER(vp)]),
             "absorber_destroy": (None, [vp]),
+            "absorber_create_batch": (ctypes.c_int, [ctypes.POINTER(AbsorberParams), i32, ctypes.POINTER(i32),
+                                                     ctypes.POINTER(i32), c_double_p, ctypes.POINTER(vp)]),
+            "absorber_batch_solve": (ctypes.c_int, [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp,
+                                                    ctypes.POINTER(IpmResult)]),
             "absorber_get_dims": (ctypes.c_int, [vp, ctypes.POINTER(Dims)]),
             "absorber_initial_point": (ctypes.c_int, [vp, vp, vp]),
             "absorber_set_scaling": (ctypes.c_int, [vp, c_double_p, vp]),
@@ -147,6 +152,7 @@ def lib():
             "absorber_mlp_adam_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(MlpTrainOptions), dbl, vp]),
             "absorber_mlp_train": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(MlpTrainOptions),
                                                   ctypes.POINTER(MlpTrainResult)]),
+            "absorber_simulate": (ctypes.c_int, [vp, vp, dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "absorber_warm_features": (ctypes.c_int, [vp, vp, vp]),
             "absorber_warm_targets": (ctypes.c_int, [vp, vp, vp, vp]),
             "absorber_warm_point": (ctypes.c_int, [vp, vp, dbl, vp, vp]),
@@ -217,7 +223,8 @@ def _stream(stream):
 
 
 class Absorber:
-    """Handle of one problem instance (S scenarios, N stages) on the current GPU."""
+    """Handle of one problem instance (S scenarios, N stages) on the current GPU,
+    or of a batch of independent problems (Absorber.batch)."""
 
     def __init__(self, params: dict, n_stages: int, feeds: np.ndarray):
         feeds = np.ascontiguousarray(feeds, dtype=np.float64)
@@ -228,11 +235,46 @@ class Absorber:
         _check(lib().absorber_create(ctypes.byref(self._p), int(n_stages), int(feeds.shape[0]),
                                      feeds.ctypes.data_as(c_double_p), ctypes.byref(h)))
         self.h = h
+        self.P = 1
         self.N, self.S = int(n_stages), int(feeds.shape[0])
+        self._sizes()
+
+    def _sizes(self):
         d = self.dims()
         self.nx = d["n_var_free"]
-        self.nc = self.N * self.S * 22
+        self.nc = d["n_eq"] + d["n_ineq"]
         self.nkkt = d["kkt_dim"]
+        self.nst = d["n_ineq"]
+
+    @classmethod
+    def batch(cls, params: dict, problems) -> "Absorber":
+        """Batch of independent problems; problems = [(n_stages, feeds (S_p, 18)), ...]."""
+        self = cls.__new__(cls)
+        Ns = np.array([int(n) for n, _ in problems], dtype=np.int32)
+        Ss = np.array([np.asarray(f).shape[0] for _, f in problems], dtype=np.int32)
+        feeds = np.ascontiguousarray(np.concatenate([np.asarray(f, dtype=np.float64) for _, f in problems]))
+        if feeds.ndim != 2 or feeds.shape[1] != 18:
+            raise ValueError("feeds must be (S_p, 18) per problem")
+        self._p = params_struct(params)
+        h = ctypes.c_void_p()
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        _check(lib().absorber_create_batch(ctypes.byref(self._p), len(problems), Ns.ctypes.data_as(i32p),
+                                           Ss.ctypes.data_as(i32p), feeds.ctypes.data_as(c_double_p),
+                                           ctypes.byref(h)))
+        self.h = h
+        self.P = len(problems)
+        self.N, self.S = int(Ns.max()), int(Ss.sum())
+        self.pN, self.pS = Ns, Ss
+        self._sizes()
+        return self
+
+    def batch_solve(self, opts: IpmOptions | None = None, x0=None, lam0=None, x_out=None, lam_out=None):
+        """Interior-point solve of every problem of the handle; returns (rc, [IpmResult] * P)."""
+        o = opts if opts is not None else self.default_options()
+        res = (IpmResult * self.P)()
+        rc = lib().absorber_batch_solve(self.h, ctypes.byref(o), _ptr(x0), _ptr(lam0), _ptr(x_out), _ptr(lam_out),
+                                        res)
+        return rc, list(res)
 
     def close(self):
         if getattr(self, "h", None):
@@ -313,6 +355,14 @@ class Absorber:
         rel = ctypes.c_double()
         _check(lib().absorber_kkt_solve(self.h, _ptr(rhs), _ptr(sol), ctypes.byref(rel), _stream(stream)))
         return rel.value
+
+    def simulate(self, x, tol=1e-10, max_iter=100):
+        """Process simulation of every scenario from x (in/out); returns (converged per problem, iterations)."""
+        conv = np.zeros(self.P, np.int32)
+        it = ctypes.c_int32()
+        _check(lib().absorber_simulate(self.h, _ptr(x), float(tol), int(max_iter),
+                                       conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(it)))
+        return conv.astype(bool), it.value
 
     def warm_features(self, X, stream=None):
         """X: float32 (S, 3) device tensor <- (gas flow, CO2 fraction, gas temperature) per scenario."""

@@ -135,9 +135,9 @@ static int build_tables(Handle& h) {
 
 int initial_point(Handle& h, double* x_dev, hipStream_t st) {
   std::vector<double> x0((size_t)h.nx);
-  for (long long t = 0; t < (long long)h.N * h.S; ++t)
+  for (long long t = 0; t < h.nst; ++t)
     for (int k = 0; k < NV; ++k) x0[t * NV + k] = h.x0[k];
-  x0[h.nx - 1] = h.x0[NV];
+  for (int p = 0; p < h.P; ++p) x0[h.nst * NV + p] = h.x0[NV];
   HIP_TRY(hipMemcpyAsync(x_dev, x0.data(), sizeof(double) * h.nx, hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   return ABS_OK;
@@ -163,8 +163,9 @@ static void free_handle(Handle& h) {
   if (h.ev0) (void)hipEventDestroy(h.ev0);
   if (h.ev1) (void)hipEventDestroy(h.ev1);
   void* ptrs[] = {h.feeds, h.gather, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
-                  h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.redbuf,
-                  h.warm_X, h.warm_Y, h.warm_x0};
+                  h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
+                  h.warm_X, h.warm_Y, h.warm_x0, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
+                  h.seg, h.pseg, h.dwv, h.dcv, h.fmask};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);
@@ -186,21 +187,39 @@ extern "C" {
 
 const char* absorber_last_error(void) { return g_last_error.c_str(); }
 
-int absorber_create(const absorber_params* prm, int32_t n_stages, int32_t n_scen, const double* feeds_host,
-                    absorber_t** out) {
-  if (!prm || !feeds_host || !out || n_stages < 1 || n_scen < 1 || n_stages > 4096) {
-    set_error("absorber_create: bad argument");
+int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const int32_t* n_stages,
+                          const int32_t* n_scen, const double* feeds_host, absorber_t** out) {
+  if (!prm || !feeds_host || !out || !n_stages || !n_scen || n_problems < 1) {
+    set_error("absorber_create_batch: bad argument");
+    return ABS_ERR_ARG;
+  }
+  long long nst = 0, W = 0;
+  int Nmax = 0;
+  for (int p = 0; p < n_problems; ++p) {
+    if (n_stages[p] < 1 || n_stages[p] > 4096 || n_scen[p] < 1) {
+      set_error("absorber_create_batch: stage counts must be 1..4096 and scenario counts >= 1");
+      return ABS_ERR_ARG;
+    }
+    nst += (long long)n_stages[p] * n_scen[p];
+    W += n_scen[p];
+    Nmax = std::max(Nmax, (int)n_stages[p]);
+  }
+  if (W > 2147483647LL / 4 || nst > 2147483647LL) {
+    set_error("absorber_create_batch: too many stages");
     return ABS_ERR_ARG;
   }
   auto* H = new (std::nothrow) absorber_handle();
   if (!H) return ABS_ERR_OOM;
   Handle& h = H->h;
-  h.N = n_stages;
-  h.S = n_scen;
-  const long long nst = (long long)h.N * h.S;
-  h.nx = nst * NV + 1;
+  h.P = n_problems;
+  h.N = Nmax;
+  h.S = (int)W;
+  h.nst = nst;
+  h.pN.assign(n_stages, n_stages + n_problems);
+  h.pS.assign(n_scen, n_scen + n_problems);
+  h.nx = nst * NV + h.P;
   h.nc = nst * NR;
-  h.nkkt = nst * NK + 1;
+  h.nkkt = nst * NK + h.P;
   ModelParams& mp = h.mp;
   memcpy(mp.nu, prm->nu, sizeof(mp.nu));
   for (int k = 0; k < 5; ++k) {
@@ -251,6 +270,35 @@ int absorber_create(const absorber_params* prm, int32_t n_stages, int32_t n_scen
   for (int k = 0; k < NV; ++k) h.sc.D[k] = 1.0;
   h.sc.Dd = 1.0;
   h.feeds_h.assign(feeds_host, feeds_host + (size_t)h.S * NF);
+  // chain, stage and segment tables
+  std::vector<StageInfo> sinfo((size_t)nst);
+  std::vector<int> chain0((size_t)W + 1), chain_p((size_t)W), pchain((size_t)h.P + 1), pseg((size_t)h.P + 1);
+  std::vector<long long> pstage((size_t)h.P + 1);
+  std::vector<Seg> segs;
+  {
+    long long t = 0;
+    int w = 0;
+    for (int p = 0; p < h.P; ++p) {
+      pchain[p] = w;
+      pstage[p] = t;
+      pseg[p] = (int)segs.size();
+      const long long ts = t;
+      for (int q = 0; q < h.pS[p]; ++q, ++w) {
+        chain0[w] = (int)t;
+        chain_p[w] = p;
+        for (int n = 0; n < h.pN[p]; ++n, ++t) sinfo[(size_t)t] = StageInfo{w, n, h.pN[p], p};
+      }
+      for (long long a = ts; a < t; a += SEG) segs.push_back(Seg{(int)a, (int)std::min(t, a + SEG), p, a == ts});
+    }
+    chain0[W] = (int)t;
+    pchain[h.P] = w;
+    pstage[h.P] = t;
+    pseg[h.P] = (int)segs.size();
+  }
+  h.nseg = (int)segs.size();
+  h.pchain_h.assign(pchain.begin(), pchain.end());
+  h.pstage_h = pstage;
+  h.pseg_h = pseg;
   static_assert(sizeof(absorber_params) > 0, "");
   for (int k = 0; k < NV; ++k) h.x0[k] = prm->x0[k];
   h.x0[NV] = prm->d0;
@@ -275,27 +323,58 @@ int absorber_create(const absorber_params* prm, int32_t n_stages, int32_t n_scen
   ALLOC(h.solb, nst * NK);
   ALLOC(h.inert, (size_t)h.S * 4);
   ALLOC(h.part, (size_t)h.S * 4);
-  ALLOC(h.scal, 1);
+  ALLOC(h.scal, h.P);
+  ALLOC(h.sinfo, nst);
+  ALLOC(h.chain0, W + 1);
+  ALLOC(h.chain_p, W);
+  ALLOC(h.pchain, h.P + 1);
+  ALLOC(h.pstage, h.P + 1);
+  ALLOC(h.seg, h.nseg);
+  ALLOC(h.pseg, h.P + 1);
+  ALLOC(h.dwv, h.P);
+  ALLOC(h.dcv, h.P);
+  ALLOC(h.fmask, h.P);
+  ALLOC(h.omega_d, 8);
   ALLOC(h.diagx, h.nx);
   ALLOC(h.diags, nst);
   ALLOC(h.kres, h.nkkt);
   ALLOC(h.kcor, h.nkkt);
-  ALLOC(h.kden, 3 * nst + 8);
-  h.red_cap = (int)std::max<long long>(64 * 1024, 9 * ((std::max<long long>(h.nx, std::max(h.nc, h.nkkt)) + 255) / 256) + 64);
+  ALLOC(h.kden, 3 * nst + h.P + 64);
+  h.red_cap = (int)std::max<long long>(
+      64 * 1024, std::max<long long>(9 * ((std::max<long long>(h.nx, std::max(h.nc, h.nkkt)) + 255) / 256),
+                                     9LL * (h.nseg + h.P)) + 64);
   ALLOC(h.redbuf, h.red_cap);
 #undef ALLOC
-  if (hipHostMalloc((void**)&h.scal_h, sizeof(DevScalars), 0) != hipSuccess ||
+  if (hipHostMalloc((void**)&h.scal_h, sizeof(DevScalars) * h.P, 0) != hipSuccess ||
       hipHostMalloc((void**)&h.redbuf_h, sizeof(double) * h.red_cap, 0) != hipSuccess) {
     set_error("absorber_create: pinned host allocation failed");
     return fail(ABS_ERR_OOM);
   }
-  if (hipMemcpy(h.feeds, feeds_host, sizeof(double) * (size_t)h.S * NF, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpy(h.feeds, feeds_host, sizeof(double) * (size_t)h.S * NF, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.sinfo, sinfo.data(), sizeof(StageInfo) * sinfo.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.chain0, chain0.data(), sizeof(int) * chain0.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.chain_p, chain_p.data(), sizeof(int) * chain_p.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.pchain, pchain.data(), sizeof(int) * pchain.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.pstage, pstage.data(), sizeof(long long) * pstage.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.seg, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h.pseg, pseg.data(), sizeof(int) * pseg.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h.dwv, 0, sizeof(double) * h.P) != hipSuccess ||
+      hipMemset(h.dcv, 0, sizeof(double) * h.P) != hipSuccess)
     return fail(ABS_ERR_HIP);
   if ((rc = build_tables(h)) != ABS_OK) return fail(rc);
   if ((rc = reset_row_scale(h)) != ABS_OK) return fail(rc);
   if (hipMemset(h.rec, 0, sizeof(double) * nst * REC) != hipSuccess) return fail(ABS_ERR_HIP);
   *out = H;
   return ABS_OK;
+}
+
+int absorber_create(const absorber_params* prm, int32_t n_stages, int32_t n_scen, const double* feeds_host,
+                    absorber_t** out) {
+  if (!prm || !feeds_host || !out || n_stages < 1 || n_scen < 1 || n_stages > 4096) {
+    set_error("absorber_create: bad argument");
+    return ABS_ERR_ARG;
+  }
+  return absorber_create_batch(prm, 1, &n_stages, &n_scen, feeds_host, out);
 }
 
 void absorber_destroy(absorber_t* H) {
@@ -310,15 +389,18 @@ int absorber_get_dims(const absorber_t* H, absorber_dims* out) {
     return ABS_ERR_ARG;
   }
   const Handle& h = H->h;
-  const long long nst = (long long)h.N * h.S;
-  out->n_var_total = 30 * nst + 1;
-  out->n_var_free = 21 * nst + 1;
+  const long long nst = h.nst;
+  out->n_var_total = 30 * nst + h.P;
+  out->n_var_free = 21 * nst + h.P;
   out->n_eq = 21 * nst;
   out->n_fixed = 9 * nst;
   out->n_ineq = nst;
-  out->nnz_jac = (long long)h.S * ((long long)h.N * NJO + (long long)(h.N - 1) * (NJU + NJD));
-  out->nnz_hess = nst * NH + 1;
-  out->kkt_dim = nst * NK + 1;
+  long long nnz = 0;
+  for (int p = 0; p < h.P; ++p)
+    nnz += (long long)h.pS[p] * ((long long)h.pN[p] * NJO + (long long)(h.pN[p] - 1) * (NJU + NJD));
+  out->nnz_jac = nnz;
+  out->nnz_hess = nst * NH + h.P;
+  out->kkt_dim = nst * NK + h.P;
   return ABS_OK;
 }
 
@@ -358,13 +440,17 @@ int absorber_profile_get(const absorber_t* H, absorber_profile* out) {
     out->ms[k] = h.prof_ms[k];
     out->calls[k] = h.prof_calls[k];
   }
-  out->bytes_factor_slots = (int64_t)h.N * h.S * NK * SLOT * (int64_t)sizeof(double);
+  out->bytes_factor_slots = (int64_t)h.nst * NK * SLOT * (int64_t)sizeof(double);
   return ABS_OK;
 }
 
 int absorber_set_scaling(absorber_t* H, const double* var_scale_host, const double* row_scale_dev) {
   if (!H) {
     set_error("absorber_set_scaling: bad argument");
+    return ABS_ERR_ARG;
+  }
+  if (H->h.P != 1) {
+    set_error("absorber_set_scaling: single-problem handles only (use absorber_batch_solve for a batch)");
     return ABS_ERR_ARG;
   }
   Handle& h = H->h;
@@ -396,6 +482,10 @@ int absorber_eval_obj(absorber_t* H, const double* x_dev, double* f_host, double
     set_error("absorber_eval_obj: bad argument");
     return ABS_ERR_ARG;
   }
+  if (H->h.P != 1) {
+    set_error("absorber_eval_obj: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
   Handle& h = H->h;
   hipStream_t st = (hipStream_t)stream;
   if (f_host) {
@@ -415,10 +505,14 @@ int absorber_jac_structure(const absorber_t* H, int64_t* rows, int64_t* cols) {
     set_error("absorber_jac_structure: bad argument");
     return ABS_ERR_ARG;
   }
+  if (H->h.P != 1) {
+    set_error("absorber_jac_structure: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
   const Handle& h = H->h;
   long long k = 0;
   const long long dcol = h.nx - 1;
-  for (int w = 0; w < h.S; ++w)
+  for (int w = 0; w < h.S; ++w)  // single problem: chain w holds stages w N .. w N + N - 1
     for (int n = 0; n < h.N; ++n) {
       const long long t = (long long)w * h.N + n;
       for (auto& e : h.jac_own) {
@@ -447,6 +541,10 @@ int absorber_eval_jac(absorber_t* H, const double* x_dev, double* vals_dev, void
     set_error("absorber_eval_jac: bad argument");
     return ABS_ERR_ARG;
   }
+  if (H->h.P != 1) {
+    set_error("absorber_eval_jac: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
   HIP_TRY(launch_jac_coo(H->h, x_dev, vals_dev, (hipStream_t)stream));
   return ABS_OK;
 }
@@ -456,9 +554,13 @@ int absorber_hess_structure(const absorber_t* H, int64_t* rows, int64_t* cols) {
     set_error("absorber_hess_structure: bad argument");
     return ABS_ERR_ARG;
   }
+  if (H->h.P != 1) {
+    set_error("absorber_hess_structure: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
   const Handle& h = H->h;
   long long k = 0;
-  for (long long t = 0; t < (long long)h.N * h.S; ++t)
+  for (long long t = 0; t < h.nst; ++t)
     for (int e = 0; e < NH; ++e) {
       rows[k] = t * NV + h.hpos[e].r;
       cols[k] = t * NV + h.hpos[e].c;
@@ -475,6 +577,10 @@ int absorber_eval_hess(absorber_t* H, const double* x_dev, const double* lambda_
     set_error("absorber_eval_hess: bad argument");
     return ABS_ERR_ARG;
   }
+  if (H->h.P != 1) {
+    set_error("absorber_eval_hess: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
   HIP_TRY(launch_hess_coo(H->h, x_dev, lambda_dev, vals_dev, (hipStream_t)stream));
   return ABS_OK;
 }
@@ -486,14 +592,20 @@ int absorber_kkt_factor(absorber_t* H, const double* x_dev, const double* lambda
     set_error("absorber_kkt_factor: bad argument");
     return ABS_ERR_ARG;
   }
+  if (H->h.P != 1) {
+    set_error("absorber_kkt_factor: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
   Handle& h = H->h;
   hipStream_t st = (hipStream_t)stream;
   // the record is evaluated at x in original units with the handle's scaling
   HIP_TRY(launch_eval(h, x_dev, 0, lambda_dev, 1, h.kres, st));
   HIP_TRY(hipMemcpyAsync(h.diagx, sigma_x_dev, sizeof(double) * h.nx, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(hipMemcpyAsync(h.diags, sigma_s_dev, sizeof(double) * (h.nx - 1) / NV, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(launch_factor(h, h.diagx, h.diags, delta_w, delta_c, nullptr, st));
-  HIP_TRY(launch_schur(h, h.diagx + (h.nx - 1), delta_w, nullptr, 0, nullptr, st));
+  HIP_TRY(hipMemcpyAsync(h.diags, sigma_s_dev, sizeof(double) * h.nst, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h.dwv, &delta_w, sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h.dcv, &delta_c, sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_factor(h, h.diagx, h.diags, nullptr, false, st));
+  HIP_TRY(launch_schur(h, h.diagx, nullptr, 0, nullptr, st));
   HIP_TRY(hipMemcpyAsync(h.scal_h, h.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (inertia_host) {

@@ -46,7 +46,23 @@ __host__ __device__ constexpr int coupling_index(int a) {
 
 struct JacEntry { int8_t row, blk, col; };
 
-// scalars produced by the Schur/inertia reduction
+// A handle holds P independent problems (P = 1 for absorber_create).  Their
+// scenarios ("chains" of stages) are stored problem after problem, each chain's
+// stages contiguous and bottom to top; the primal vector is [21 entries per
+// stage; d of problem 0..P-1], the rows [22 per stage], the KKT unknowns
+// [43 per stage; d of problem 0..P-1].
+struct StageInfo {
+  int w, n, N, p;  // chain, stage within the chain, chain length, problem
+};
+// IPM work unit: at most SEG consecutive stages of one problem, so that one
+// 256-thread block covers their primal (21 SEG), row (22 SEG) and stage entries
+// and the block's partial reductions belong to a single problem
+constexpr int SEG = 11;
+struct Seg {
+  int t0, t1, p, first;  // stage range, problem, 1 for the problem's first segment (it also owns d)
+};
+
+// scalars produced by the Schur/inertia reduction (one per problem)
 struct DevScalars {
   double sd, kdd, sig_b, sig_r, dd, rd, wdd, pad0;
   long long npos, nneg, nzero, pad1;
@@ -60,8 +76,25 @@ struct Scaling {
 
 // all per-handle device and host state
 struct Handle {
-  int N = 0, S = 0;
-  long long nx = 0, nc = 0, nkkt = 0;       // primal incl. d, rows, KKT unknowns incl. d
+  int P = 1;                                 // independent problems
+  int N = 0, S = 0;                          // P == 1: stages and scenarios; otherwise the largest
+                                             // stage count and the number of chains
+  long long nst = 0;                         // stages of all problems
+  long long nx = 0, nc = 0, nkkt = 0;       // primal incl. the d's, rows, KKT unknowns incl. the d's
+  std::vector<int> pN, pS;                   // per problem: stages, scenarios
+  std::vector<long long> pstage_h, pchain_h; // [P+1] first stage / first chain of each problem
+  std::vector<int> pseg_h;                   // [P+1] first segment of each problem
+  StageInfo* sinfo = nullptr;                // device [nst]
+  int* chain0 = nullptr;                     // device [chains+1] first stage of each chain
+  int* chain_p = nullptr;                    // device [chains] problem of each chain
+  int* pchain = nullptr;                     // device [P+1]
+  long long* pstage = nullptr;               // device [P+1]
+  Seg* seg = nullptr;                        // device [nseg]
+  int* pseg = nullptr;                       // device [P+1]
+  int nseg = 0;
+  double* dwv = nullptr;                     // device [P] delta_w of the stored factorisation
+  double* dcv = nullptr;                     // device [P] delta_c
+  int* fmask = nullptr;                      // device [P] problems to (re)factorise (null: all)
   ModelParams mp{};
   double xL[NV], xU[NV], dL = 0, dU = 0;     // unscaled bounds per local variable
   std::vector<double> feeds_h;
@@ -79,20 +112,20 @@ struct Handle {
   double* slots = nullptr;                   // [S][N][NK][SLOT] stored pivot columns
   double* solr = nullptr;                    // [S][N][NK] K_w^{-1} r
   double* solb = nullptr;                    // [S][N][NK] K_w^{-1} b
-  int* inert = nullptr;                      // [S][4]
-  double* part = nullptr;                    // [S][4] per-scenario partial sums
-  DevScalars* scal = nullptr;                // device scalars
-  DevScalars* scal_h = nullptr;              // pinned host mirror
+  int* inert = nullptr;                      // [chains][4]
+  double* part = nullptr;                    // [chains][4] per-chain partial sums
+  DevScalars* scal = nullptr;                // device scalars [P]
+  DevScalars* scal_h = nullptr;              // pinned host mirror [P]
   double* diagx = nullptr;                   // [nx] Sigma_x for the KKT (scaled)
   double* diags = nullptr;                   // [S][N] Sigma_s
   double* kres = nullptr;                    // [nkkt] refinement residual
   double* kcor = nullptr;                    // [nkkt] refinement correction
-  double* kden = nullptr;                    // [S][N] per-stage backward-error partials
+  double* kden = nullptr;                    // residual partials: 2 per stage, block maxima, per-problem d rows
+  double* omega_d = nullptr;                 // [2] backward errors of the last residual
   double* redbuf = nullptr;                  // device reduction partials
   double* redbuf_h = nullptr;                // pinned host mirror
   int red_cap = 0;
   hipStream_t stream = nullptr;
-  double fdw = 0, fdc = 0;                   // regularisation of the stored factorisation
   bool factored = false;
   double last_diag_d = 0;
   double x0[NV + 1];                         // cold-start stage vector and diameter
@@ -132,27 +165,37 @@ hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling
                            const double* y, int full, double* c_out, hipStream_t st);
 // solve with the stored factors, Schur combine and iterative refinement
 int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st);
+// res[P]; active0 (host [P], may be null): only these problems iterate and
+// are written to xout/yout/res
 int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0, const double* y0, double* xout,
-              double* yout, absorber_ipm_result* res);
+              double* yout, absorber_ipm_result* res, const unsigned char* active0 = nullptr);
+int solve_with_restart(Handle& h, const absorber_ipm_options& o, const double* x0, const double* y0, double* xout,
+                       double* yout, absorber_ipm_result* res);
+// process simulation (damped Newton on every scenario's MESH block) of the
+// problems in pmask (host [P], null: all) from x (unscaled, in/out)
+int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, int max_iter, int* conv, int* iters);
+// d_p = (1 + margin) * the largest hydraulic diameter of problem p's stages in x
+int set_hydraulic_diameters(Handle& h, double* x_dev, double margin, hipStream_t st);
 hipError_t launch_rowmax(Handle& h, const double* x, int scaled, double* rowmax, hipStream_t st);
 hipError_t launch_jac_coo(Handle& h, const double* x, double* vals, hipStream_t st);
 hipError_t launch_hess_coo(Handle& h, const double* x, const double* lam, double* vals, hipStream_t st);
-// factorise every scenario block from the records; solve for rhs (may be null) and b
-hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, double dw, double dc,
-                         const double* rhs, hipStream_t st);
+// factorise every scenario block from the records with the per-problem
+// regularisation h.dwv/h.dcv (chains of problems whose h.fmask entry is 0 are
+// skipped when mask is true); solve for rhs (may be null) and b
+hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
+                         hipStream_t st);
 // forward/backward with the stored factors: solr <- K_w^{-1} rhs
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st);
-// Schur complement on d.  diagd: device pointer to Sigma_d; rd: device pointer to
-// the d entry of the right-hand side.  mode 0: after launch_factor without a
-// right-hand side (S_d, inertia); 1: after launch_factor with one; 2: after
-// launch_solve.  For modes 1 and 2, sol (if not null) receives the combined
-// solution of the bordered system.
-hipError_t launch_schur(Handle& h, const double* diagd, double dw, const double* rd, int mode, double* sol,
-                        hipStream_t st);
-// residual res = rhs - K sol of the bordered system; omega_out[0] = max
-// componentwise backward error over the scenario rows, omega_out[1] that of the d row
-hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, double dw, double dc,
-                           const double* sol, const double* rhs, double* res, double* omega_out, hipStream_t st);
+// Schur complement on each problem's d.  diagx: Sigma_x (its d entries are
+// Sigma_d); rhs: the right-hand side (its d entries are r_d; may be null in
+// mode 0).  mode 0: after launch_factor without a right-hand side (S_d,
+// inertia); 1: after launch_factor with one; 2: after launch_solve.  For modes
+// 1 and 2, sol (if not null) receives the combined solution of the bordered system.
+hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st);
+// residual res = rhs - K sol of the bordered systems; omega_out[0] = max
+// componentwise backward error over the scenario rows, omega_out[1] over the d rows
+hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
+                           const double* rhs, double* res, double* omega_out, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st);
 
 }  // namespace absorber

@@ -1,8 +1,18 @@
 // Filter line-search primal-dual interior-point method (the algorithm MadNLP
-// implements, Waechter & Biegler 2006) for problem (10), driven from the host
-// with every vector operation, reduction, evaluation and linear solve on the
-// device.  Host work is scalar control flow: barrier update, inertia
-// correction, filter and step acceptance.
+// implements, Waechter & Biegler 2006) for problem (10), run in lockstep over
+// the P independent problems a handle holds (P = 1 for a single problem).
+// Every vector operation, reduction, evaluation and linear solve is one launch
+// over all problems; each problem keeps its own barrier parameter, filter,
+// step sizes, regularisation and convergence state.  Those scalars live on the
+// host, which runs the per-problem control flow (barrier update, inertia
+// correction, filter and step acceptance), and reach the kernels through a
+// small per-problem array on the device.
+//
+// Work units: element-wise kernels run over segments, at most SEG consecutive
+// stages of one problem per 256-thread block (the block covers their primal,
+// row and stage entries, and the problem's first segment also its d), so each
+// block's partial reductions belong to one problem; a second launch reduces
+// the partials of every problem in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -20,18 +30,30 @@ namespace absorber {
 namespace {
 
 constexpr int BS = 256;
+static_assert(NR * SEG < BS, "a segment's rows and the d entry must fit one block");
 inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// per-problem scalars read by the kernels
+struct PS {
+  double mu, tau, alpha, alpha_z;
+  int active;  // still iterating
+  int search;  // in the line search: the trial point is (re)written
+  int accept;  // the trial point is accepted in this iteration
+  int zero_y;  // drop the least-squares multiplier estimate
+  int write;   // write this problem's final iterate to the caller's vectors
+  int pad;
+};
 
 // scaled bounds per stage-local index (0-20) and d (21)
 struct Bnd {
   double lo[NV + 1], hi[NV + 1];
 };
 
-__device__ __forceinline__ int lidx(long long i, long long nx) { return i == nx - 1 ? NV : (int)(i % NV); }
+__device__ __forceinline__ int lidx(long long i, long long nxs) { return i >= nxs ? NV : (int)(i % NV); }
 
 // primal index -> KKT index
-__device__ __forceinline__ long long kkt_of_primal(long long i, long long nx, long long nkkt) {
-  return i == nx - 1 ? nkkt - 1 : (i / NV) * NK + (i % NV);
+__device__ __forceinline__ long long kkt_of_primal(long long i, long long nxs, long long nks) {
+  return i >= nxs ? nks + (i - nxs) : (i / NV) * NK + (i % NV);
 }
 // row index -> KKT index
 __device__ __forceinline__ long long kkt_of_row(long long j) {
@@ -44,32 +66,76 @@ template <int K>
 struct Part {
   double v[K];
 };
-
-// block reduction of K values: op 0 sum, 1 max, 2 min; per-block partials
 template <int K>
-__device__ void block_reduce(Part<K> p, const int* ops, double* out) {
+struct Ops {
+  int op[K];  // 0 sum, 1 max, 2 min
+};
+
+__device__ __forceinline__ double red_op(int op, double a, double b) {
+  return op == 0 ? a + b : (op == 1 ? fmax(a, b) : fmin(a, b));
+}
+
+// block reduction of K values; per-block partials out[blockIdx.x * K + k]
+template <int K>
+__device__ void block_reduce(Part<K> p, const Ops<K>& ops, double* out) {
   __shared__ double sm[K][BS];
   for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = p.v[k];
   __syncthreads();
   for (int s = BS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
-      for (int k = 0; k < K; ++k) {
-        const double a = sm[k][threadIdx.x], b = sm[k][threadIdx.x + s];
-        sm[k][threadIdx.x] = ops[k] == 0 ? a + b : (ops[k] == 1 ? fmax(a, b) : fmin(a, b));
-      }
+      for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = red_op(ops.op[k], sm[k][threadIdx.x], sm[k][threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0)
     for (int k = 0; k < K; ++k) out[blockIdx.x * K + k] = sm[k][0];
 }
 
-// ---- Lagrangian gradient g = grad f~ + J~^T y for the stage primals; d part in dpart
+// per-problem reduction of segment partials (one block per problem, fixed order)
+template <int K>
+__global__ void k_seg_reduce(const double* __restrict__ parts, const int* __restrict__ pseg, Ops<K> ops,
+                             double* __restrict__ out) {
+  const int p = blockIdx.x;
+  Part<K> acc;
+  for (int k = 0; k < K; ++k) acc.v[k] = ops.op[k] == 0 ? 0.0 : (ops.op[k] == 1 ? -INFINITY : INFINITY);
+  for (int b = pseg[p] + threadIdx.x; b < pseg[p + 1]; b += BS)
+    for (int k = 0; k < K; ++k) acc.v[k] = red_op(ops.op[k], acc.v[k], parts[(long long)b * K + k]);
+  block_reduce<K>(acc, ops, out);
+}
+
+// the entries of one segment: thread tid owns primal entry NV t0 + tid (tid <
+// NV ns), row entry NR t0 + tid (tid < NR ns), stage t0 + tid (tid < ns), and
+// the last thread of the problem's first segment owns d
+struct SegView {
+  long long t0;
+  int ns, p, tid;
+  bool owns_d;
+  __device__ SegView(const Seg* seg) {
+    const Seg s = seg[blockIdx.x];
+    t0 = s.t0;
+    ns = s.t1 - s.t0;
+    p = s.p;
+    tid = threadIdx.x;
+    owns_d = s.first && tid == BS - 1;
+  }
+  // primal entry of this thread (or -1)
+  __device__ long long xi(long long nxs) const {
+    if (tid < NV * ns) return NV * t0 + tid;
+    if (owns_d) return nxs + p;
+    return -1;
+  }
+  __device__ long long ci() const { return tid < NR * ns ? NR * t0 + tid : -1; }
+  __device__ long long ti() const { return tid < ns ? t0 + tid : -1; }
+};
+
+// ---- Lagrangian gradient g = grad f~ + J~^T y for the stage primals; the
+// stage's contribution to the d entry in dpart
 __global__ void k_lag_grad(const double* __restrict__ rec, const int* __restrict__ jtab,
-                           const double* __restrict__ y, int N, int S, double* __restrict__ g,
-                           double* __restrict__ dpart) {
+                           const double* __restrict__ y, const StageInfo* __restrict__ sinfo, long long nst,
+                           double* __restrict__ g, double* __restrict__ dpart) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)N * S) return;
-  const int n = (int)(t % N);
+  if (t >= nst) return;
+  const StageInfo si = sinfo[t];
+  const int n = si.n, N = si.N;
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -103,35 +169,39 @@ __global__ void k_lag_grad(const double* __restrict__ rec, const int* __restrict
   dpart[t] = dp;
 }
 
-// g_d = sf * D_d + sum over all hydraulic rows (one block, fixed order)
-__global__ void k_grad_d(const double* __restrict__ dpart, long long nst, double gf, double* __restrict__ gd) {
+// g_d = sf * D_d + the problem's hydraulic-row terms (one block per problem, fixed order)
+__global__ void k_grad_d(const double* __restrict__ dpart, const long long* __restrict__ pstage, double gf,
+                         long long nxs, double* __restrict__ g) {
   __shared__ double sm[BS];
+  const int p = blockIdx.x;
   double a = 0.0;
-  for (long long t = threadIdx.x; t < nst; t += BS) a += dpart[t];
+  for (long long t = pstage[p] + threadIdx.x; t < pstage[p + 1]; t += BS) a += dpart[t];
   sm[threadIdx.x] = a;
   __syncthreads();
   for (int s = BS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *gd = gf + sm[0];
+  if (threadIdx.x == 0) g[nxs + p] = gf + sm[0];
 }
 
-// ---- optimality-error partials
+// ---- optimality-error partials per segment
 // 0 max|g - zL + zU|, 1 max|vU - y_hyd|, 2 max|cE|, 3 max|c_hyd - s|, 4 min compl product,
 // 5 max compl product, 6 sum|y|, 7 sum|z| (zL, zU, vU), 8 nonfinite count
-__global__ void k_opt_parts(const double* __restrict__ x, const double* __restrict__ zL, const double* __restrict__ zU,
+__global__ void k_opt_parts(const Seg* __restrict__ seg, const double* __restrict__ x,
+                            const double* __restrict__ zL, const double* __restrict__ zU,
                             const double* __restrict__ g, const double* __restrict__ y, const double* __restrict__ c,
-                            const double* __restrict__ s, const double* __restrict__ vU, Bnd b, long long nx,
-                            long long nc, long long nst, double* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+                            const double* __restrict__ s, const double* __restrict__ vU, Bnd b, long long nxs,
+                            double* __restrict__ out) {
+  const SegView V(seg);
   Part<9> p;
   p.v[0] = p.v[1] = p.v[2] = p.v[3] = 0.0;
   p.v[4] = INFINITY;
   p.v[5] = -INFINITY;
   p.v[6] = p.v[7] = p.v[8] = 0.0;
-  if (i < nx) {
-    const int k = lidx(i, nx);
+  const long long i = V.xi(nxs);
+  if (i >= 0) {
+    const int k = lidx(i, nxs);
     const double gi = g[i] - zL[i] + zU[i];
     p.v[0] = fabs(gi);
     if (!isfinite(gi)) p.v[8] += 1.0;
@@ -148,31 +218,32 @@ __global__ void k_opt_parts(const double* __restrict__ x, const double* __restri
       p.v[7] += fabs(zU[i]);
     }
   }
-  if (i < nc) {
-    const double cj = c[i];
+  const long long j = V.ci();
+  if (j >= 0) {
+    const double cj = c[j];
     if (!isfinite(cj)) p.v[8] += 1.0;
-    p.v[6] += fabs(y[i]);
-    if (i % NR != NR - 1) p.v[2] = fabs(cj);
+    p.v[6] += fabs(y[j]);
+    if (j % NR != NR - 1) p.v[2] = fabs(cj);
   }
-  if (i < nst) {
-    p.v[1] = fabs(vU[i] - y[i * NR + NR - 1]);
-    p.v[3] = fabs(c[i * NR + NR - 1] - s[i]);
-    const double pr = -s[i] * vU[i];
+  const long long t = V.ti();
+  if (t >= 0) {
+    p.v[1] = fabs(vU[t] - y[t * NR + NR - 1]);
+    p.v[3] = fabs(c[t * NR + NR - 1] - s[t]);
+    const double pr = -s[t] * vU[t];
     p.v[4] = fmin(p.v[4], pr);
     p.v[5] = fmax(p.v[5], pr);
-    p.v[7] += fabs(vU[i]);
+    p.v[7] += fabs(vU[t]);
   }
-  const int ops[9] = {1, 1, 1, 1, 2, 1, 0, 0, 0};
-  block_reduce<9>(p, ops, out);
+  block_reduce<9>(p, Ops<9>{{1, 1, 1, 1, 2, 1, 0, 0, 0}}, out);
 }
 
 // ---- barrier diagonals
 __global__ void k_sigma(const double* __restrict__ x, const double* __restrict__ zL, const double* __restrict__ zU,
                         const double* __restrict__ s, const double* __restrict__ vU, Bnd b, long long nx,
-                        long long nst, double* __restrict__ dx, double* __restrict__ ds) {
+                        long long nxs, long long nst, double* __restrict__ dx, double* __restrict__ ds) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
   if (i < nx) {
-    const int k = lidx(i, nx);
+    const int k = lidx(i, nxs);
     double sg = 0.0;
     if (isfinite(b.lo[k])) sg += zL[i] / (x[i] - b.lo[k]);
     if (isfinite(b.hi[k])) sg += zU[i] / (b.hi[k] - x[i]);
@@ -192,45 +263,54 @@ __device__ __forceinline__ double barrier_grad(double xi, int k, const Bnd& b, d
   return v;
 }
 
-// ---- right-hand side of the slack-reduced primal-dual system
-__global__ void k_rhs(const double* __restrict__ x, const double* __restrict__ g, const double* __restrict__ y,
+// ---- right-hand side of the slack-reduced primal-dual system (zero for
+// problems no longer iterating)
+__global__ void k_rhs(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ dwv,
+                      const double* __restrict__ x, const double* __restrict__ g, const double* __restrict__ y,
                       const double* __restrict__ c, const double* __restrict__ s, const double* __restrict__ ds,
-                      Bnd b, double mu, double kd, double gf, double dw, long long nx, long long nc, long long nst,
-                      long long nkkt, double* __restrict__ rhs) {
-  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) {
-    const int k = lidx(i, nx);
+                      Bnd b, double kd, double gf, long long nxs, long long nks, double* __restrict__ rhs) {
+  const SegView V(seg);
+  const PS q = ps[V.p];
+  const double mu = q.mu, dw = dwv[V.p];
+  const long long i = V.xi(nxs);
+  if (i >= 0) {
+    const int k = lidx(i, nxs);
     // g holds grad f~ + J~^T y; remove grad f~ for d since barrier_grad adds it
     const double gl = (k == NV) ? g[i] - gf : g[i];
-    rhs[kkt_of_primal(i, nx, nkkt)] = -(gl + barrier_grad(x[i], k, b, mu, kd, gf));
+    rhs[kkt_of_primal(i, nxs, nks)] = q.active ? -(gl + barrier_grad(x[i], k, b, mu, kd, gf)) : 0.0;
   }
-  if (i < nc && i % NR != NR - 1) rhs[kkt_of_row(i)] = -c[i];
-  if (i < nst) {
-    const double yh = y[i * NR + NR - 1];
-    const double rs = mu / (-s[i]) - kd * mu - yh;
-    const double rd = c[i * NR + NR - 1] - s[i];
-    rhs[i * NK + NK - 1] = -rd - rs / (ds[i] + dw);
+  const long long j = V.ci();
+  if (j >= 0 && j % NR != NR - 1) rhs[kkt_of_row(j)] = q.active ? -c[j] : 0.0;
+  const long long t = V.ti();
+  if (t >= 0) {
+    const double yh = y[t * NR + NR - 1];
+    const double rs = mu / (-s[t]) - kd * mu - yh;
+    const double rd = c[t * NR + NR - 1] - s[t];
+    rhs[t * NK + NK - 1] = q.active ? -rd - rs / (ds[t] + dw) : 0.0;
   }
 }
 
 // ---- search direction pieces, fraction to the boundary and grad(phi)^T dx
-// partials: 0 min alpha primal, 1 min alpha dual, 2 sum grad phi . d
-__global__ void k_direction(const double* __restrict__ x, const double* __restrict__ zL,
+// segment partials: 0 min alpha primal, 1 min alpha dual, 2 sum grad phi . d
+__global__ void k_direction(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ dwv,
+                            const double* __restrict__ x, const double* __restrict__ zL,
                             const double* __restrict__ zU, const double* __restrict__ y, const double* __restrict__ s,
                             const double* __restrict__ vU, const double* __restrict__ dss,
-                            const double* __restrict__ sol, Bnd b, double mu, double kd, double gf, double dw,
-                            double tau, long long nx, long long nc, long long nst, long long nkkt,
+                            const double* __restrict__ sol, Bnd b, double kd, double gf, long long nxs, long long nks,
                             double* __restrict__ dx, double* __restrict__ dy, double* __restrict__ dzL,
                             double* __restrict__ dzU, double* __restrict__ dsl, double* __restrict__ dvU,
                             double* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  const SegView V(seg);
+  const PS q = ps[V.p];
+  const double mu = q.mu, tau = q.tau, dw = dwv[V.p];
   Part<3> p;
   p.v[0] = 1.0;
   p.v[1] = 1.0;
   p.v[2] = 0.0;
-  if (i < nx) {
-    const int k = lidx(i, nx);
-    const double d = sol[kkt_of_primal(i, nx, nkkt)];
+  const long long i = V.xi(nxs);
+  if (i >= 0) {
+    const int k = lidx(i, nxs);
+    const double d = sol[kkt_of_primal(i, nxs, nks)];
     dx[i] = d;
     const double xi = x[i];
     double a = 0.0, bz = 0.0;
@@ -250,41 +330,49 @@ __global__ void k_direction(const double* __restrict__ x, const double* __restri
     dzU[i] = bz;
     p.v[2] += barrier_grad(xi, k, b, mu, kd, gf) * d;
   }
-  if (i < nc) dy[i] = sol[kkt_of_row(i)];
-  if (i < nst) {
-    const double si = -s[i];  // distance of the slack to its bound 0
-    const double yh = y[i * NR + NR - 1];
+  const long long j = V.ci();
+  if (j >= 0) dy[j] = sol[kkt_of_row(j)];
+  const long long t = V.ti();
+  if (t >= 0) {
+    const double si = -s[t];  // distance of the slack to its bound 0
+    const double yh = y[t * NR + NR - 1];
     const double rs = mu / si - kd * mu - yh;
-    const double dyh = sol[i * NK + NK - 1];
-    const double d = (dyh - rs) / (dss[i] + dw);
-    dsl[i] = d;
-    const double dv = mu / si - vU[i] + vU[i] / si * d;
-    dvU[i] = dv;
+    const double dyh = sol[t * NK + NK - 1];
+    const double d = (dyh - rs) / (dss[t] + dw);
+    dsl[t] = d;
+    const double dv = mu / si - vU[t] + vU[t] / si * d;
+    dvU[t] = dv;
     if (d > 0.0) p.v[0] = fmin(p.v[0], tau * si / d);
-    if (dv < 0.0) p.v[1] = fmin(p.v[1], -tau * vU[i] / dv);
+    if (dv < 0.0) p.v[1] = fmin(p.v[1], -tau * vU[t] / dv);
     p.v[2] += (mu / si - kd * mu) * d;
   }
-  const int ops[3] = {2, 2, 0};
-  block_reduce<3>(p, ops, out);
+  block_reduce<3>(p, Ops<3>{{2, 2, 0}}, out);
 }
 
-__global__ void k_trial(const double* __restrict__ x, const double* __restrict__ dx, const double* __restrict__ s,
-                        const double* __restrict__ dsl, double a, long long nx, long long nst, double* __restrict__ xt,
-                        double* __restrict__ st) {
-  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) xt[i] = x[i] + a * dx[i];
-  if (i < nst) st[i] = s[i] + a * dsl[i];
+// trial point of the problems in the line search
+__global__ void k_trial(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ x,
+                        const double* __restrict__ dx, const double* __restrict__ s, const double* __restrict__ dsl,
+                        long long nxs, double* __restrict__ xt, double* __restrict__ st) {
+  const SegView V(seg);
+  const PS q = ps[V.p];
+  if (!q.search) return;
+  const long long i = V.xi(nxs);
+  if (i >= 0) xt[i] = x[i] + q.alpha * dx[i];
+  const long long t = V.ti();
+  if (t >= 0) st[t] = s[t] + q.alpha * dsl[t];
 }
 
-// line-search partials at a trial point: 0 theta (1-norm), 1 barrier sum, 2 infeasible count
-__global__ void k_ls_parts(const double* __restrict__ xt, const double* __restrict__ st, const double* __restrict__ c,
-                           Bnd b, double mu, double kd, long long nx, long long nc, long long nst,
-                           double* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+// line-search partials at a point: 0 theta (1-norm), 1 barrier sum, 2 infeasible count
+__global__ void k_ls_parts(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ xt,
+                           const double* __restrict__ st, const double* __restrict__ c, Bnd b, double kd,
+                           long long nxs, double* __restrict__ out) {
+  const SegView V(seg);
+  const double mu = ps[V.p].mu;
   Part<3> p;
   p.v[0] = p.v[1] = p.v[2] = 0.0;
-  if (i < nx) {
-    const int k = lidx(i, nx);
+  const long long i = V.xi(nxs);
+  if (i >= 0) {
+    const int k = lidx(i, nxs);
     const bool hl = isfinite(b.lo[k]), hu = isfinite(b.hi[k]);
     if (hl) {
       const double sl = xt[i] - b.lo[k];
@@ -299,54 +387,69 @@ __global__ void k_ls_parts(const double* __restrict__ xt, const double* __restri
       if (!hl) p.v[1] += kd * mu * su;
     }
   }
-  if (i < nc) {
-    if (i % NR != NR - 1) p.v[0] += fabs(c[i]);
-    if (!isfinite(c[i])) p.v[2] += 1.0;
+  const long long j = V.ci();
+  if (j >= 0) {
+    if (j % NR != NR - 1) p.v[0] += fabs(c[j]);
+    if (!isfinite(c[j])) p.v[2] += 1.0;
   }
-  if (i < nst) {
-    const double si = -st[i];
+  const long long t = V.ti();
+  if (t >= 0) {
+    const double si = -st[t];
     if (!(si > 0.0)) p.v[2] += 1.0;
     else p.v[1] += -mu * log(si) + kd * mu * si;
-    p.v[0] += fabs(c[i * NR + NR - 1] - st[i]);
+    p.v[0] += fabs(c[t * NR + NR - 1] - st[t]);
   }
-  const int ops[3] = {0, 0, 0};
-  block_reduce<3>(p, ops, out);
+  block_reduce<3>(p, Ops<3>{{0, 0, 0}}, out);
 }
 
-// accept the step: multipliers, bound multipliers with their own step and the safeguard
-__global__ void k_accept(const double* __restrict__ xn, const double* __restrict__ sn, double* __restrict__ y,
-                         const double* __restrict__ dy, double* __restrict__ zL, const double* __restrict__ dzL,
-                         double* __restrict__ zU, const double* __restrict__ dzU, double* __restrict__ vU,
-                         const double* __restrict__ dvU, Bnd b, double a, double az, double mu, double ksig,
-                         long long nx, long long nc, long long nst) {
-  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) {
-    const int k = lidx(i, nx);
+// accept the step of the problems whose trial point passed: primal and slack
+// from the trial point, multipliers, bound multipliers with their own step and
+// the safeguard
+__global__ void k_accept(const Seg* __restrict__ seg, const PS* __restrict__ ps, double* __restrict__ x,
+                         const double* __restrict__ xn, double* __restrict__ s, const double* __restrict__ sn,
+                         double* __restrict__ y, const double* __restrict__ dy, double* __restrict__ zL,
+                         const double* __restrict__ dzL, double* __restrict__ zU, const double* __restrict__ dzU,
+                         double* __restrict__ vU, const double* __restrict__ dvU, Bnd b, double ksig,
+                         long long nxs) {
+  const SegView V(seg);
+  const PS q = ps[V.p];
+  if (!q.accept) return;
+  const double a = q.alpha, az = q.alpha_z, mu = q.mu;
+  const long long i = V.xi(nxs);
+  if (i >= 0) {
+    const int k = lidx(i, nxs);
+    const double xi = xn[i];
+    x[i] = xi;
     if (isfinite(b.lo[k])) {
-      const double sl = xn[i] - b.lo[k];
+      const double sl = xi - b.lo[k];
       const double z = zL[i] + az * dzL[i];
       zL[i] = fmax(fmin(z, ksig * mu / sl), mu / (ksig * sl));
     }
     if (isfinite(b.hi[k])) {
-      const double su = b.hi[k] - xn[i];
+      const double su = b.hi[k] - xi;
       const double z = zU[i] + az * dzU[i];
       zU[i] = fmax(fmin(z, ksig * mu / su), mu / (ksig * su));
     }
   }
-  if (i < nc) y[i] += a * dy[i];
-  if (i < nst) {
-    const double si = -sn[i];
-    const double v = vU[i] + az * dvU[i];
-    vU[i] = fmax(fmin(v, ksig * mu / si), mu / (ksig * si));
+  const long long j = V.ci();
+  if (j >= 0) y[j] += a * dy[j];
+  const long long t = V.ti();
+  if (t >= 0) {
+    const double snt = sn[t];
+    s[t] = snt;
+    const double si = -snt;
+    const double v = vU[t] + az * dvU[t];
+    vU[t] = fmax(fmin(v, ksig * mu / si), mu / (ksig * si));
   }
 }
 
-// bound push, multiplier initialisation and the least-squares right-hand side
+// bound push and multiplier initialisation
 __global__ void k_init_point(double* __restrict__ x, double* __restrict__ zL, double* __restrict__ zU, Bnd b,
-                             double push, double frac, int warm, double mu, double zinit, long long nx) {
+                             double push, double frac, int warm, double mu, double zinit, long long nx,
+                             long long nxs) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
   if (i >= nx) return;
-  const int k = lidx(i, nx);
+  const int k = lidx(i, nxs);
   const double lo = b.lo[k], hi = b.hi[k];
   const bool hl = isfinite(lo), hu = isfinite(hi);
   double xi = x[i];
@@ -376,15 +479,32 @@ __global__ void k_init_slack(const double* __restrict__ c, double* __restrict__ 
 
 // rhs of the least-squares multiplier system [[I, J^T], [J, 0]] (slack block eliminated)
 __global__ void k_ls_rhs(const double* __restrict__ zL, const double* __restrict__ zU, const double* __restrict__ vU,
-                         double gf, long long nx, long long nst, long long nkkt, double* __restrict__ rhs) {
+                         double gf, long long nx, long long nxs, long long nks, long long nst,
+                         double* __restrict__ rhs) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) rhs[kkt_of_primal(i, nx, nkkt)] = -((i == nx - 1 ? gf : 0.0) - zL[i] + zU[i]);
+  if (i < nx) rhs[kkt_of_primal(i, nxs, nks)] = -((i >= nxs ? gf : 0.0) - zL[i] + zU[i]);
   if (i < nst) rhs[i * NK + NK - 1] = -vU[i];
 }
 
 __global__ void k_copy_duals(const double* __restrict__ sol, long long nc, double* __restrict__ y) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
   if (i < nc) y[i] = sol[kkt_of_row(i)];
+}
+
+// per-segment max |y| (least-squares multiplier check)
+__global__ void k_ymax_parts(const Seg* __restrict__ seg, const double* __restrict__ y, double* __restrict__ out) {
+  const SegView V(seg);
+  Part<1> p;
+  const long long j = V.ci();
+  p.v[0] = j >= 0 ? (isfinite(y[j]) ? fabs(y[j]) : INFINITY) : 0.0;
+  block_reduce<1>(p, Ops<1>{{1}}, out);
+}
+
+__global__ void k_zero_y(const Seg* __restrict__ seg, const PS* __restrict__ ps, double* __restrict__ y) {
+  const SegView V(seg);
+  if (!ps[V.p].zero_y) return;
+  const long long j = V.ci();
+  if (j >= 0) y[j] = 0.0;
 }
 
 __global__ void k_fill(double* __restrict__ p, double v, long long n) {
@@ -397,18 +517,31 @@ __global__ void k_absmax_parts(const double* __restrict__ v, long long n, double
   Part<1> p;
   p.v[0] = i < n ? fabs(v[i]) : 0.0;
   if (i < n && !isfinite(v[i])) p.v[0] = INFINITY;
-  const int ops[1] = {1};
-  block_reduce<1>(p, ops, out);
+  block_reduce<1>(p, Ops<1>{{1}}, out);
+}
+
+// final iterate of the problems flagged "write": x = D * xt and y = y~ * cs
+__global__ void k_output(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ xt,
+                         const double* __restrict__ y, const double* __restrict__ cs, Scaling sc, long long nxs,
+                         double* __restrict__ xout, double* __restrict__ yout) {
+  const SegView V(seg);
+  if (!ps[V.p].write) return;
+  const long long i = V.xi(nxs);
+  if (xout && i >= 0) xout[i] = xt[i] * (i >= nxs ? sc.Dd : sc.D[i % NV]);
+  const long long j = V.ci();
+  if (yout && j >= 0) yout[j] = y[j] * cs[j];
 }
 
 // unscale x = D * xt, y = y~ (multipliers of scaled rows) * cs
-__global__ void k_unscale(const double* __restrict__ xt, Scaling sc, long long nx, double* __restrict__ x) {
+__global__ void k_unscale(const double* __restrict__ xt, Scaling sc, long long nx, long long nxs,
+                          double* __restrict__ x) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) x[i] = xt[i] * (i == nx - 1 ? sc.Dd : sc.D[i % NV]);
+  if (i < nx) x[i] = xt[i] * (i >= nxs ? sc.Dd : sc.D[i % NV]);
 }
-__global__ void k_scale_x(const double* __restrict__ x, Scaling sc, long long nx, double* __restrict__ xt) {
+__global__ void k_scale_x(const double* __restrict__ x, Scaling sc, long long nx, long long nxs,
+                          double* __restrict__ xt) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) xt[i] = x[i] / (i == nx - 1 ? sc.Dd : sc.D[i % NV]);
+  if (i < nx) xt[i] = x[i] / (i >= nxs ? sc.Dd : sc.D[i % NV]);
 }
 __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b, long long n, int divide,
                       double* __restrict__ out) {
@@ -429,14 +562,28 @@ struct Work {
   double *xt = nullptr, *xtt = nullptr, *zL = nullptr, *zU = nullptr, *y = nullptr, *s = nullptr, *st = nullptr,
          *vU = nullptr, *c = nullptr, *ct = nullptr, *g = nullptr, *dpart = nullptr, *rhs = nullptr, *sol = nullptr,
          *dx = nullptr, *dy = nullptr, *dzL = nullptr, *dzU = nullptr, *ds = nullptr, *dvU = nullptr,
-         *rowmax = nullptr, *omega = nullptr, *best = nullptr;
-  std::vector<void*> all;
+         *rowmax = nullptr;
+  PS* ps = nullptr;        // device [P]
+  PS* ps_h = nullptr;      // pinned [P]
+  double* dw_h = nullptr;  // pinned [P]
+  double* dc_h = nullptr;  // pinned [P]
+  int* fm_h = nullptr;     // pinned [P]
+  double* dd_h = nullptr;  // pinned [P]: the d entries of a primal vector
+  std::vector<void*> all, pinned;
   ~Work() {
     for (void* p : all) (void)hipFree(p);
+    for (void* p : pinned) (void)hipHostFree(p);
   }
-  hipError_t alloc(double** p, long long n) {
-    hipError_t e = hipMalloc((void**)p, sizeof(double) * (size_t)std::max<long long>(n, 1));
-    if (e == hipSuccess) all.push_back(*p);
+  template <class T>
+  hipError_t alloc(T** p, long long n) {
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)std::max<long long>(n, 1));
+    if (e == hipSuccess) all.push_back((void*)*p);
+    return e;
+  }
+  template <class T>
+  hipError_t host(T** p, long long n) {
+    hipError_t e = hipHostMalloc((void**)p, sizeof(T) * (size_t)std::max<long long>(n, 1), 0);
+    if (e == hipSuccess) pinned.push_back((void*)*p);
     return e;
   }
 };
@@ -457,11 +604,23 @@ struct Consts {
   double eta_phi = 1e-8, gamma_alpha = 0.05, theta_max_fact = 1e4, theta_min_fact = 1e-4;
   double dw_init = 1e-4, dw_min = 1e-20, dw_max = 1e40, kw_minus = 1.0 / 3.0, kw_plus = 8.0, kw_plus_bar = 100.0;
   double dc_bar = 1e-8, kappa_c = 0.25, constr_mult_init_max = 1e3, zinit = 1.0;
+  double alpha_floor = 0x1p-52;
+};
+
+// host state of one problem
+struct Prob {
+  double mu = 0, tau = 0, dw = 0, dc = 0, dw_last = 0, theta_max = 0, theta_min = 0;
+  double E0 = INFINITY, inf_pr = 0, inf_du = 0, compl0 = 0, xd = 0, dxd = 0;
+  double alpha = 0, alpha_max = 0, alpha_z = 0, gdx = 0, th = 0, phi = 0, amin = 0;
+  double n_all = 0, n_b = 0, nx_p = 0, nc_p = 0;
+  int status = ABS_ERR_MAXITER, it = 0, ncorr = 0, nls = 0;
+  bool active = true, need = false, searching = false, accepted = false, ftype = false;
+  Filter filt;
 };
 
 }  // namespace
 
-// host-side reduction of per-block partials
+// host-side reduction of per-block partials (global)
 static int reduce_parts(Handle& h, int nblocks, int K, const int* ops, double* outv, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(h.redbuf_h, h.redbuf, sizeof(double) * nblocks * K, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -473,6 +632,17 @@ static int reduce_parts(Handle& h, int nblocks, int K, const int* ops, double* o
     }
     outv[k] = a;
   }
+  return ABS_OK;
+}
+
+// per-problem results of the segment partials in h.redbuf -> h.redbuf_h[p * K + k]
+template <int K>
+static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
+  double* out = h.redbuf + (long long)h.nseg * K;
+  hipLaunchKernelGGL(k_seg_reduce<K>, dim3(h.P), dim3(BS), 0, st, h.redbuf, h.pseg, ops, out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * h.P * K, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return ABS_OK;
 }
 
@@ -488,22 +658,19 @@ static int absmax(Handle& h, const double* v, long long n, double* out, hipStrea
 }
 
 int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st) {
-  const long long nkk = h.nkkt - 1;
-  const double* diagd = h.diagx + (h.nx - 1);
   if (!fused_first) {
     HIP_TRY(launch_solve(h, rhs, st));
-    HIP_TRY(launch_schur(h, diagd, h.fdw, rhs + nkk, 2, sol, st));
+    HIP_TRY(launch_schur(h, h.diagx, rhs, 2, sol, st));
   }
   double rn = 0.0;
   int rc = absmax(h, rhs, h.nkkt, &rn, st);
   if (rc) return rc;
-  double* om_d = h.kden + 3 * ((long long)h.N * h.S);  // two doubles after the residual block partials
   double best_om = INFINITY, best_rel = INFINITY;
   bool have_best = false;
+  double* om = h.redbuf_h + h.red_cap - 2;  // two pinned doubles past the partials
   for (int it = 0; it <= 10; ++it) {
-    HIP_TRY(launch_residual(h, h.diagx, h.diags, h.fdw, h.fdc, sol, rhs, h.kres, om_d, st));
-    double om[2];
-    HIP_TRY(hipMemcpyAsync(om, om_d, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(launch_residual(h, h.diagx, h.diags, sol, rhs, h.kres, h.omega_d, st));
+    HIP_TRY(hipMemcpyAsync(om, h.omega_d, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     double resn = 0.0;
     rc = absmax(h, h.kres, h.nkkt, &resn, st);  // synchronises the stream
     if (rc) return rc;
@@ -519,7 +686,7 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     HIP_TRY(hipMemcpyAsync(h.kcor, sol, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
     have_best = true;
     HIP_TRY(launch_solve(h, h.kres, st));
-    HIP_TRY(launch_schur(h, diagd, h.fdw, h.kres + nkk, 2, h.kres, st));  // correction in place
+    HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st));  // correction in place
     HIP_TRY(launch_axpy(sol, h.kres, 1.0, h.nkkt, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
@@ -528,14 +695,15 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
 }
 
 int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, const double* y0_dev, double* xout,
-              double* yout, absorber_ipm_result* res) {
+              double* yout, absorber_ipm_result* res, const unsigned char* active0) {
   const auto t_start = std::chrono::steady_clock::now();
   const Consts C;
   hipStream_t st = h.stream;
-  const long long nx = h.nx, nc = h.nc, nst = (long long)h.N * h.S, nkkt = h.nkkt;
-  const long long nmax = std::max(nx, nc);
-  const int nb = (int)grid_for(nmax, BS);
-  if (nb * 9 > h.red_cap) {
+  const int P = h.P;
+  const long long nx = h.nx, nc = h.nc, nst = h.nst, nkkt = h.nkkt;
+  const long long nxs = nst * NV, nks = nst * NK;
+  const int nseg = h.nseg;
+  if (9LL * (nseg + P) > h.red_cap - 2) {
     set_error("ipm_solve: problem too large for the reduction buffer");
     return ABS_ERR_ARG;
   }
@@ -548,7 +716,51 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   for (double** p : bufs_ns) HIP_TRY(W.alloc(p, nst));
   HIP_TRY(W.alloc(&W.rhs, nkkt));
   HIP_TRY(W.alloc(&W.sol, nkkt));
-  HIP_TRY(W.alloc(&W.omega, 8));
+  HIP_TRY(W.alloc(&W.ps, P));
+  HIP_TRY(W.host(&W.ps_h, P));
+  HIP_TRY(W.host(&W.dw_h, P));
+  HIP_TRY(W.host(&W.dc_h, P));
+  HIP_TRY(W.host(&W.fm_h, P));
+  HIP_TRY(W.host(&W.dd_h, P));
+  std::vector<Prob> pr((size_t)P);
+  auto upload_ps = [&]() -> int {
+    for (int p = 0; p < P; ++p) {
+      const Prob& q = pr[(size_t)p];
+      PS& d = W.ps_h[p];
+      d.mu = q.mu;
+      d.tau = q.tau;
+      d.alpha = q.alpha;
+      d.alpha_z = q.alpha_z;
+      d.active = q.active;
+      d.search = q.searching;
+      d.accept = q.accepted;
+      d.zero_y = 0;
+      d.write = !active0 || active0[p];
+    }
+    HIP_TRY(hipMemcpyAsync(W.ps, W.ps_h, sizeof(PS) * P, hipMemcpyHostToDevice, st));
+    return ABS_OK;
+  };
+  auto upload_reg = [&](bool mask) -> int {
+    for (int p = 0; p < P; ++p) {
+      W.dw_h[p] = pr[(size_t)p].dw;
+      W.dc_h[p] = pr[(size_t)p].dc;
+      W.fm_h[p] = mask ? (pr[(size_t)p].need ? 1 : 0) : 1;
+    }
+    HIP_TRY(hipMemcpyAsync(h.dwv, W.dw_h, sizeof(double) * P, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h.dcv, W.dc_h, sizeof(double) * P, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h.fmask, W.fm_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+    return ABS_OK;
+  };
+  auto read_d = [&](const double* v) -> int {  // d entries of a primal vector -> W.dd_h
+    HIP_TRY(hipMemcpyAsync(W.dd_h, v + nxs, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ABS_OK;
+  };
+#define TRY(expr)            \
+  do {                       \
+    const int rc_ = (expr);  \
+    if (rc_) return rc_;     \
+  } while (0)
 
   // ---- variable scaling from the cold-start point: x = D * xt
   const double* zc = h.x0;
@@ -562,31 +774,34 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   b.lo[NV] = h.dL / h.sc.Dd;
   b.hi[NV] = h.dU / h.sc.Dd;
   const bool warm = o.warm_start && x0_dev;
-  const unsigned gx = grid_for(nx, BS), gc = grid_for(nc, BS), gm = grid_for(nmax, BS);
-  // ---- bound-pushed cold point and gradient-based row scaling there (A-1)
-  {
-    int rc = initial_point(h, W.xtt, st);
-    if (rc) return rc;
-  }
-  hipLaunchKernelGGL(k_scale_x, dim3(gx), dim3(BS), 0, st, W.xtt, h.sc, nx, W.xt);
+  const unsigned gx = grid_for(nx, BS), gc = grid_for(nc, BS), gst = grid_for(nst, BS);
+  const unsigned gm = grid_for(std::max(nx, nc), BS);
+  // ---- bound-pushed cold point and gradient-based row scaling there
+  TRY(initial_point(h, W.xtt, st));
+  hipLaunchKernelGGL(k_scale_x, dim3(gx), dim3(BS), 0, st, W.xtt, h.sc, nx, nxs, W.xt);
   hipLaunchKernelGGL(k_init_point, dim3(gx), dim3(BS), 0, st, W.xt, W.zL, W.zU, b, o.bound_push, o.bound_push, 0,
-                     0.0, C.zinit, nx);
+                     0.0, C.zinit, nx, nxs);
   HIP_TRY(launch_rowmax(h, W.xt, 1, W.rowmax, st));
   hipLaunchKernelGGL(k_rowscale, dim3(gc), dim3(BS), 0, st, W.rowmax, o.nlp_scaling_max_gradient, nc, h.cs);
   h.sf = std::min(1.0, o.nlp_scaling_max_gradient / h.sc.Dd);
   const double gf = h.sf * h.sc.Dd;  // gradient of f~ = sf * d with respect to xt_d
-  double mu = warm ? o.warm_mu_init : o.mu_init;
+  const double mu0 = warm ? o.warm_mu_init : o.mu_init;
+  for (auto& q : pr) {
+    q.mu = mu0;
+    q.tau = std::max(C.tau_min, 1.0 - mu0);
+  }
   if (warm) {
-    hipLaunchKernelGGL(k_scale_x, dim3(gx), dim3(BS), 0, st, x0_dev, h.sc, nx, W.xt);
+    hipLaunchKernelGGL(k_scale_x, dim3(gx), dim3(BS), 0, st, x0_dev, h.sc, nx, nxs, W.xt);
     hipLaunchKernelGGL(k_init_point, dim3(gx), dim3(BS), 0, st, W.xt, W.zL, W.zU, b, o.warm_bound_push,
-                       o.warm_bound_push, 1, mu, C.zinit, nx);
+                       o.warm_bound_push, 1, mu0, C.zinit, nx, nxs);
   }
   HIP_TRY(launch_eval(h, W.xt, 1, nullptr, 0, W.c, st));
-  hipLaunchKernelGGL(k_init_slack, dim3(grid_for(nst, BS)), dim3(BS), 0, st, W.c, W.s, W.vU,
-                     warm ? o.warm_bound_push : o.bound_push, warm ? 1 : 0, mu, C.zinit, nst);
+  hipLaunchKernelGGL(k_init_slack, dim3(gst), dim3(BS), 0, st, W.c, W.s, W.vU, warm ? o.warm_bound_push : o.bound_push,
+                     warm ? 1 : 0, mu0, C.zinit, nst);
   hipLaunchKernelGGL(k_fill, dim3(gc), dim3(BS), 0, st, W.y, 0.0, nc);
   double rel = 0.0, max_rel = 0.0;
-  int nfact = 0, ncorr_tot = 0;
+  int nfact = 0;
+  TRY(upload_ps());
   if (warm && y0_dev) {
     // multipliers of the unscaled rows -> multipliers of the scaled rows
     hipLaunchKernelGGL(k_mul, dim3(gc), dim3(BS), 0, st, y0_dev, h.cs, nc, 1, W.y);
@@ -594,234 +809,364 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     // least-squares multipliers: [[I, J^T], [J, 0]] (slack block eliminated)
     HIP_TRY(launch_eval(h, W.xt, 1, W.y, 1, W.ct, st));
     hipLaunchKernelGGL(k_fill, dim3(gx), dim3(BS), 0, st, h.diagx, 0.0, nx);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(nst, BS)), dim3(BS), 0, st, h.diags, 0.0, nst);
+    hipLaunchKernelGGL(k_fill, dim3(gst), dim3(BS), 0, st, h.diags, 0.0, nst);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(nkkt, BS)), dim3(BS), 0, st, W.rhs, 0.0, nkkt);
-    hipLaunchKernelGGL(k_ls_rhs, dim3(grid_for(nkkt, BS)), dim3(BS), 0, st, W.zL, W.zU, W.vU, gf, nx, nst, nkkt,
-                       W.rhs);
-    HIP_TRY(launch_factor(h, h.diagx, h.diags, 1.0, 0.0, W.rhs, st));
+    hipLaunchKernelGGL(k_ls_rhs, dim3(grid_for(std::max(nx, nst), BS)), dim3(BS), 0, st, W.zL, W.zU, W.vU, gf, nx,
+                       nxs, nks, nst, W.rhs);
+    for (auto& q : pr) {
+      q.dw = 1.0;
+      q.dc = 0.0;
+    }
+    TRY(upload_reg(false));
+    HIP_TRY(launch_factor(h, h.diagx, h.diags, W.rhs, false, st));
     ++nfact;
-    HIP_TRY(launch_schur(h, h.diagx + (nx - 1), 1.0, W.rhs + (nkkt - 1), 1, W.sol, st));
-    int rc = kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st);
-    if (rc) return rc;
+    HIP_TRY(launch_schur(h, h.diagx, W.rhs, 1, W.sol, st));
+    TRY(kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st));
     hipLaunchKernelGGL(k_copy_duals, dim3(gc), dim3(BS), 0, st, W.sol, nc, W.y);
-    double ymax = 0.0;
-    rc = absmax(h, W.y, nc, &ymax, st);
-    if (rc) return rc;
-    if (!(ymax <= C.constr_mult_init_max)) hipLaunchKernelGGL(k_fill, dim3(gc), dim3(BS), 0, st, W.y, 0.0, nc);
+    hipLaunchKernelGGL(k_ymax_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.y, h.redbuf);
+    TRY(seg_reduce<1>(h, Ops<1>{{1}}, st));
+    bool any = false;
+    for (int p = 0; p < P; ++p) {
+      W.ps_h[p].zero_y = !(h.redbuf_h[p] <= C.constr_mult_init_max);
+      any = any || W.ps_h[p].zero_y;
+    }
+    if (any) {
+      HIP_TRY(hipMemcpyAsync(W.ps, W.ps_h, sizeof(PS) * P, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_zero_y, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.y);
+    }
   }
-  // host copy of the scaled diameter (kept in step with the device copy)
-  double xd = 0.0;
-  HIP_TRY(hipMemcpyAsync(&xd, W.xt + (nx - 1), sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  // ---- filter bounds from theta(x0)
-  const int ls_ops[3] = {0, 0, 0};
-  double lsv[3];
-  hipLaunchKernelGGL(k_ls_parts, dim3(gm), dim3(BS), 0, st, W.xt, W.s, W.c, b, 0.0, C.kappa_d, nx, nc, nst,
+  TRY(read_d(W.xt));
+  // ---- per-problem filter bounds from theta(x0) and multiplier counts
+  hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
                      h.redbuf);
-  {
-    int rc = reduce_parts(h, gm, 3, ls_ops, lsv, st);
-    if (rc) return rc;
-  }
-  const double theta0 = lsv[0];
-  const double theta_max = C.theta_max_fact * std::max(1.0, theta0);
-  const double theta_min = C.theta_min_fact * std::max(1.0, theta0);
-  Filter filt;
-  double dw_last = 0.0;
-  double tau = std::max(C.tau_min, 1.0 - mu);
-  int status = ABS_ERR_MAXITER, it = 0;
-  double E0 = INFINITY, inf_pr = 0, inf_du = 0, compl0 = 0;
-  const double n_mult = (double)nc + 0.0;
-  // counts of bound multipliers (per-local pattern times the stages, plus d)
-  long long nbL = 0, nbU = 0;
+  TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
+  long long nbL1 = 0, nbU1 = 0;  // finite bounds per stage
   for (int k = 0; k < NV; ++k) {
-    nbL += std::isfinite(b.lo[k]) ? nst : 0;
-    nbU += std::isfinite(b.hi[k]) ? nst : 0;
+    nbL1 += std::isfinite(b.lo[k]);
+    nbU1 += std::isfinite(b.hi[k]);
   }
-  nbL += std::isfinite(b.lo[NV]);
-  nbU += std::isfinite(b.hi[NV]);
-  const double n_all = n_mult + (double)(nbL + nbU + nst);
-  const double n_b = (double)(nbL + nbU + nst);
-  const int opt_ops[9] = {1, 1, 1, 1, 2, 1, 0, 0, 0};
-  const int dir_ops[3] = {2, 2, 0};
+  for (int p = 0; p < P; ++p) {
+    Prob& q = pr[(size_t)p];
+    const double th0 = h.redbuf_h[p * 3 + 0];
+    q.theta_max = C.theta_max_fact * std::max(1.0, th0);
+    q.theta_min = C.theta_min_fact * std::max(1.0, th0);
+    q.xd = W.dd_h[p];
+    const double nsp = (double)(h.pstage_h[(size_t)p + 1] - h.pstage_h[(size_t)p]);
+    q.nx_p = NV * nsp + 1;
+    q.nc_p = NR * nsp;
+    const double nbL = nbL1 * nsp + std::isfinite(b.lo[NV]), nbU = nbU1 * nsp + std::isfinite(b.hi[NV]);
+    q.n_all = q.nc_p + nbL + nbU + nsp;
+    q.n_b = nbL + nbU + nsp;
+  }
+  int n_active = P, iter = 0;
+  if (active0) {
+    n_active = 0;
+    for (int p = 0; p < P; ++p) {
+      pr[(size_t)p].active = active0[p] != 0;
+      n_active += active0[p] != 0;
+    }
+  }
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
   while (true) {
+    const auto ph0 = now();
+    int n_fac_it = 0, n_ls_it = 0;
     // ---- evaluation at (x_k, y_k): residuals, Jacobian, Hessian, Lagrangian gradient
     HIP_TRY(launch_eval(h, W.xt, 1, W.y, 1, W.c, st));
-    hipLaunchKernelGGL(k_lag_grad, dim3(grid_for(nst, 128)), dim3(128), 0, st, h.rec, h.jtab, W.y, h.N, h.S, W.g,
-                       W.dpart);
-    hipLaunchKernelGGL(k_grad_d, dim3(1), dim3(BS), 0, st, W.dpart, nst, gf, W.g + (nx - 1));
-    hipLaunchKernelGGL(k_opt_parts, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s, W.vU, b, nx,
-                       nc, nst, h.redbuf);
-    double ov[9];
-    {
-      int rc = reduce_parts(h, gm, 9, opt_ops, ov, st);
-      if (rc) return rc;
+    hipLaunchKernelGGL(k_lag_grad, dim3(grid_for(nst, 128)), dim3(128), 0, st, h.rec, h.jtab, W.y, h.sinfo, nst,
+                       W.g, W.dpart);
+    hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pstage, gf, nxs, W.g);
+    hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s, W.vU,
+                       b, nxs, h.redbuf);
+    TRY(seg_reduce<9>(h, Ops<9>{{1, 1, 1, 1, 2, 1, 0, 0, 0}}, st));
+    for (int p = 0; p < P; ++p) {
+      Prob& q = pr[(size_t)p];
+      if (!q.active) continue;
+      const double* ov = h.redbuf_h + p * 9;
+      const double dual = std::max(ov[0], ov[1]);
+      const double primal = std::max(ov[2], ov[3]);
+      const double sd = std::max(C.s_max, (ov[6] + ov[7]) / q.n_all) / C.s_max;
+      const double sc = std::max(C.s_max, ov[7] / q.n_b) / C.s_max;
+      auto Emu = [&](double m) {
+        const double comp = std::max(fabs(ov[5] - m), fabs(ov[4] - m));
+        return std::max(std::max(dual / sd, primal), comp / sc);
+      };
+      q.E0 = Emu(0.0);
+      q.inf_pr = primal;
+      q.inf_du = dual;
+      q.compl0 = std::max(fabs(ov[4]), fabs(ov[5]));
+      int stop = 1;
+      if (ov[8] > 0 || !std::isfinite(q.E0)) q.status = ABS_ERR_NAN;
+      else if (q.E0 <= o.tol) q.status = ABS_OK;
+      else if (q.it >= o.max_iter) q.status = ABS_ERR_MAXITER;
+      else stop = 0;
+      if (stop) {
+        q.active = false;
+        --n_active;
+        continue;
+      }
+      // monotone barrier update (repeated while the barrier problem is solved)
+      while (Emu(q.mu) <= C.kappa_eps * q.mu) {
+        const double mu_new = std::max(o.tol / 10.0, std::min(C.kappa_mu * q.mu, pow(q.mu, C.theta_mu)));
+        if (mu_new >= q.mu) break;  // already at its floor tol / 10: the update is done
+        q.mu = mu_new;
+        q.tau = std::max(C.tau_min, 1.0 - q.mu);
+        q.filt.pts.clear();
+      }
     }
-    const double dual = std::max(ov[0], ov[1]);
-    const double primal = std::max(ov[2], ov[3]);
-    const double sd = std::max(C.s_max, (ov[6] + ov[7]) / n_all) / C.s_max;
-    const double sc = std::max(C.s_max, ov[7] / n_b) / C.s_max;
-    auto Emu = [&](double m) {
-      const double comp = std::max(fabs(ov[5] - m), fabs(ov[4] - m));
-      return std::max(std::max(dual / sd, primal), comp / sc);
-    };
-    E0 = Emu(0.0);
-    inf_pr = primal;
-    inf_du = dual;
-    compl0 = std::max(fabs(ov[4]), fabs(ov[5]));
-    if (ov[8] > 0 || !std::isfinite(E0)) {
-      status = ABS_ERR_NAN;
-      break;
-    }
-    if (E0 <= o.tol) {
-      status = ABS_OK;
-      break;
-    }
-    if (it >= o.max_iter) {
-      status = ABS_ERR_MAXITER;
-      break;
-    }
-    // ---- A-3: monotone barrier update (repeated while the barrier problem is solved)
-    while (Emu(mu) <= C.kappa_eps * mu) {
-      mu = std::max(o.tol / 10.0, std::min(C.kappa_mu * mu, pow(mu, C.theta_mu)));
-      tau = std::max(C.tau_min, 1.0 - mu);
-      filt.pts.clear();
-    }
-    // ---- A-4: search direction with inertia correction
-    hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nst, h.diagx,
+    if (n_active == 0) break;
+    const auto ph1 = now();
+    TRY(upload_ps());
+    // ---- search direction with inertia correction (each problem its own delta_w)
+    hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nxs, nst, h.diagx,
                        h.diags);
-    double dw = 0.0, dc = 0.0;
-    int ncorr = 0;
-    bool ok = false;
+    for (auto& q : pr) {
+      q.dw = 0.0;
+      q.dc = 0.0;
+      q.need = q.active;
+    }
     while (true) {
-      hipLaunchKernelGGL(k_rhs, dim3(gm), dim3(BS), 0, st, W.xt, W.g, W.y, W.c, W.s, h.diags, b, mu, C.kappa_d, gf,
-                         dw, nx, nc, nst, nkkt, W.rhs);
-      HIP_TRY(launch_factor(h, h.diagx, h.diags, dw, dc, W.rhs, st));
+      TRY(upload_reg(true));
+      hipLaunchKernelGGL(k_rhs, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.g, W.y, W.c, W.s, h.diags,
+                         b, C.kappa_d, gf, nxs, nks, W.rhs);
+      HIP_TRY(launch_factor(h, h.diagx, h.diags, W.rhs, true, st));
       ++nfact;
-      HIP_TRY(launch_schur(h, h.diagx + (nx - 1), dw, W.rhs + (nkkt - 1), 1, W.sol, st));
-      HIP_TRY(hipMemcpyAsync(h.scal_h, h.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+      ++n_fac_it;
+      HIP_TRY(launch_schur(h, h.diagx, W.rhs, 1, W.sol, st));
+      HIP_TRY(hipMemcpyAsync(h.scal_h, h.scal, sizeof(DevScalars) * P, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
-      const DevScalars& D = *h.scal_h;
-      if (D.npos == nx && D.nneg == nc && D.nzero == 0) {
-        if (dw > 0.0) dw_last = dw;
-        ok = true;
-        break;
-      }
-      ++ncorr;
-      if (D.nzero > 0) dc = C.dc_bar * pow(mu, C.kappa_c);
-      if (dw == 0.0) dw = dw_last == 0.0 ? C.dw_init : std::max(C.dw_min, C.kw_minus * dw_last);
-      else dw = (dw_last == 0.0 ? C.kw_plus_bar : C.kw_plus) * dw;
-      if (dw > C.dw_max) break;
-    }
-    if (!ok) {
-      status = ABS_ERR_INERTIA;
-      break;
-    }
-    ncorr_tot += ncorr;
-    {
-      int rc = kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st);
-      if (rc) return rc;
-      max_rel = std::max(max_rel, rel);
-    }
-    // ---- A-5: step pieces and fraction to the boundary
-    hipLaunchKernelGGL(k_direction, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.y, W.s, W.vU, h.diags, W.sol, b,
-                       mu, C.kappa_d, gf, dw, tau, nx, nc, nst, nkkt, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
-                       h.redbuf);
-    double dv[3];
-    {
-      int rc = reduce_parts(h, gm, 3, dir_ops, dv, st);
-      if (rc) return rc;
-    }
-    double dxd = 0.0;
-    HIP_TRY(hipMemcpyAsync(&dxd, W.dx + (nx - 1), sizeof(double), hipMemcpyDeviceToHost, st));
-    hipLaunchKernelGGL(k_ls_parts, dim3(gm), dim3(BS), 0, st, W.xt, W.s, W.c, b, mu, C.kappa_d, nx, nc, nst,
-                       h.redbuf);
-    {
-      int rc = reduce_parts(h, gm, 3, ls_ops, lsv, st);
-      if (rc) return rc;
-    }
-    const double alpha_max = dv[0], alpha_z = dv[1], gdx = dv[2];
-    const double th = lsv[0];
-    const double phi = h.sf * h.sc.Dd * xd + lsv[1];
-    double amin;
-    if (gdx < 0 && th <= theta_min)
-      amin = C.gamma_alpha * std::min({C.gamma_theta, C.gamma_phi * th / (-gdx),
-                                       C.delta * pow(th, C.s_theta) / pow(-gdx, C.s_phi)});
-    else if (gdx < 0)
-      amin = C.gamma_alpha * std::min(C.gamma_theta, C.gamma_phi * th / (-gdx));
-    else
-      amin = C.gamma_alpha * C.gamma_theta;
-    double alpha = alpha_max;
-    bool accepted = false, ftype = false;
-    int nls = 0;
-    while (true) {
-      hipLaunchKernelGGL(k_trial, dim3(gx), dim3(BS), 0, st, W.xt, W.dx, W.s, W.ds, alpha, nx, nst, W.xtt, W.st);
-      HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
-      hipLaunchKernelGGL(k_ls_parts, dim3(gm), dim3(BS), 0, st, W.xtt, W.st, W.ct, b, mu, C.kappa_d, nx, nc, nst,
-                         h.redbuf);
-      double tv[3];
-      {
-        int rc = reduce_parts(h, gm, 3, ls_ops, tv, st);
-        if (rc) return rc;
-      }
-      ++nls;
-      const double tht = tv[0];
-      const double phit = tv[2] > 0 ? INFINITY : h.sf * h.sc.Dd * (xd + alpha * dxd) + tv[1];
-      bool okt = std::isfinite(phit) && std::isfinite(tht) && tht < theta_max && filt.acceptable(tht, phit);
-      if (okt) {
-        const double ma = alpha * gdx;
-        const bool switching =
-            ma < 0 && pow(-ma, C.s_phi) * pow(alpha, 1 - C.s_phi) > C.delta * pow(th, C.s_theta);
-        if (th <= theta_min && switching) {
-          if (phit <= phi + C.eta_phi * ma) {
-            accepted = true;
-            ftype = true;
-          }
-        } else if (tht <= (1 - C.gamma_theta) * th || phit <= phi - C.gamma_phi * th) {
-          accepted = true;
-          ftype = false;
+      bool again = false;
+      for (int p = 0; p < P; ++p) {
+        Prob& q = pr[(size_t)p];
+        if (!q.need) continue;
+        const DevScalars& D = h.scal_h[p];
+        if ((double)D.npos == q.nx_p && (double)D.nneg == q.nc_p && D.nzero == 0) {
+          if (q.dw > 0.0) q.dw_last = q.dw;
+          q.need = false;
+          continue;
         }
+        ++q.ncorr;
+        if (D.nzero > 0) q.dc = C.dc_bar * pow(q.mu, C.kappa_c);
+        if (q.dw == 0.0) q.dw = q.dw_last == 0.0 ? C.dw_init : std::max(C.dw_min, C.kw_minus * q.dw_last);
+        else q.dw = (q.dw_last == 0.0 ? C.kw_plus_bar : C.kw_plus) * q.dw;
+        if (q.dw > C.dw_max) {
+          q.status = ABS_ERR_INERTIA;
+          q.active = false;
+          q.need = false;
+          --n_active;
+          continue;
+        }
+        again = true;
       }
-      if (accepted) break;
-      alpha *= 0.5;
-      if (alpha < amin) break;
+      if (!again) break;
     }
-    if (!accepted) {
-      status = ABS_ERR_LS;
-      break;
+    if (n_active == 0) break;
+    const auto ph2 = now();
+    TRY(upload_ps());
+    TRY(kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st));
+    max_rel = std::max(max_rel, rel);
+    const auto ph3 = now();
+    // ---- step pieces and fraction to the boundary
+    hipLaunchKernelGGL(k_direction, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.zL, W.zU, W.y, W.s,
+                       W.vU, h.diags, W.sol, b, C.kappa_d, gf, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
+                       h.redbuf);
+    TRY(seg_reduce<3>(h, Ops<3>{{2, 2, 0}}, st));
+    for (int p = 0; p < P; ++p) {
+      Prob& q = pr[(size_t)p];
+      q.alpha_max = h.redbuf_h[p * 3 + 0];
+      q.alpha_z = h.redbuf_h[p * 3 + 1];
+      q.gdx = h.redbuf_h[p * 3 + 2];
     }
-    if (!ftype) filt.pts.push_back({(1 - C.gamma_theta) * th, phi - C.gamma_phi * th});
-    hipLaunchKernelGGL(k_accept, dim3(gm), dim3(BS), 0, st, W.xtt, W.st, W.y, W.dy, W.zL, W.dzL, W.zU, W.dzU, W.vU,
-                       W.dvU, b, alpha, alpha_z, mu, C.kappa_sigma, nx, nc, nst);
-    std::swap(W.xt, W.xtt);
-    std::swap(W.s, W.st);
-    xd = xd + alpha * dxd;
-    ++it;
-    if (o.print_level > 0)
-      fprintf(stderr, "it %4d mu %9.2e th %9.2e a %9.2e az %9.2e ls %2d dw %8.1e d %.10f E0 %9.2e res %8.1e\n", it,
-              mu, th, alpha, alpha_z, nls, dw, xd * h.sc.Dd, E0, rel);
-    if (fabs(xd) > 1e20) {
-      status = ABS_ERR_DIVERGE;
-      break;
+    TRY(read_d(W.dx));
+    hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
+                       h.redbuf);
+    TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
+    for (int p = 0; p < P; ++p) {
+      Prob& q = pr[(size_t)p];
+      q.dxd = W.dd_h[p];
+      if (!q.active) continue;
+      q.th = h.redbuf_h[p * 3 + 0];
+      q.phi = h.sf * h.sc.Dd * q.xd + h.redbuf_h[p * 3 + 1];
+      const double th = q.th, gdx = q.gdx;
+      if (gdx < 0 && th <= q.theta_min)
+        q.amin = C.gamma_alpha * std::min({C.gamma_theta, C.gamma_phi * th / (-gdx),
+                                           C.delta * pow(th, C.s_theta) / pow(-gdx, C.s_phi)});
+      else if (gdx < 0)
+        q.amin = C.gamma_alpha * std::min(C.gamma_theta, C.gamma_phi * th / (-gdx));
+      else
+        q.amin = C.gamma_alpha * C.gamma_theta;
+      q.alpha = q.alpha_max;
+      q.searching = true;
+      q.accepted = false;
+      q.nls = 0;
     }
+    // ---- filter line search, all searching problems at once
+    const auto ph4 = now();
+    while (true) {
+      ++n_ls_it;
+      TRY(upload_ps());
+      hipLaunchKernelGGL(k_trial, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.dx, W.s, W.ds, nxs, W.xtt, W.st);
+      HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
+      hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d, nxs,
+                         h.redbuf);
+      TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
+      bool any = false;
+      for (int p = 0; p < P; ++p) {
+        Prob& q = pr[(size_t)p];
+        if (!q.searching) continue;
+        const double* tv = h.redbuf_h + p * 3;
+        ++q.nls;
+        const double tht = tv[0];
+        const double phit = tv[2] > 0 ? INFINITY : h.sf * h.sc.Dd * (q.xd + q.alpha * q.dxd) + tv[1];
+        const double th = q.th, phi = q.phi;
+        bool okt = std::isfinite(phit) && std::isfinite(tht) && tht < q.theta_max && q.filt.acceptable(tht, phit);
+        bool acc = false, ftype = false;
+        if (okt) {
+          const double ma = q.alpha * q.gdx;
+          const bool switching =
+              ma < 0 && pow(-ma, C.s_phi) * pow(q.alpha, 1 - C.s_phi) > C.delta * pow(th, C.s_theta);
+          if (th <= q.theta_min && switching) {
+            if (phit <= phi + C.eta_phi * ma) {
+              acc = true;
+              ftype = true;
+            }
+          } else if (tht <= (1 - C.gamma_theta) * th || phit <= phi - C.gamma_phi * th) {
+            acc = true;
+          }
+        }
+        if (acc) {
+          q.searching = false;
+          q.accepted = true;
+          q.ftype = ftype;
+          continue;
+        }
+        q.alpha *= 0.5;
+        // below the minimum step (or below double resolution when that bound underflows)
+        if (q.alpha < std::max(q.amin, C.alpha_floor)) {
+          q.searching = false;
+          q.status = ABS_ERR_LS;
+          q.active = false;
+          --n_active;
+          continue;
+        }
+        any = true;
+      }
+      if (!any) break;
+    }
+    // ---- accept
+    for (int p = 0; p < P; ++p) {
+      Prob& q = pr[(size_t)p];
+      if (!q.accepted) continue;
+      if (!q.ftype) q.filt.pts.push_back({(1 - C.gamma_theta) * q.th, q.phi - C.gamma_phi * q.th});
+      q.xd = q.xd + q.alpha * q.dxd;
+      ++q.it;
+    }
+    TRY(upload_ps());
+    hipLaunchKernelGGL(k_accept, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.xtt, W.s, W.st, W.y, W.dy, W.zL,
+                       W.dzL, W.zU, W.dzU, W.vU, W.dvU, b, C.kappa_sigma, nxs);
+    ++iter;
+    for (int p = 0; p < P; ++p) {
+      Prob& q = pr[(size_t)p];
+      if (q.accepted && P == 1 && o.print_level > 0)
+        fprintf(stderr, "it %4d mu %9.2e th %9.2e a %9.2e az %9.2e ls %2d dw %8.1e d %.10f E0 %9.2e res %8.1e\n",
+                q.it, q.mu, q.th, q.alpha, q.alpha_z, q.nls, q.dw, q.xd * h.sc.Dd, q.E0, rel);
+      q.accepted = false;
+      if (q.active && fabs(q.xd) > 1e20) {
+        q.status = ABS_ERR_DIVERGE;
+        q.active = false;
+        --n_active;
+      }
+    }
+    if (P > 1 && o.print_level > 0) fprintf(stderr, "batch iteration %4d: %d of %d problems active\n", iter, n_active, P);
+    if (o.print_level > 1) {
+      const auto ph5 = now();
+      fprintf(stderr,
+              "  phases [ms] eval+opt %.1f  factor(x%d) %.1f  refine %.1f  direction %.1f  line search(x%d) %.1f\n",
+              ms(ph0, ph1), n_fac_it, ms(ph1, ph2), ms(ph2, ph3), ms(ph3, ph4), n_ls_it, ms(ph4, ph5));
+    }
+    if (n_active == 0) break;
   }
   HIP_TRY(hipStreamSynchronize(st));
-  if (xout) hipLaunchKernelGGL(k_unscale, dim3(gx), dim3(BS), 0, st, W.xt, h.sc, nx, xout);
-  if (yout) hipLaunchKernelGGL(k_mul, dim3(gc), dim3(BS), 0, st, W.y, h.cs, nc, 0, yout);
-  HIP_TRY(hipStreamSynchronize(st));
-  if (res) {
-    res->status = status;
-    res->iterations = it;
-    res->E0 = E0;
-    res->inf_pr = inf_pr;
-    res->inf_du = inf_du;
-    res->compl_ = compl0;
-    res->d = xd * h.sc.Dd;
-    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    res->n_inertia_corrections = ncorr_tot;
-    res->n_factorizations = nfact;
-    res->max_lin_resid = max_rel;
+  if (xout || yout) {
+    TRY(upload_ps());
+    hipLaunchKernelGGL(k_output, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.y, h.cs, h.sc, nxs, xout, yout);
   }
-  return status;
+#undef TRY
+  HIP_TRY(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  int first_err = ABS_OK;
+  for (int p = 0; p < P; ++p) {
+    if (active0 && !active0[p]) continue;
+    const Prob& q = pr[(size_t)p];
+    if (q.status != ABS_OK && first_err == ABS_OK) first_err = q.status;
+    if (!res) continue;
+    absorber_ipm_result& r = res[p];
+    r.status = q.status;
+    r.iterations = q.it;
+    r.E0 = q.E0;
+    r.inf_pr = q.inf_pr;
+    r.inf_du = q.inf_du;
+    r.compl_ = q.compl0;
+    r.d = q.xd * h.sc.Dd;
+    r.seconds = secs;
+    r.n_inertia_corrections = q.ncorr;
+    r.n_factorizations = nfact;
+    r.max_lin_resid = max_rel;
+    r.feasibility_restarts = 0;
+  }
+  return first_err;
+}
+
+// Solve; then, with o.feasibility_restart, solve the problems that stopped
+// without converging once more from their simulated states (process
+// simulation of every scenario, d at its hydraulic minimum times 1 + 1e-3,
+// warm-start options).  The results of a restarted problem count both runs.
+int solve_with_restart(Handle& h, const absorber_ipm_options& o, const double* x0_dev, const double* y0_dev,
+                       double* xout, double* yout, absorber_ipm_result* res) {
+  const int P = h.P;
+  std::vector<absorber_ipm_result> r1((size_t)P);
+  int rc = ipm_solve(h, o, x0_dev, y0_dev, xout, yout, r1.data(), nullptr);
+  if (rc < 0 && rc > ABS_ERR_INERTIA) return rc;  // argument, device or allocation error
+  std::vector<unsigned char> redo((size_t)P, 0);
+  bool any = false;
+  for (int p = 0; p < P; ++p) {
+    const int s = r1[(size_t)p].status;
+    redo[(size_t)p] = o.feasibility_restart && (s == ABS_ERR_LS || s == ABS_ERR_INERTIA || s == ABS_ERR_MAXITER ||
+                                                 s == ABS_ERR_DIVERGE || s == ABS_ERR_NAN);
+    any = any || redo[(size_t)p];
+  }
+  if (any) {
+    double* xs = nullptr;
+    HIP_TRY(hipMalloc((void**)&xs, sizeof(double) * (size_t)h.nx));
+    std::vector<int> conv((size_t)P);
+    int it = 0;
+    int rs = initial_point(h, xs, h.stream);
+    if (!rs) rs = simulate(h, xs, redo.data(), 1e-10, 100, conv.data(), &it);
+    if (!rs) rs = set_hydraulic_diameters(h, xs, 1e-3, h.stream);
+    if (!rs) {
+      absorber_ipm_options ow = o;
+      ow.warm_start = 1;
+      std::vector<absorber_ipm_result> r2 = r1;
+      ipm_solve(h, ow, xs, nullptr, xout, yout, r2.data(), redo.data());
+      for (int p = 0; p < P; ++p)
+        if (redo[(size_t)p]) {
+          r2[(size_t)p].iterations += r1[(size_t)p].iterations;
+          r2[(size_t)p].n_inertia_corrections += r1[(size_t)p].n_inertia_corrections;
+          r2[(size_t)p].feasibility_restarts = 1;
+          r1[(size_t)p] = r2[(size_t)p];
+        }
+    }
+    (void)hipFree(xs);
+    if (rs) return rs;
+  }
+  rc = ABS_OK;
+  for (int p = 0; p < P; ++p) {
+    if (r1[(size_t)p].status != ABS_OK && rc == ABS_OK) rc = r1[(size_t)p].status;
+    if (res) res[p] = r1[(size_t)p];
+  }
+  return rc;
 }
 
 }  // namespace absorber
@@ -843,6 +1188,17 @@ void absorber_ipm_default_options(absorber_ipm_options* o) {
   o->nlp_scaling_max_gradient = 100.0;
   o->print_level = 0;
   o->use_graph = 0;
+  o->feasibility_restart = 1;
+}
+
+static int check_options(const absorber_ipm_options* opts, absorber_ipm_options* o, const char* who) {
+  if (opts) *o = *opts;
+  else absorber_ipm_default_options(o);
+  if (!(o->tol > 0) || o->max_iter < 0) {
+    set_error(std::string(who) + ": bad options");
+    return ABS_ERR_ARG;
+  }
+  return ABS_OK;
 }
 
 int absorber_ipm_solve(absorber_t* H, const absorber_ipm_options* opts, const double* x0_dev,
@@ -852,14 +1208,27 @@ int absorber_ipm_solve(absorber_t* H, const absorber_ipm_options* opts, const do
     set_error("absorber_ipm_solve: bad argument");
     return ABS_ERR_ARG;
   }
-  absorber_ipm_options o;
-  if (opts) o = *opts;
-  else absorber_ipm_default_options(&o);
-  if (!(o.tol > 0) || o.max_iter < 0) {
-    set_error("absorber_ipm_solve: bad options");
+  if (H->h.P != 1) {
+    set_error("absorber_ipm_solve: single-problem handles only (use absorber_batch_solve for a batch)");
     return ABS_ERR_ARG;
   }
-  return ipm_solve(H->h, o, x0_dev, lambda0_dev, x_out_dev, lambda_out_dev, result);
+  absorber_ipm_options o;
+  const int rc = check_options(opts, &o, "absorber_ipm_solve");
+  if (rc) return rc;
+  return solve_with_restart(H->h, o, x0_dev, lambda0_dev, x_out_dev, lambda_out_dev, result);
+}
+
+int absorber_batch_solve(absorber_t* H, const absorber_ipm_options* opts, const double* x0_dev,
+                         const double* lambda0_dev, double* x_out_dev, double* lambda_out_dev,
+                         absorber_ipm_result* results) {
+  if (!H || !results) {
+    set_error("absorber_batch_solve: bad argument");
+    return ABS_ERR_ARG;
+  }
+  absorber_ipm_options o;
+  const int rc = check_options(opts, &o, "absorber_batch_solve");
+  if (rc) return rc;
+  return solve_with_restart(H->h, o, x0_dev, lambda0_dev, x_out_dev, lambda_out_dev, results);
 }
 
 int absorber_kkt_solve(absorber_t* H, const double* rhs_dev, double* sol_dev, double* rel_resid_host, void* stream) {
@@ -868,6 +1237,10 @@ int absorber_kkt_solve(absorber_t* H, const double* rhs_dev, double* sol_dev, do
     return ABS_ERR_ARG;
   }
   Handle& h = H->h;
+  if (h.P != 1) {
+    set_error("absorber_kkt_solve: single-problem handles only");
+    return ABS_ERR_ARG;
+  }
   if (!h.factored) {
     set_error("absorber_kkt_solve: no factorisation (call absorber_kkt_factor first)");
     return ABS_ERR_STATE;

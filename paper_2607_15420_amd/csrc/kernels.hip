@@ -104,21 +104,23 @@ __device__ __forceinline__ void load_inflow(const double* __restrict__ x, const 
   }
 }
 
-// One thread per (scenario, stage): residuals (scaled by cs) and, if full, the
-// scaled stage record: Jacobian blocks and the Lagrangian Hessian block.
+// One thread per stage: residuals (scaled by cs) and, if full, the scaled stage
+// record: Jacobian blocks and the Lagrangian Hessian block.
 __global__ void k_eval(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ y,
-                       const double* __restrict__ cs, const double* __restrict__ feeds, ModelParams p, int N,
-                       int S, int full, double* __restrict__ cout, double* __restrict__ rec) {
+                       const double* __restrict__ cs, const double* __restrict__ feeds, ModelParams p,
+                       const StageInfo* __restrict__ sinfo, long long nst, int full, double* __restrict__ cout,
+                       double* __restrict__ rec) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)N * S) return;
-  const int w = (int)(t / N), n = (int)(t % N);
-  const double* feed = feeds + (long long)w * NF;
+  if (t >= nst) return;
+  const StageInfo si = sinfo[t];
+  const int n = si.n, N = si.N;
+  const double* feed = feeds + (long long)si.w * NF;
   double z[NV];
   load_stage(x, sc, scaled, t, z);
   Inflow f;
   load_inflow(x, sc, scaled, t, n, N, feed, f);
-  const long long nx = (long long)N * S * NV;
-  const double d = scaled ? x[nx] * sc.Dd : x[nx];
+  const long long xd = nst * NV + si.p;
+  const double d = scaled ? x[xd] * sc.Dd : x[xd];
   const double P = feed[17];
   double csr[NR];
 #pragma unroll
@@ -149,17 +151,19 @@ __global__ void k_eval(const double* __restrict__ x, Scaling sc, int scaled, con
 
 // maximum |d c~_r / d xt| over the whole row (for gradient-based row scaling)
 __global__ void k_rowmax(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ feeds,
-                         ModelParams p, int N, int S, double* __restrict__ rowmax) {
+                         ModelParams p, const StageInfo* __restrict__ sinfo, long long nst,
+                         double* __restrict__ rowmax) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)N * S) return;
-  const int w = (int)(t / N), n = (int)(t % N);
-  const double* feed = feeds + (long long)w * NF;
+  if (t >= nst) return;
+  const StageInfo si = sinfo[t];
+  const int n = si.n, N = si.N;
+  const double* feed = feeds + (long long)si.w * NF;
   double z[NV];
   load_stage(x, sc, scaled, t, z);
   Inflow f;
   load_inflow(x, sc, scaled, t, n, N, feed, f);
-  const long long nx = (long long)N * S * NV;
-  const double d = scaled ? x[nx] * sc.Dd : x[nx];
+  const long long xd = nst * NV + si.p;
+  const double d = scaled ? x[xd] * sc.Dd : x[xd];
   double m[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) m[r] = 0.0;
@@ -485,21 +489,26 @@ __device__ __forceinline__ void backward_stage(const double* __restrict__ sb, do
 }
 
 template <int WITH_RHS>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void k_factor(const double* __restrict__ rec, const int* __restrict__ gather,
-                                                 const double* __restrict__ rhs, const double* __restrict__ diagx,
-                                                 const double* __restrict__ diags, double dw, double dc, int N, int S,
-                                                 int jd, double* __restrict__ slots, double* __restrict__ solr,
-                                                 double* __restrict__ solb, int* __restrict__ inert,
-                                                 double* __restrict__ part) {
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void k_factor(
+    const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
+    const double* __restrict__ diagx, const double* __restrict__ diags, const double* __restrict__ dwv,
+    const double* __restrict__ dcv, const int* __restrict__ chain0, const int* __restrict__ chain_p,
+    const int* __restrict__ fmask, int W, int jd, double* __restrict__ slots, double* __restrict__ solr,
+    double* __restrict__ solb, int* __restrict__ inert, double* __restrict__ part) {
   __shared__ WaveLDS L;
   const int w = blockIdx.x;
-  if (w >= S) return;
+  if (w >= W) return;
+  const int pw = chain_p[w];
+  if (fmask && !fmask[pw]) return;  // this problem keeps its factorisation
+  const long long t0 = chain0[w];
+  const int N = chain0[w + 1] - (int)t0;
+  const double dw = dwv[pw], dc = dcv[pw];
   const int lane = lane_id();
   for (int i = lane; i < NC * (NC + 2); i += WAVE) L.src[SRC_CTB + i] = 0.0;
   if (lane == 0) L.src[SRC_ZERO] = 0.0;
   int npos = 0, nneg = 0, nzero = 0;
   for (int n = 0; n < N; ++n) {
-    const long long t = (long long)w * N + n;
+    const long long t = t0 + n;
     const double* R = rec + t * REC;
     double v[FR];
     for (int i = lane; i < REC; i += WAVE) L.src[SRC_REC + i] = R[i];
@@ -537,7 +546,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void 
   __syncthreads();
   double sigb = 0.0, sigr = 0.0, wdd = 0.0;
   for (int n = N - 1; n >= 0; --n) {
-    const long long t = (long long)w * N + n;
+    const long long t = t0 + n;
     const double* sb = slots + t * NK * SLOT;
     const int ls = lane < NK ? lane : 0;
     const double yr = sb[ls * SLOT + FR_R], yb = sb[ls * SLOT + FR_B];
@@ -575,15 +584,18 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void 
 
 // Forward and backward substitution with stored pivot columns: solr <- K_w^{-1} rhs.
 __global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
-                                                const double* __restrict__ rhs, int N, int S, int jd,
-                                                double* __restrict__ solr, double* __restrict__ part) {
+                                                const double* __restrict__ rhs, const int* __restrict__ chain0,
+                                                int W, int jd, double* __restrict__ solr,
+                                                double* __restrict__ part) {
   __shared__ double sh[WAVE];
   const int w = blockIdx.x;
-  if (w >= S) return;
+  if (w >= W) return;
+  const long long t0 = chain0[w];
+  const int N = chain0[w + 1] - (int)t0;
   const int lane = lane_id();
   double ctb = 0.0;  // contribution carried by coupling lane 43+a to stage n+1's index R[a]
   for (int n = 0; n < N; ++n) {
-    const long long t = (long long)w * N + n;
+    const long long t = t0 + n;
     const double* sb = slots + t * NK * SLOT;
     sh[lane] = 0.0;
     __syncthreads();
@@ -633,7 +645,7 @@ __global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, 
   __syncthreads();
   double sig = 0.0;
   for (int n = N - 1; n >= 0; --n) {
-    const long long t = (long long)w * N + n;
+    const long long t = t0 + n;
     const double* sb = slots + t * NK * SLOT;
     const double y = lane < NK ? solr[t * NK + lane] : 0.0;
     double x_s, unused;
@@ -652,15 +664,22 @@ __global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, 
 
 // Schur complement on d.  Fixed-order reduction of the per-scenario partials:
 // sigma_b = sum b^T K^{-1} b, sigma_r = sum b^T K^{-1} r, W_dd and the inertia.
-__global__ void k_schur(const double* __restrict__ part, const int* __restrict__ inert, int S,
-                        const double* __restrict__ diagd, double dw, const double* __restrict__ rd, int mode,
-                        DevScalars* __restrict__ out) {
+// One block per problem: sums over the problem's chains (fixed order), then
+// S_d = k_dd - sigma_b with k_dd = sum W_dd + Sigma_d + delta_w, the inertia
+// (Haynsworth: the chains' counts plus the sign of S_d) and
+// dd = (r_d - sigma_r) / S_d.
+__global__ void k_schur(const double* __restrict__ part, const int* __restrict__ inert, const int* __restrict__ pchain,
+                        const double* __restrict__ diagd, const double* __restrict__ dwv, const double* __restrict__ rd,
+                        int mode, DevScalars* __restrict__ outv) {
   // mode 0: factor only; 1: factor with a right-hand side; 2: right-hand side only
   __shared__ double sb[256], sr[256], sw[256];
   __shared__ long long ip[256], in_[256], iz[256];
+  const int pb = blockIdx.x;
+  const int w0 = pchain[pb], w1 = pchain[pb + 1];
+  DevScalars* out = outv + pb;
   double ab = 0, ar = 0, aw = 0;
   long long p = 0, q = 0, z = 0;
-  for (int w = threadIdx.x; w < S; w += blockDim.x) {
+  for (int w = w0 + threadIdx.x; w < w1; w += blockDim.x) {
     ab += part[w * 4 + 0];
     ar += part[w * 4 + 1];
     aw += part[w * 4 + 2];
@@ -690,7 +709,7 @@ __global__ void k_schur(const double* __restrict__ part, const int* __restrict__
     if (mode != 2) {
       out->sig_b = sb[0];
       out->wdd = sw[0];
-      out->kdd = sw[0] + *diagd + dw;
+      out->kdd = sw[0] + diagd[pb] + dwv[pb];
       out->sd = out->kdd - sb[0];
       long long np = ip[0], nn = in_[0], nz = iz[0];
       if (out->sd > 0.0) ++np;
@@ -702,19 +721,19 @@ __global__ void k_schur(const double* __restrict__ part, const int* __restrict__
     }
     if (mode != 0) {
       out->sig_r = sr[0];
-      out->rd = *rd;
-      out->dd = (*rd - sr[0]) / out->sd;
+      out->rd = rd[pb];
+      out->dd = (rd[pb] - sr[0]) / out->sd;
     }
   }
 }
 
-// sol = solr - solb * dd (scenario part), sol[last] = dd
+// sol = solr - solb * dd_p on the stage entries, sol[d_p] = dd_p
 __global__ void k_combine(const double* __restrict__ solr, const double* __restrict__ solb,
-                          const DevScalars* __restrict__ sc, long long nk, double* __restrict__ sol) {
+                          const DevScalars* __restrict__ sc, const StageInfo* __restrict__ sinfo, long long nk,
+                          int P, double* __restrict__ sol) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const double dd = sc->dd;
-  if (i < nk) sol[i] = solr[i] - solb[i] * dd;
-  if (i == nk) sol[nk] = dd;
+  if (i < nk) sol[i] = solr[i] - solb[i] * sc[sinfo[i / NK].p].dd;
+  else if (i < nk + P) sol[i] = sc[i - nk].dd;
 }
 
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, long long n) {
@@ -730,17 +749,21 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
 constexpr int RES_BS = 64;
 __global__ __launch_bounds__(RES_BS) void k_residual(const double* __restrict__ rec, const int* __restrict__ jtab,
                                                      const double* __restrict__ diagx, const double* __restrict__ diags,
-                                                     double dw, double dc, const double* __restrict__ sol,
-                                                     const double* __restrict__ rhs, int N, int S, int jd,
-                                                     double* __restrict__ res, double* __restrict__ bpart) {
+                                                     const double* __restrict__ dwv, const double* __restrict__ dcv,
+                                                     const double* __restrict__ sol, const double* __restrict__ rhs,
+                                                     const StageInfo* __restrict__ sinfo, long long nst, int jd,
+                                                     double* __restrict__ res, double* __restrict__ stage_d,
+                                                     double* __restrict__ bmax) {
   __shared__ double ku[NK][RES_BS], ka[NK][RES_BS];
-  __shared__ double r0[RES_BS], r1[RES_BS], r2[RES_BS];
+  __shared__ double r2[RES_BS];
   const int tid = threadIdx.x;
   const long long t = (long long)blockIdx.x * RES_BS + tid;
-  double dp = 0.0, da = 0.0, om = 0.0;
-  if (t < (long long)N * S) {
-    const int n = (int)(t % N);
-    const long long nkk = (long long)N * S * NK;
+  double om = 0.0;
+  if (t < nst) {
+    const StageInfo si = sinfo[t];
+    const int n = si.n, N = si.N;
+    const double dw = dwv[si.p], dc = dcv[si.p];
+    const long long nkk = nst * NK + si.p;  // this problem's d unknown
     const double* R = rec + t * REC;
     const double* u = sol + t * NK;
 #define KU(k) ku[k][tid]
@@ -833,61 +856,74 @@ __global__ __launch_bounds__(RES_BS) void k_residual(const double* __restrict__ 
     }
 #undef KU
 #undef KA
-    dp = R[jd] * u[NK - 1];
-    da = fabs(dp);
+    const double dp = R[jd] * u[NK - 1];
+    stage_d[2 * t] = dp;
+    stage_d[2 * t + 1] = fabs(dp);
   }
-  r0[tid] = dp;
-  r1[tid] = da;
   r2[tid] = om;
   __syncthreads();
   for (int s = RES_BS / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      r0[tid] += r0[tid + s];
-      r1[tid] += r1[tid + s];
-      r2[tid] = fmax(r2[tid], r2[tid + s]);
-    }
+    if (tid < s) r2[tid] = fmax(r2[tid], r2[tid + s]);
     __syncthreads();
   }
-  if (tid == 0) {
-    bpart[blockIdx.x * 3 + 0] = r0[0];
-    bpart[blockIdx.x * 3 + 1] = r1[0];
-    bpart[blockIdx.x * 3 + 2] = r2[0];
-  }
+  if (tid == 0) bmax[blockIdx.x] = r2[0];
 }
 
-// d row of the residual from the block partials (one block, fixed order):
-// res_d = rhs_d - sum b u_hyd - kdd u_d; omega_out[0] = largest backward error
-// of the scenario rows, omega_out[1] = that of the d row
-__global__ void k_residual_d(const double* __restrict__ bpart, int nb, const DevScalars* __restrict__ sc,
-                             const double* __restrict__ sol, const double* __restrict__ rhs, long long nkk,
-                             double* __restrict__ res, double* __restrict__ omega_out) {
-  __shared__ double s1[256], s2[256], s3[256];
-  double a = 0, b = 0, m = 0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    a += bpart[i * 3 + 0];
-    b += bpart[i * 3 + 1];
-    m = fmax(m, bpart[i * 3 + 2]);
+// d row of each problem's residual (one block per problem, fixed order):
+// res_d = rhs_d - sum b u_hyd - kdd u_d; omd[p] = its backward error
+__global__ void k_residual_d(const double* __restrict__ stage_d, const long long* __restrict__ pstage,
+                             const DevScalars* __restrict__ scv, const double* __restrict__ sol,
+                             const double* __restrict__ rhs, long long nkk, double* __restrict__ res,
+                             double* __restrict__ omd) {
+  __shared__ double s1[256], s2[256];
+  const int pb = blockIdx.x;
+  double a = 0, b = 0;
+  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += blockDim.x) {
+    a += stage_d[2 * t];
+    b += stage_d[2 * t + 1];
   }
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = b;
-  s3[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
       s1[threadIdx.x] += s1[threadIdx.x + s];
       s2[threadIdx.x] += s2[threadIdx.x + s];
-      s3[threadIdx.x] = fmax(s3[threadIdx.x], s3[threadIdx.x + s]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double ku = s1[0] + sc->kdd * sol[nkk];
-    const double ka = s2[0] + fabs(sc->kdd * sol[nkk]);
-    const double rr = rhs[nkk] - ku;
-    res[nkk] = rr;
-    const double den = ka + fabs(rhs[nkk]);
-    omega_out[0] = s3[0];
-    omega_out[1] = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
+    const long long i = nkk + pb;
+    const double kdd = scv[pb].kdd;
+    const double ku = s1[0] + kdd * sol[i];
+    const double ka = s2[0] + fabs(kdd * sol[i]);
+    const double rr = rhs[i] - ku;
+    res[i] = rr;
+    const double den = ka + fabs(rhs[i]);
+    omd[pb] = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
+  }
+}
+
+// omega_out[0] = max of the block maxima, omega_out[1] = max over the problems' d rows
+__global__ void k_residual_max(const double* __restrict__ bmax, int nb, const double* __restrict__ omd, int P,
+                               double* __restrict__ omega_out) {
+  __shared__ double s1[256], s2[256];
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) a = fmax(a, bmax[i]);
+  for (int i = threadIdx.x; i < P; i += blockDim.x) b = fmax(b, omd[i]);
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + s]);
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    omega_out[0] = s1[0];
+    omega_out[1] = s2[0];
   }
 }
 
@@ -903,18 +939,16 @@ hipError_t launch_eval(Handle& h, const double* x, int scaled, const double* y, 
 
 hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling& sc, const double* cs,
                            const double* y, int full, double* c_out, hipStream_t st) {
-  const long long nst = (long long)h.N * h.S;
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_eval, dim3(grid_for(nst, 128)), dim3(128), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp, h.N,
-                     h.S, full, c_out, h.rec);
+  hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, 128)), dim3(128), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
+                     h.sinfo, h.nst, full, c_out, h.rec);
   prof_end(h, 2, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rowmax(Handle& h, const double* x, int scaled, double* rowmax, hipStream_t st) {
-  const long long nst = (long long)h.N * h.S;
-  hipLaunchKernelGGL(k_rowmax, dim3(grid_for(nst, 128)), dim3(128), 0, st, x, h.sc, scaled, h.feeds, h.mp, h.N,
-                     h.S, rowmax);
+  hipLaunchKernelGGL(k_rowmax, dim3(grid_for(h.nst, 128)), dim3(128), 0, st, x, h.sc, scaled, h.feeds, h.mp, h.sinfo,
+                     h.nst, rowmax);
   return hipGetLastError();
 }
 
@@ -932,18 +966,17 @@ hipError_t launch_hess_coo(Handle& h, const double* x, const double* lam, double
   return hipGetLastError();
 }
 
-hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, double dw, double dc,
-                         const double* rhs, hipStream_t st) {
+hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
+                         hipStream_t st) {
+  const int* fm = mask ? h.fmask : nullptr;
   prof_begin(h, st);
   if (rhs)
-    hipLaunchKernelGGL(k_factor<1>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, dw, dc, h.N,
-                       h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
+    hipLaunchKernelGGL(k_factor<1>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, h.dcv,
+                       h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
   else
-    hipLaunchKernelGGL(k_factor<0>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, dw, dc, h.N,
-                       h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
+    hipLaunchKernelGGL(k_factor<0>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, h.dcv,
+                       h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
   prof_end(h, 0, st);
-  h.fdw = dw;
-  h.fdc = dc;
   h.factored = true;
   ++h.n_factor;
   return hipGetLastError();
@@ -951,33 +984,38 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, do
 
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_solve, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.N, h.S, h.jac_d_index, h.solr,
-                     h.part);
+  hipLaunchKernelGGL(k_solve, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.S, h.jac_d_index,
+                     h.solr, h.part);
   prof_end(h, 1, st);
   ++h.n_solve;
   return hipGetLastError();
 }
 
-hipError_t launch_schur(Handle& h, const double* diagd, double dw, const double* rd, int mode, double* sol,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_schur, dim3(1), dim3(256), 0, st, h.part, h.inert, h.S, diagd, dw, rd, mode, h.scal);
+hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st) {
+  const double* rd = rhs ? rhs + h.nst * NK : nullptr;
+  hipLaunchKernelGGL(k_schur, dim3(h.P), dim3(256), 0, st, h.part, h.inert, h.pchain, diagx + h.nst * NV, h.dwv, rd,
+                     mode, h.scal);
   if (mode != 0 && sol) {
-    const long long nk = (long long)h.N * h.S * NK;
-    hipLaunchKernelGGL(k_combine, dim3(grid_for(nk + 1, 256)), dim3(256), 0, st, h.solr, h.solb, h.scal, nk, sol);
+    const long long nk = h.nst * NK;
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(nk + h.P, 256)), dim3(256), 0, st, h.solr, h.solb, h.scal, h.sinfo,
+                       nk, h.P, sol);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, double dw, double dc,
-                           const double* sol, const double* rhs, double* res, double* omega_out, hipStream_t st) {
-  const long long nst = (long long)h.N * h.S;
-  const long long nkk = nst * NK;
-  const int nb = (int)grid_for(nst, RES_BS);  // block partials in kden (3 per block)
+hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
+                           const double* rhs, double* res, double* omega_out, hipStream_t st) {
+  const long long nkk = h.nst * NK;
+  const int nb = (int)grid_for(h.nst, RES_BS);
+  double* stage_d = h.kden;               // 2 per stage
+  double* bmax = h.kden + 2 * h.nst;      // one per block
+  double* omd = bmax + nb;                // one per problem
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_BS), 0, st, h.rec, h.jtab, diagx, diags, dw, dc, sol, rhs, h.N,
-                     h.S, h.jac_d_index, res, h.kden);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_BS), 0, st, h.rec, h.jtab, diagx, diags, h.dwv, h.dcv, sol, rhs,
+                     h.sinfo, h.nst, h.jac_d_index, res, stage_d, bmax);
   prof_end(h, 3, st);
-  hipLaunchKernelGGL(k_residual_d, dim3(1), dim3(256), 0, st, h.kden, nb, h.scal, sol, rhs, nkk, res, omega_out);
+  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, stage_d, h.pstage, h.scal, sol, rhs, nkk, res, omd);
+  hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(256), 0, st, bmax, nb, omd, h.P, omega_out);
   return hipGetLastError();
 }
 

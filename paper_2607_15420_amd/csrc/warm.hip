@@ -42,42 +42,36 @@ __global__ void k_targets(const double* __restrict__ x, long long n, float* __re
   T[i] = (float)(k < NLOG ? log(fmax(v, LOG_FLOOR)) : v);
 }
 
-// decode the predicted stage vectors; per-block maxima of the hydraulic diameter
-__global__ void k_decode(const float* __restrict__ Y, const double* __restrict__ feeds, ModelParams p, int N,
-                         long long nst, double* __restrict__ x0, double* __restrict__ part) {
-  __shared__ double sm[WB];
+// decode the predicted stage vectors; each stage's hydraulic diameter into dh
+__global__ void k_decode(const float* __restrict__ Y, const double* __restrict__ feeds, ModelParams p,
+                         const StageInfo* __restrict__ sinfo, long long nst, double* __restrict__ x0,
+                         double* __restrict__ dh) {
   const long long t = (long long)blockIdx.x * WB + threadIdx.x;
-  double dh = 0.0;
-  if (t < nst) {
-    const float* y = Y + t * NV;
-    double* z = x0 + t * NV;
+  if (t >= nst) return;
+  const float* y = Y + t * NV;
+  double* z = x0 + t * NV;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) z[k] = k < NLOG ? exp((double)y[k]) : (double)y[k];
-    const double P = feeds[(t / N) * NF + 17];
-    const double V = z[IV], T = z[IT];
-    const double a = 4.0 * V * p.R * T / (M_PI * p.u_max * P);
-    dh = a > 0.0 ? sqrt(a) : 0.0;
-  }
-  sm[threadIdx.x] = dh;
-  __syncthreads();
-  for (int s = WB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+  for (int k = 0; k < NV; ++k) z[k] = k < NLOG ? exp((double)y[k]) : (double)y[k];
+  const double P = feeds[(long long)sinfo[t].w * NF + 17];
+  const double V = z[IV], T = z[IT];
+  const double a = 4.0 * V * p.R * T / (M_PI * p.u_max * P);
+  dh[t] = a > 0.0 ? sqrt(a) : 0.0;
 }
 
-__global__ void k_decode_d(const double* __restrict__ part, int nb, double margin, double* __restrict__ d0) {
+// d_p = (1 + margin) * the largest hydraulic diameter of problem p (one block per problem)
+__global__ void k_decode_d(const double* __restrict__ dh, const long long* __restrict__ pstage, double margin,
+                           double* __restrict__ d0) {
   __shared__ double sm[WB];
+  const int pb = blockIdx.x;
   double m = 0.0;
-  for (int i = threadIdx.x; i < nb; i += WB) m = fmax(m, part[i]);
+  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += WB) m = fmax(m, dh[t]);
   sm[threadIdx.x] = m;
   __syncthreads();
   for (int s = WB / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *d0 = (1.0 + margin) * sm[0];
+  if (threadIdx.x == 0) d0[pb] = (1.0 + margin) * sm[0];
 }
 
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -109,7 +103,7 @@ int absorber_warm_targets(absorber_t* ah, const double* x_dev, float* T_dev, voi
     return ABS_ERR_ARG;
   }
   Handle& h = ah->h;
-  const long long n = h.nx - 1;
+  const long long n = h.nst * NV;
   hipLaunchKernelGGL(absorber::k_targets, dim3(absorber::nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x_dev,
                      n, T_dev);
   HIP_TRY(hipGetLastError());
@@ -122,17 +116,13 @@ int absorber_warm_point(absorber_t* ah, const float* Y_dev, double d_margin, dou
     return ABS_ERR_ARG;
   }
   Handle& h = ah->h;
-  const long long nst = (long long)h.N * h.S;
-  const int nb = (int)absorber::nblk(nst, absorber::WB);
-  if (nb > h.red_cap) {
-    set_error("absorber_warm_point: problem too large for the reduction buffer");
-    return ABS_ERR_ARG;
-  }
+  const long long nst = h.nst;
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(absorber::k_decode, dim3(nb), dim3(absorber::WB), 0, st, Y_dev, h.feeds, h.mp, h.N, nst, x0_dev,
-                     h.redbuf);
-  hipLaunchKernelGGL(absorber::k_decode_d, dim3(1), dim3(absorber::WB), 0, st, h.redbuf, nb, d_margin,
-                     x0_dev + (h.nx - 1));
+  double* dh = h.kden;  // per-stage scratch
+  hipLaunchKernelGGL(absorber::k_decode, dim3(absorber::nblk(nst, absorber::WB)), dim3(absorber::WB), 0, st, Y_dev,
+                     h.feeds, h.mp, h.sinfo, nst, x0_dev, dh);
+  hipLaunchKernelGGL(absorber::k_decode_d, dim3(h.P), dim3(absorber::WB), 0, st, dh, h.pstage, d_margin,
+                     x0_dev + nst * NV);
   HIP_TRY(hipGetLastError());
   return ABS_OK;
 }
@@ -146,8 +136,10 @@ int absorber_warm_start(absorber_t* ah, absorber_mlp* net, float* X_work_dev, fl
   absorber_mlp_config cfg;
   int rc = absorber_mlp_get_config(net, &cfg);
   if (rc) return rc;
-  if (cfg.n_in != 3 || cfg.n_out != NV * ah->h.N) {
-    set_error("absorber_warm_start: the network needs 3 inputs and 21 N outputs");
+  bool fits = cfg.n_in == 3;
+  for (int n : ah->h.pN) fits = fits && cfg.n_out == NV * n;
+  if (!fits) {
+    set_error("absorber_warm_start: the network needs 3 inputs and 21 N outputs (every problem N stages)");
     return ABS_ERR_ARG;
   }
   rc = absorber_warm_features(ah, X_work_dev, stream);
@@ -162,10 +154,14 @@ int absorber_warm_solve(absorber_t* ah, absorber_mlp* net, const absorber_ipm_op
     set_error("absorber_warm_solve: bad argument");
     return ABS_ERR_ARG;
   }
+  if (ah->h.P != 1) {
+    set_error("absorber_warm_solve: single-problem handles only");
+    return ABS_ERR_ARG;
+  }
   Handle& h = ah->h;
   if (!h.warm_X) {
     HIP_TRY(hipMalloc((void**)&h.warm_X, sizeof(float) * 3 * (size_t)h.S));
-    HIP_TRY(hipMalloc((void**)&h.warm_Y, sizeof(float) * (size_t)NV * h.N * h.S));
+    HIP_TRY(hipMalloc((void**)&h.warm_Y, sizeof(float) * (size_t)NV * h.nst));
     HIP_TRY(hipMalloc((void**)&h.warm_x0, sizeof(double) * (size_t)h.nx));
   }
   const auto t0 = std::chrono::steady_clock::now();

@@ -1,0 +1,136 @@
+"""The batched form: independent design problems of uneven stage and scenario
+counts in one handle, solved together by one interior-point run in which each
+problem keeps its own barrier parameter, filter, steps and regularisation.
+
+Each problem is checked against its closed-form optimum (independent
+per-scenario Newton simulations, oracle) and against its own single-problem
+solve.  Tolerances as for the single solve: d relative error <= 1e-6, E_0 <= 1e-8.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from absorber_inputs import CONFIGS, feed_table, perturbations
+from oracle import model as M
+from oracle import simulate
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _problems(params, Ns, Ss, amp, seed):
+    return [(N, feed_table(perturbations(S, amp, seed + p), params)) for p, (N, S) in enumerate(zip(Ns, Ss))]
+
+
+def _states_of(x, problems):
+    out, o = [], 0
+    for N, F in problems:
+        n = N * F.shape[0] * M.NV
+        out.append(x[o:o + n].reshape(F.shape[0], N, M.NV))
+        o += n
+    return out
+
+
+def test_uneven_batch_matches_closed_form_and_single_solves(params):
+    from paper_2607_15420_amd import Absorber
+    problems = _problems(params, [8, 10, 13, 6, 20], [3, 7, 1, 12, 4], 0.15, 100)
+    h = Absorber.batch(params, problems)
+    assert h.P == 5 and h.nx == 21 * sum(N * F.shape[0] for N, F in problems) + 5
+    x = torch.empty(h.nx, dtype=torch.float64, device=DEV)
+    rc, res = h.batch_solve(x_out=x)
+    torch.cuda.synchronize()
+    assert rc == 0, [r.as_dict() for r in res]
+    xh = x.cpu().numpy()
+    nxs = h.nx - h.P
+    Zb = _states_of(xh[:nxs], problems)
+    for p, ((N, F), r) in enumerate(zip(problems, res)):
+        assert r.status == 0 and r.E0 <= 1e-8, (p, r.as_dict())
+        assert xh[nxs + p] == pytest.approx(r.d, rel=1e-14)
+        dstar, _, Zs, ok = simulate.closed_form_diameter(F, N, params)
+        assert ok.all()
+        assert abs(r.d - dstar) / dstar <= 1e-6, (p, r.d, dstar)
+        assert np.abs(Zb[p] - Zs).max() / np.abs(Zs).max() <= 1e-8, p
+        hs = Absorber(params, N, F)
+        rs = hs.ipm_solve()
+        hs.close()
+        assert rs.status == 0
+        assert abs(rs.d - r.d) / r.d <= 1e-8, (p, rs.d, r.d)
+    h.close()
+
+
+def test_identical_problems_follow_the_single_trajectory(params):
+    from paper_2607_15420_amd import Absorber
+    w = CONFIGS["C1"]
+    F = w.feeds(params)
+    hs = Absorber(params, w.n_stages, F)
+    rs = hs.ipm_solve()
+    hs.close()
+    h = Absorber.batch(params, [(w.n_stages, F)] * 3)
+    rc, res = h.batch_solve()
+    h.close()
+    assert rc == 0
+    for r in res:
+        assert r.iterations == rs.iterations
+        assert r.d == pytest.approx(rs.d, rel=1e-12)
+
+
+def test_batch_handle_rejects_single_problem_calls(params):
+    from paper_2607_15420_amd import Absorber, AbsorberError
+    problems = _problems(params, [4, 5], [2, 1], 0.1, 7)
+    h = Absorber.batch(params, problems)
+    x = torch.zeros(h.nx, dtype=torch.float64, device=DEV)
+    vals = torch.empty(10, dtype=torch.float64, device=DEV)
+    with pytest.raises(AbsorberError):
+        h.eval_jac(x, vals)
+    from paper_2607_15420_amd import lib
+    assert lib().absorber_ipm_solve(h.h, None, None, None, None, None, None) == -1  # ABS_ERR_ARG
+    # residual evaluation works on the union layout
+    h.initial_point(x)
+    c = torch.empty(h.nc, dtype=torch.float64, device=DEV)
+    h.eval_cons(x, c)
+    torch.cuda.synchronize()
+    assert torch.isfinite(c).all()
+    h.close()
+
+
+def test_simulation_matches_oracle(params):
+    """Process simulation (damped Newton on every scenario's MESH block) against
+    the oracle's independent per-scenario Newton solves."""
+    from paper_2607_15420_amd import Absorber
+    problems = _problems(params, [8, 20], [4, 3], 0.15, 104)
+    h = Absorber.batch(params, problems)
+    x = torch.empty(h.nx, dtype=torch.float64, device=DEV)
+    h.initial_point(x)
+    conv, it = h.simulate(x)
+    assert conv.all() and it < 100
+    xh = x.cpu().numpy()
+    nxs = h.nx - h.P
+    for p, ((N, F), Z) in enumerate(zip(problems, _states_of(xh[:nxs], problems))):
+        dstar, _, Zs, ok = simulate.closed_form_diameter(F, N, params)
+        assert ok.all()
+        assert np.abs(Z - Zs).max() / np.abs(Zs).max() <= 1e-9, p
+        assert xh[nxs + p] == pytest.approx(dstar, rel=1e-9)
+    h.close()
+
+
+def test_tall_column_fails_cold_like_the_oracle_and_restarts(params):
+    """20 stages: the cold-started method stops with a line-search failure at the
+    same iteration and diameter as the oracle; the feasibility restart then
+    reaches the closed-form optimum."""
+    from paper_2607_15420_amd import Absorber
+    from oracle import ipm as oipm
+    F = feed_table(perturbations(4, 0.15, 104), params)[1:2]
+    N = 20
+    ro = oipm.solve(params, F, N)
+    assert ro.status == -11
+    h = Absorber(params, N, F)
+    r0 = h.ipm_solve(Absorber.default_options(feasibility_restart=0))
+    assert r0.status == -11 and r0.iterations == ro.iterations
+    assert r0.d == pytest.approx(ro.d, rel=1e-8)
+    r1 = h.ipm_solve()
+    dstar, _, _, ok = simulate.closed_form_diameter(F, N, params)
+    assert ok.all()
+    assert r1.status == 0 and r1.E0 <= 1e-8 and r1.feasibility_restarts == 1
+    assert abs(r1.d - dstar) / dstar <= 1e-6
+    h.close()
