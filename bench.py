@@ -148,6 +148,56 @@ def warm_leg(params, steps: int, epochs: int):
     }
 
 
+def batch_leg(params, n_problems: int, sequential: bool):
+    """64 independent design problems (stages uniform in 8-60, scenarios
+    log-uniform in 50-2000, feeds +-15%, seed 5) solved as one batch, against
+    solving them one after another with the same solver."""
+    import numpy as np
+    import torch
+    from absorber_inputs import batch_problems, feed_table
+    from paper_2607_15420_amd import Absorber
+
+    probs = [(N, feed_table(pert, params)) for N, pert in batch_problems()[:n_problems]]
+    n_chains = sum(f.shape[0] for _, f in probs)
+    n_stages = sum(N * f.shape[0] for N, f in probs)
+    opts = Absorber.default_options()
+    h = Absorber.batch(params, probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, res = h.batch_solve(opts)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    h.close()
+    out = {
+        "workload": f"C5: {len(probs)} problems, stages uniform 8-60, scenarios log-uniform 50-2000, feeds +-15%, "
+                    f"seed 5 ({n_chains} scenarios, {n_stages} stages in all)",
+        "batched_s": t_batch, "batched_converged": int(sum(r.status == 0 for r in res)),
+        "batched_restarted": int(sum(r.feasibility_restarts for r in res)),
+        "batched_solves_per_s": len(probs) / t_batch,
+        "max_iterations": int(max(r.iterations for r in res)),
+    }
+    print(f"bench: batch of {len(probs)} solved in {t_batch:.2f} s", file=sys.stderr, flush=True)
+    if sequential:
+        t_seq, conv, d_agree = 0.0, 0, 0
+        for p, (N, F) in enumerate(probs):
+            hs = Absorber(params, N, F)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = hs.ipm_solve(opts)
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t0
+            hs.close()
+            conv += r.status == 0
+            if r.status == 0 and res[p].status == 0 and abs(r.d - res[p].d) <= 1e-6 * r.d:
+                d_agree += 1
+            if p % 8 == 7:
+                print(f"bench: sequential {p + 1}/{len(probs)}, {t_seq:.1f} s", file=sys.stderr, flush=True)
+        out.update({"sequential_s": t_seq, "sequential_converged": int(conv),
+                    "sequential_solves_per_s": len(probs) / t_seq, "speedup": t_seq / t_batch,
+                    "d_agree_1e-6": int(d_agree)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +208,9 @@ def main():
     ap.add_argument("--cpu-scen", type=int, default=16)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
+    ap.add_argument("--batch-problems", type=int, default=64)
+    ap.add_argument("--no-sequential", action="store_true", help="batched leg without the sequential comparison")
     ap.add_argument("--warm-epochs", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -240,8 +293,12 @@ def main():
                     "paper_hardware": "1x H200 / Xeon 8568Y+ 1 thread; other model constants and data"},
     }
     h.close()
+    print(f"bench: headline {ms_per_step:.1f} ms per solve", file=sys.stderr, flush=True)
     if not args.no_warm:
         out["warm_start"] = warm_leg(params, args.steps, args.warm_epochs)
+        print("bench: warm-start leg done", file=sys.stderr, flush=True)
+    if not args.no_batch:
+        out["batch"] = batch_leg(params, args.batch_problems, not args.no_sequential)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, feeds, N, r.iterations, args.cpu_scen, args.cpu_iters)
     print(json.dumps(out), flush=True)

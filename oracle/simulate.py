@@ -41,7 +41,8 @@ def simulate_scenario(Z0: np.ndarray, feed: np.ndarray, P: M.OracleParams, tol: 
     Newton's method on F(Z) = 0 with the mole fractions carried as their
     logarithms (this keeps them positive and leaves the solution unchanged), the
     rows scaled by their Jacobian row maxima at the start, log-steps capped at 5
-    and backtracking on the scaled residual inf-norm.
+    and backtracking on the scaled residual inf-norm (stopping when even a step
+    of 1e-10 gives no decrease).
     Returns (Z, converged, iterations, final scaled residual inf-norm).
     """
     N = Z0.shape[0]
@@ -71,14 +72,20 @@ def simulate_scenario(Z0: np.ndarray, feed: np.ndarray, P: M.OracleParams, tol: 
         big = float(du[lm].abs().max())
         if big > 5.0:
             a = 5.0 / big
+        stalled = False
         while True:
             ut = u + a * du
             rt = F(ut) * rs
             nt = float(rt.abs().max())
-            if (math.isfinite(nt) and nt < (1.0 - 1e-4 * a) * nr) or a < 1e-10:
+            if math.isfinite(nt) and nt < (1.0 - 1e-4 * a) * nr:
+                break
+            if a < 1e-10:  # no decrease even for a tiny step: give up
+                stalled = True
                 break
             a *= 0.5
         u, r, nr = ut, rt, nt
+        if stalled:
+            break
     return to_z(u).reshape(N, M.NV).numpy(), nr <= tol, it, nr
 
 

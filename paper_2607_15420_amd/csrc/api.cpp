@@ -165,7 +165,7 @@ static void free_handle(Handle& h) {
   void* ptrs[] = {h.feeds, h.gather, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
-                  h.seg, h.pseg, h.dwv, h.dcv, h.fmask};
+                  h.seg, h.pseg, h.dwv, h.dcv, h.fmask, h.pact};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);
@@ -334,6 +334,7 @@ int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const 
   ALLOC(h.dwv, h.P);
   ALLOC(h.dcv, h.P);
   ALLOC(h.fmask, h.P);
+  ALLOC(h.pact, h.P);
   ALLOC(h.omega_d, 8);
   ALLOC(h.diagx, h.nx);
   ALLOC(h.diags, nst);

@@ -95,6 +95,8 @@ struct Handle {
   double* dwv = nullptr;                     // device [P] delta_w of the stored factorisation
   double* dcv = nullptr;                     // device [P] delta_c
   int* fmask = nullptr;                      // device [P] problems to (re)factorise (null: all)
+  int* pact = nullptr;                       // device [P] problems the per-stage kernels work on
+  bool pact_on = false;                      // false: every problem
   ModelParams mp{};
   double xL[NV], xU[NV], dL = 0, dU = 0;     // unscaled bounds per local variable
   std::vector<double> feeds_h;

@@ -722,6 +722,8 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   HIP_TRY(W.host(&W.dc_h, P));
   HIP_TRY(W.host(&W.fm_h, P));
   HIP_TRY(W.host(&W.dd_h, P));
+  int* pa_h = nullptr;
+  HIP_TRY(W.host(&pa_h, P));
   std::vector<Prob> pr((size_t)P);
   auto upload_ps = [&]() -> int {
     for (int p = 0; p < P; ++p) {
@@ -736,10 +738,17 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       d.accept = q.accepted;
       d.zero_y = 0;
       d.write = !active0 || active0[p];
+      pa_h[p] = q.active;
     }
     HIP_TRY(hipMemcpyAsync(W.ps, W.ps_h, sizeof(PS) * P, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h.pact, pa_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
     return ABS_OK;
   };
+  // the per-stage kernels skip problems that are done (or not asked for)
+  struct PactGuard {
+    Handle& h;
+    ~PactGuard() { h.pact_on = false; }
+  } pact_guard{h};
   auto upload_reg = [&](bool mask) -> int {
     for (int p = 0; p < P; ++p) {
       W.dw_h[p] = pr[(size_t)p].dw;
@@ -866,6 +875,8 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       n_active += active0[p] != 0;
     }
   }
+  TRY(upload_ps());
+  h.pact_on = true;
   auto now = [] { return std::chrono::steady_clock::now(); };
   auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();

@@ -108,11 +108,12 @@ __device__ __forceinline__ void load_inflow(const double* __restrict__ x, const 
 // record: Jacobian blocks and the Lagrangian Hessian block.
 __global__ void k_eval(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ y,
                        const double* __restrict__ cs, const double* __restrict__ feeds, ModelParams p,
-                       const StageInfo* __restrict__ sinfo, long long nst, int full, double* __restrict__ cout,
-                       double* __restrict__ rec) {
+                       const StageInfo* __restrict__ sinfo, long long nst, const int* __restrict__ pact, int full,
+                       double* __restrict__ cout, double* __restrict__ rec) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nst) return;
   const StageInfo si = sinfo[t];
+  if (pact && !pact[si.p]) return;  // problem not being worked on
   const int n = si.n, N = si.N;
   const double* feed = feeds + (long long)si.w * NF;
   double z[NV];
@@ -585,11 +586,18 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void 
 // Forward and backward substitution with stored pivot columns: solr <- K_w^{-1} rhs.
 __global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
                                                 const double* __restrict__ rhs, const int* __restrict__ chain0,
+                                                const int* __restrict__ chain_p, const int* __restrict__ pact,
                                                 int W, int jd, double* __restrict__ solr,
                                                 double* __restrict__ part) {
   __shared__ double sh[WAVE];
   const int w = blockIdx.x;
   if (w >= W) return;
+  if (pact && !pact[chain_p[w]]) {  // problem not being worked on: zero solution
+    if (threadIdx.x == 0) part[(long long)w * 4 + 1] = 0.0;
+    for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE)
+      solr[i] = 0.0;
+    return;
+  }
   const long long t0 = chain0[w];
   const int N = chain0[w + 1] - (int)t0;
   const int lane = lane_id();
@@ -751,7 +759,8 @@ __global__ __launch_bounds__(RES_BS) void k_residual(const double* __restrict__ 
                                                      const double* __restrict__ diagx, const double* __restrict__ diags,
                                                      const double* __restrict__ dwv, const double* __restrict__ dcv,
                                                      const double* __restrict__ sol, const double* __restrict__ rhs,
-                                                     const StageInfo* __restrict__ sinfo, long long nst, int jd,
+                                                     const StageInfo* __restrict__ sinfo, long long nst,
+                                                     const int* __restrict__ pact, int jd,
                                                      double* __restrict__ res, double* __restrict__ stage_d,
                                                      double* __restrict__ bmax) {
   __shared__ double ku[NK][RES_BS], ka[NK][RES_BS];
@@ -759,7 +768,13 @@ __global__ __launch_bounds__(RES_BS) void k_residual(const double* __restrict__ 
   const int tid = threadIdx.x;
   const long long t = (long long)blockIdx.x * RES_BS + tid;
   double om = 0.0;
-  if (t < nst) {
+  const bool on = t < nst && (!pact || pact[sinfo[t].p]);
+  if (t < nst && !on) {  // problem not being worked on: zero residual
+    for (int k = 0; k < NK; ++k) res[t * NK + k] = 0.0;
+    stage_d[2 * t] = 0.0;
+    stage_d[2 * t + 1] = 0.0;
+  }
+  if (on) {
     const StageInfo si = sinfo[t];
     const int n = si.n, N = si.N;
     const double dw = dwv[si.p], dc = dcv[si.p];
@@ -873,10 +888,17 @@ __global__ __launch_bounds__(RES_BS) void k_residual(const double* __restrict__ 
 // res_d = rhs_d - sum b u_hyd - kdd u_d; omd[p] = its backward error
 __global__ void k_residual_d(const double* __restrict__ stage_d, const long long* __restrict__ pstage,
                              const DevScalars* __restrict__ scv, const double* __restrict__ sol,
-                             const double* __restrict__ rhs, long long nkk, double* __restrict__ res,
-                             double* __restrict__ omd) {
+                             const double* __restrict__ rhs, long long nkk, const int* __restrict__ pact,
+                             double* __restrict__ res, double* __restrict__ omd) {
   __shared__ double s1[256], s2[256];
   const int pb = blockIdx.x;
+  if (pact && !pact[pb]) {
+    if (threadIdx.x == 0) {
+      res[nkk + pb] = 0.0;
+      omd[pb] = 0.0;
+    }
+    return;
+  }
   double a = 0, b = 0;
   for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += blockDim.x) {
     a += stage_d[2 * t];
@@ -941,7 +963,7 @@ hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling
                            const double* y, int full, double* c_out, hipStream_t st) {
   prof_begin(h, st);
   hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, 128)), dim3(128), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
-                     h.sinfo, h.nst, full, c_out, h.rec);
+                     h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, full, c_out, h.rec);
   prof_end(h, 2, st);
   return hipGetLastError();
 }
@@ -984,7 +1006,8 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
 
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_solve, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.S, h.jac_d_index,
+  hipLaunchKernelGGL(k_solve, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p,
+                     h.pact_on ? h.pact : nullptr, h.S, h.jac_d_index,
                      h.solr, h.part);
   prof_end(h, 1, st);
   ++h.n_solve;
@@ -1012,9 +1035,10 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   double* omd = bmax + nb;                // one per problem
   prof_begin(h, st);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_BS), 0, st, h.rec, h.jtab, diagx, diags, h.dwv, h.dcv, sol, rhs,
-                     h.sinfo, h.nst, h.jac_d_index, res, stage_d, bmax);
+                     h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, h.jac_d_index, res, stage_d, bmax);
   prof_end(h, 3, st);
-  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, stage_d, h.pstage, h.scal, sol, rhs, nkk, res, omd);
+  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, stage_d, h.pstage, h.scal, sol, rhs, nkk,
+                     h.pact_on ? h.pact : nullptr, res, omd);
   hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(256), 0, st, bmax, nb, omd, h.P, omega_out);
   return hipGetLastError();
 }

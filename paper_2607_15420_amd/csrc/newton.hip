@@ -178,6 +178,17 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
   std::vector<int> wp((size_t)W);  // problem of each chain
   for (int p = 0; p < P; ++p)
     for (long long w = h.pchain_h[(size_t)p]; w < h.pchain_h[(size_t)p + 1]; ++w) wp[(size_t)w] = p;
+  // work only on the requested problems (factorisation, evaluation, solves, residuals)
+  int* pm_h = nullptr;
+  HIP_TRY(B.h(&pm_h, P));
+  for (int p = 0; p < P; ++p) pm_h[p] = !pmask || pmask[p];
+  HIP_TRY(hipMemcpyAsync(h.pact, pm_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h.fmask, pm_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+  struct PactGuard {
+    Handle& h;
+    ~PactGuard() { h.pact_on = false; }
+  } pact_guard{h};
+  h.pact_on = true;
   // scaling as in the interior-point method: variables by the cold point,
   // rows by their largest scaled gradient entry at the starting point
   for (int k = 0; k < NV; ++k) h.sc.D[k] = h.x0[k] != 0.0 ? fabs(h.x0[k]) : 1.0;
@@ -196,14 +207,15 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
   HIP_TRY(hipStreamSynchronize(st));
   std::vector<double> nr((size_t)W);
   for (int w = 0; w < W; ++w) nr[(size_t)w] = st_h[2 * w];
-  auto wanted = [&](int w) { return !pmask || pmask[wp[(size_t)w]]; };
+  std::vector<char> stalled((size_t)W, 0);  // backtracking exhausted without decrease
+  auto wanted = [&](int w) { return (!pmask || pmask[wp[(size_t)w]]) && !stalled[(size_t)w]; };
   int it = 0;
   for (; it < max_iter; ++it) {
     bool any = false;
     for (int w = 0; w < W; ++w) any = any || (wanted(w) && !(nr[(size_t)w] <= tol));
     if (!any) break;
     hipLaunchKernelGGL(k_newton_rhs, dim3(nblk(nkkt, BS)), dim3(BS), 0, st, c, nks, nkkt, rhs);
-    HIP_TRY(launch_factor(h, h.diagx, h.diags, rhs, false, st));
+    HIP_TRY(launch_factor(h, h.diagx, h.diags, rhs, true, st));
     HIP_TRY(launch_schur(h, h.diagx, rhs, 1, sol, st));
     double rel = 0.0;
     {
@@ -232,8 +244,10 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
       for (int w = 0; w < W; ++w) {
         if (!searching[(size_t)w]) continue;
         const double a = aw_h[w], nt = st_h[2 * w];
-        if ((std::isfinite(nt) && nt < (1.0 - 1e-4 * a) * nr[(size_t)w]) || a < 1e-10) {
+        const bool dec = std::isfinite(nt) && nt < (1.0 - 1e-4 * a) * nr[(size_t)w];
+        if (dec || a < 1e-10) {
           searching[(size_t)w] = 0;
+          if (!dec) stalled[(size_t)w] = 1;  // no decrease even for a tiny step: give up on this chain
           nr[(size_t)w] = nt;
           continue;
         }
