@@ -212,7 +212,19 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--no-sequential", action="store_true", help="batched leg without the sequential comparison")
     ap.add_argument("--warm-epochs", type=int, default=300)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the scenario "
               "sharding over several GPUs is a design, not an implemented path.", file=sys.stderr)

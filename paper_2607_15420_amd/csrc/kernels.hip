@@ -749,144 +749,128 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
   if (i < n) y[i] += a * x[i];
 }
 
-// Residual of the bordered KKT system for the rows of stage (w, n) (one thread
-// per stage, accumulators in LDS, row-major over the block so that the uniform
-// row index of a table entry gives consecutive addresses): res = rhs - K sol.
-// Per block: the sum of b * sol_hyd and of its magnitude (d row) and the
-// largest componentwise backward error |res_i| / (|K||sol| + |rhs|)_i.
-constexpr int RES_BS = 64;
-__global__ __launch_bounds__(RES_BS) void k_residual(const double* __restrict__ rec, const int* __restrict__ jtab,
-                                                     const double* __restrict__ diagx, const double* __restrict__ diags,
-                                                     const double* __restrict__ dwv, const double* __restrict__ dcv,
-                                                     const double* __restrict__ sol, const double* __restrict__ rhs,
-                                                     const StageInfo* __restrict__ sinfo, long long nst,
-                                                     const int* __restrict__ pact, int jd,
-                                                     double* __restrict__ res, double* __restrict__ stage_d,
-                                                     double* __restrict__ bmax) {
-  __shared__ double ku[NK][RES_BS], ka[NK][RES_BS];
-  __shared__ double r2[RES_BS];
-  const int tid = threadIdx.x;
-  const long long t = (long long)blockIdx.x * RES_BS + tid;
-  double om = 0.0;
-  const bool on = t < nst && (!pact || pact[sinfo[t].p]);
-  if (t < nst && !on) {  // problem not being worked on: zero residual
-    for (int k = 0; k < NK; ++k) res[t * NK + k] = 0.0;
-    stage_d[2 * t] = 0.0;
-    stage_d[2 * t + 1] = 0.0;
+// Residual res = rhs - K sol of the bordered system, one wave per chain, bottom
+// to top.  Each stage's frontal matrix is assembled exactly as for the
+// factorisation (same gather table, no contribution block, no right-hand
+// side), so lane j holds column j = row j of the stage's KKT rows against its
+// own unknowns, the 16 coupling unknowns of the stage above and d (row 60 is
+// the border b).  Lane j then forms (K sol)_j = sum_i F[i][j] xf_i with xf
+// broadcast through LDS; the coupling lanes 43-58 produce the contribution of
+// this stage's unknowns to the rows of the stage above, which that stage adds.
+// Per chain: part[2w] = sum b u_hyd, part[2w+1] = sum |b u_hyd| (d rows),
+// omc[w] = largest componentwise backward error |res_i| / (|K||sol| + |rhs|)_i.
+struct ResLDS {
+  double xf[WAVE];  // broadcast unknowns (first: reachable by immediate offsets)
+  double src[NSRC];
+  double cy[WAVE];  // contribution to the stage above, by stage-local index
+  double ca[WAVE];  // its magnitude sum
+};
+
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void k_residual(
+    const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ diagx,
+    const double* __restrict__ diags, const double* __restrict__ dwv, const double* __restrict__ dcv,
+    const double* __restrict__ sol, const double* __restrict__ rhs, const int* __restrict__ chain0,
+    const int* __restrict__ chain_p, const int* __restrict__ pact, int W, long long nks, int jd,
+    double* __restrict__ res, double* __restrict__ part, double* __restrict__ omc) {
+  __shared__ ResLDS L;
+  const int w = blockIdx.x;
+  if (w >= W) return;
+  const int pw = chain_p[w];
+  const long long t0 = chain0[w];
+  const int N = chain0[w + 1] - (int)t0;
+  const int lane = lane_id();
+  if (pact && !pact[pw]) {  // problem not being worked on: zero residual
+    for (long long i = t0 * NK + lane; i < (t0 + N) * NK; i += WAVE) res[i] = 0.0;
+    if (lane == 0) {
+      part[2 * w] = 0.0;
+      part[2 * w + 1] = 0.0;
+      omc[w] = 0.0;
+    }
+    return;
   }
-  if (on) {
-    const StageInfo si = sinfo[t];
-    const int n = si.n, N = si.N;
-    const double dw = dwv[si.p], dc = dcv[si.p];
-    const long long nkk = nst * NK + si.p;  // this problem's d unknown
+  const double dw = dwv[pw], dc = dcv[pw];
+  const double ud = sol[nks + pw];
+  for (int i = lane; i < NC * (NC + 2); i += WAVE) L.src[SRC_CTB + i] = 0.0;
+  if (lane == 0) L.src[SRC_ZERO] = 0.0;
+  if (lane < NK) L.src[SRC_RHS + lane] = 0.0;
+  L.cy[lane] = 0.0;
+  L.ca[lane] = 0.0;
+  double dp = 0.0, da = 0.0, om = 0.0;
+  for (int n = 0; n < N; ++n) {
+    const long long t = t0 + n;
     const double* R = rec + t * REC;
-    const double* u = sol + t * NK;
-#define KU(k) ku[k][tid]
-#define KA(k) ka[k][tid]
-    for (int k = 0; k < NK; ++k) {
-      KU(k) = 0.0;
-      KA(k) = 0.0;
+    for (int i = lane; i < REC; i += WAVE) L.src[SRC_REC + i] = R[i];
+    if (lane < NJD) L.src[SRC_DOWN1 + lane] = (n < N - 1) ? rec[(t + 1) * REC + REC_DOWN + lane] : 0.0;
+    if (lane < NV) L.src[SRC_DIAGX + lane] = diagx[t * NV + lane] + dw;
+    if (lane == 0) {
+      L.src[SRC_BRD] = R[jd];
+      L.src[SRC_DC] = -dc;
+      L.src[SRC_DHYD] = -(1.0 / (diags[t] + dw) + dc);
     }
-    for (int e = 0; e < NJO; ++e) {  // own block (rows: duals, cols: primals) and the d entry
-      const int rc = jtab[e];
-      const int r = rc & 255, col = (rc >> 8) & 255, blk = rc >> 16;
-      const double j = R[REC_OWN + e];
-      const int dr = r < NE ? NV + r : NK - 1;
-      if (blk == BLK_D) {
-        KU(dr) += j * sol[nkk];
-        KA(dr) += fabs(j * sol[nkk]);
-        continue;
-      }
-      KU(dr) += j * u[col];
-      KA(dr) += fabs(j * u[col]);
-      KU(col) += j * u[dr];
-      KA(col) += fabs(j * u[dr]);
+    // unknowns of the frontal: own (0-42), the stage above at its coupling indices (43-58), d (60)
+    double xv = 0.0;
+    if (lane < NK) xv = sol[t * NK + lane];
+    else if (lane < NK + NC) xv = n < N - 1 ? sol[(t + 1) * NK + coupling_index(lane - NK)] : 0.0;
+    else if (lane == FR_B) xv = ud;
+    L.xf[lane] = xv;
+    __syncthreads();
+    // keep the table loads inside the stage loop (hoisting them would pin ~120 registers)
+    const int* gt = gather;
+    __asm__ volatile("" : "+s"(gt));
+    double v[FR];
+#pragma unroll
+    for (int i = 0; i < FR; ++i) {
+      const int g = gt[i * WAVE + lane];
+      v[i] = L.src[g & 1023] + L.src[(g >> 10) & 1023] + L.src[(g >> 20) & 1023];
+      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
-    if (n < N - 1) {
-      for (int e = 0; e < NJU; ++e) {  // this stage's rows against stage n+1's primals
-        const int rc = jtab[NJO + e];
-        const int r = rc & 255, col = (rc >> 8) & 255;
-        const double j = R[REC_UP + e];
-        KU(NV + r) += j * u[NK + col];
-        KA(NV + r) += fabs(j * u[NK + col]);
-      }
-      const double* R1 = R + REC;  // stage n+1's rows against this stage's primals
-      for (int e = 0; e < NJD; ++e) {
-        const int rc = jtab[NJO + NJU + e];
-        const int r = rc & 255, col = (rc >> 8) & 255;
-        const double j = R1[REC_DOWN + e];
-        KU(col) += j * u[NK + NV + r];
-        KA(col) += fabs(j * u[NK + NV + r]);
-      }
+    double y = 0.0, ya = 0.0;
+#pragma unroll
+    for (int i = 0; i < FR; ++i) {
+      if (i == FR_R) continue;  // the right-hand-side row is not part of K
+      const double pr = (i == FR_B && lane == FR_B) ? 0.0 : v[i] * L.xf[i];
+      y += pr;
+      ya += fabs(pr);
     }
-    if (n > 0) {
-      for (int e = 0; e < NJD; ++e) {  // this stage's rows against stage n-1's primals
-        const int rc = jtab[NJO + NJU + e];
-        const int r = rc & 255, col = (rc >> 8) & 255;
-        const double j = R[REC_DOWN + e];
-        KU(NV + r) += j * u[-NK + col];
-        KA(NV + r) += fabs(j * u[-NK + col]);
-      }
-      const double* R0 = R - REC;  // stage n-1's rows against this stage's primals
-      for (int e = 0; e < NJU; ++e) {
-        const int rc = jtab[NJO + e];
-        const int r = rc & 255, col = (rc >> 8) & 255;
-        const double j = R0[REC_UP + e];
-        KU(col) += j * u[-NK + NV + r];
-        KA(col) += fabs(j * u[-NK + NV + r]);
-      }
+    // rows of this stage also see the stage below (its coupling lanes, by our local index)
+    if (lane < NK) {
+      y += L.cy[lane];
+      ya += L.ca[lane];
     }
-    HessPos pos[NH];
-    hess_positions(pos);
-    for (int e = 0; e < NH; ++e) {
-      const int a = pos[e].r, b = pos[e].c;
-      const double hv = R[REC_H + e];
-      KU(a) += hv * u[b];
-      KA(a) += fabs(hv * u[b]);
-      if (a != b) {
-        KU(b) += hv * u[a];
-        KA(b) += fabs(hv * u[a]);
-      }
+    __syncthreads();
+    L.cy[lane] = 0.0;
+    L.ca[lane] = 0.0;
+    __syncthreads();
+    if (lane >= NK && lane < NK + NC) {
+      L.cy[coupling_index(lane - NK)] = y;
+      L.ca[coupling_index(lane - NK)] = ya;
     }
-    for (int k = 0; k < NV; ++k) {
-      const double dg = diagx[t * NV + k] + dw;
-      KU(k) += dg * u[k];
-      KA(k) += fabs(dg * u[k]);
+    if (lane < NK) {
+      const double r = rhs[t * NK + lane];
+      const double rr = r - y;
+      res[t * NK + lane] = rr;
+      const double den = ya + fabs(r);
+      om = fmax(om, den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY));
     }
-    for (int r = 0; r < NE; ++r) {
-      KU(NV + r) -= dc * u[NV + r];
-      KA(NV + r) += fabs(dc * u[NV + r]);
+    if (lane == FR_B) {  // b . u_hyd of this stage (the d row)
+      dp += y;
+      da += ya;
     }
-    {
-      const double dh = -(1.0 / (diags[t] + dw) + dc);
-      KU(NK - 1) += dh * u[NK - 1];
-      KA(NK - 1) += fabs(dh * u[NK - 1]);
-    }
-    for (int k = 0; k < NK; ++k) {
-      const double rr = rhs[t * NK + k] - KU(k);
-      res[t * NK + k] = rr;
-      const double den = KA(k) + fabs(rhs[t * NK + k]);
-      const double o = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
-      om = fmax(om, o);
-    }
-#undef KU
-#undef KA
-    const double dp = R[jd] * u[NK - 1];
-    stage_d[2 * t] = dp;
-    stage_d[2 * t + 1] = fabs(dp);
-  }
-  r2[tid] = om;
-  __syncthreads();
-  for (int s = RES_BS / 2; s > 0; s >>= 1) {
-    if (tid < s) r2[tid] = fmax(r2[tid], r2[tid + s]);
     __syncthreads();
   }
-  if (tid == 0) bmax[blockIdx.x] = r2[0];
+  // fixed-order wave maximum of the backward errors
+#pragma unroll
+  for (int m = 1; m < WAVE; m <<= 1) om = fmax(om, __shfl_xor(om, m, WAVE));
+  if (lane == FR_B) {
+    part[2 * w] = dp;
+    part[2 * w + 1] = da;
+  }
+  if (lane == 0) omc[w] = om;
 }
 
-// d row of each problem's residual (one block per problem, fixed order):
-// res_d = rhs_d - sum b u_hyd - kdd u_d; omd[p] = its backward error
-__global__ void k_residual_d(const double* __restrict__ stage_d, const long long* __restrict__ pstage,
+// d row of each problem's residual (one block per problem, fixed order over
+// its chains): res_d = rhs_d - sum b u_hyd - kdd u_d; omd[p] = its backward error
+__global__ void k_residual_d(const double* __restrict__ part, const int* __restrict__ pchain,
                              const DevScalars* __restrict__ scv, const double* __restrict__ sol,
                              const double* __restrict__ rhs, long long nkk, const int* __restrict__ pact,
                              double* __restrict__ res, double* __restrict__ omd) {
@@ -900,9 +884,9 @@ __global__ void k_residual_d(const double* __restrict__ stage_d, const long long
     return;
   }
   double a = 0, b = 0;
-  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += blockDim.x) {
-    a += stage_d[2 * t];
-    b += stage_d[2 * t + 1];
+  for (int w = pchain[pb] + threadIdx.x; w < pchain[pb + 1]; w += blockDim.x) {
+    a += part[2 * w];
+    b += part[2 * w + 1];
   }
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = b;
@@ -926,12 +910,12 @@ __global__ void k_residual_d(const double* __restrict__ stage_d, const long long
   }
 }
 
-// omega_out[0] = max of the block maxima, omega_out[1] = max over the problems' d rows
-__global__ void k_residual_max(const double* __restrict__ bmax, int nb, const double* __restrict__ omd, int P,
+// omega_out[0] = max over the chains, omega_out[1] = max over the problems' d rows
+__global__ void k_residual_max(const double* __restrict__ omc, int W, const double* __restrict__ omd, int P,
                                double* __restrict__ omega_out) {
   __shared__ double s1[256], s2[256];
   double a = 0, b = 0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) a = fmax(a, bmax[i]);
+  for (int i = threadIdx.x; i < W; i += blockDim.x) a = fmax(a, omc[i]);
   for (int i = threadIdx.x; i < P; i += blockDim.x) b = fmax(b, omd[i]);
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = b;
@@ -1028,18 +1012,17 @@ hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int m
 
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
                            const double* rhs, double* res, double* omega_out, hipStream_t st) {
-  const long long nkk = h.nst * NK;
-  const int nb = (int)grid_for(h.nst, RES_BS);
-  double* stage_d = h.kden;               // 2 per stage
-  double* bmax = h.kden + 2 * h.nst;      // one per block
-  double* omd = bmax + nb;                // one per problem
+  const long long nks = h.nst * NK;
+  const int* pa = h.pact_on ? h.pact : nullptr;
+  double* part = h.kden;            // 2 per chain
+  double* omc = h.kden + 2LL * h.S;  // 1 per chain
+  double* omd = omc + h.S;          // 1 per problem
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_BS), 0, st, h.rec, h.jtab, diagx, diags, h.dwv, h.dcv, sol, rhs,
-                     h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, h.jac_d_index, res, stage_d, bmax);
+  hipLaunchKernelGGL(k_residual, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, diagx, diags, h.dwv, h.dcv, sol, rhs,
+                     h.chain0, h.chain_p, pa, h.S, nks, h.jac_d_index, res, part, omc);
   prof_end(h, 3, st);
-  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, stage_d, h.pstage, h.scal, sol, rhs, nkk,
-                     h.pact_on ? h.pact : nullptr, res, omd);
-  hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(256), 0, st, bmax, nb, omd, h.P, omega_out);
+  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pchain, h.scal, sol, rhs, nks, pa, res, omd);
+  hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(256), 0, st, omc, h.S, omd, h.P, omega_out);
   return hipGetLastError();
 }
 
