@@ -283,6 +283,7 @@ def main():
                    "start": "cold"},
         "converged": ok,
         "iterations": r.iterations,
+        "tuning": h.tuning(),
         "E0": r.E0,
         "d": r.d,
         "max_lin_resid": r.max_lin_resid,

@@ -161,6 +161,8 @@ typedef struct {
                                   iteration limit) is solved again from its simulated states
                                   (absorber_simulate, d at 1.001 x its hydraulic minimum) with the
                                   warm-start options; 0: report the failure (default 1) */
+  int32_t autotune;         /* 1: on the handle's first factorisation, time the launch-shape candidates
+                               (absorber_tuning) on its own data and keep the fastest (default 1) */
 } absorber_ipm_options;
 
 typedef struct {
@@ -229,6 +231,19 @@ typedef struct {
   int64_t bytes_factor_slots; /* bytes of pivot columns one factorisation writes */
 } absorber_profile;
 int absorber_profile_enable(absorber_t* h, int32_t mask);
+
+/* Launch shapes chosen by the autotuner (absorber_ipm_options.autotune): the
+ * occupancy target of the factorisation and of the stored-factor solve (waves
+ * per SIMD 2, 3 or 4, which fixes each wave's register budget) and the block
+ * size of the stage evaluation (64, 128 or 256), with the measured time of each
+ * candidate in ms (index 0-2 in the order listed).  tuned = 0 until the first
+ * factorisation of a solve with autotune on. */
+typedef struct {
+  int32_t tuned;
+  int32_t factor_waves_per_simd, solve_waves_per_simd, eval_block;
+  float factor_ms[3], solve_ms[3], eval_ms[3];
+} absorber_tuning;
+int absorber_tuning_get(const absorber_t* h, absorber_tuning* out);
 int absorber_profile_get(const absorber_t* h, absorber_profile* out);
 
 /* ------------------------------------------------------------------------

@@ -62,6 +62,7 @@ class IpmOptions(ctypes.Structure):
         ("mu_init", ctypes.c_double), ("warm_mu_init", ctypes.c_double), ("bound_push", ctypes.c_double),
         ("warm_bound_push", ctypes.c_double), ("nlp_scaling_max_gradient", ctypes.c_double),
         ("print_level", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("feasibility_restart", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
     ]
 
 
@@ -96,6 +97,12 @@ class MlpTrainOptions(ctypes.Structure):
 
 class MlpTrainResult(ctypes.Structure):
     _fields_ = [("final_loss", ctypes.c_double), ("seconds", ctypes.c_double), ("steps", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int32), ("factor_waves_per_simd", ctypes.c_int32),
+                ("solve_waves_per_simd", ctypes.c_int32), ("eval_block", ctypes.c_int32),
+                ("factor_ms", ctypes.c_float * 3), ("solve_ms", ctypes.c_float * 3), ("eval_ms", ctypes.c_float * 3)]
 
 
 PROFILE_CLASSES = ("factor", "solve", "eval", "residual")
@@ -135,6 +142,7 @@ def lib():
                                                   ctypes.POINTER(IpmResult)]),
             "absorber_profile_enable": (ctypes.c_int, [vp, i32]),
             "absorber_profile_get": (ctypes.c_int, [vp, ctypes.POINTER(Profile)]),
+            "absorber_tuning_get": (ctypes.c_int, [vp, ctypes.POINTER(Tuning)]),
             "absorber_last_error": (ctypes.c_char_p, []),
             "absorber_mlp_default_config": (None, [ctypes.POINTER(MlpConfig)]),
             "absorber_mlp_default_train_options": (None, [ctypes.POINTER(MlpTrainOptions)]),
@@ -336,6 +344,13 @@ class Absorber:
     def profile_enable(self, on=True, mask=0xF):
         """Time the kernel classes in mask (bit 0 factor, 1 solve, 2 eval, 3 residual)."""
         _check(lib().absorber_profile_enable(self.h, int(mask) if on else 0))
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().absorber_tuning_get(self.h, ctypes.byref(t)))
+        return {"tuned": bool(t.tuned), "factor_waves_per_simd": t.factor_waves_per_simd,
+                "solve_waves_per_simd": t.solve_waves_per_simd, "eval_block": t.eval_block,
+                "factor_ms": list(t.factor_ms), "solve_ms": list(t.solve_ms), "eval_ms": list(t.eval_ms)}
 
     def profile(self) -> dict:
         p = Profile()

@@ -74,6 +74,13 @@ struct Scaling {
   double Dd;
 };
 
+// launch shapes picked by measurement (autotune)
+struct Tune {
+  int factor_wpe = 3, solve_wpe = 3, eval_bs = 128;
+  bool done = false;
+  float ms_factor[3] = {0, 0, 0}, ms_solve[3] = {0, 0, 0}, ms_eval[3] = {0, 0, 0};
+};
+
 // all per-handle device and host state
 struct Handle {
   int P = 1;                                 // independent problems
@@ -124,6 +131,7 @@ struct Handle {
   double* kcor = nullptr;                    // [nkkt] refinement correction
   double* kden = nullptr;                    // residual partials: 2 per stage, block maxima, per-problem d rows
   double* omega_d = nullptr;                 // [2] backward errors of the last residual
+  Tune tune;
   double* redbuf = nullptr;                  // device reduction partials
   double* redbuf_h = nullptr;                // pinned host mirror
   int red_cap = 0;
@@ -199,6 +207,10 @@ hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int m
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
                            const double* rhs, double* res, double* omega_out, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st);
+// time the launch-shape candidates on the current data and keep the fastest (h.tune); x, y, c as for
+// launch_eval (scaled, full), diagx/diags/rhs as for launch_factor
+int autotune(Handle& h, const double* x, const double* y, double* c, const double* diagx, const double* diags,
+             const double* rhs, hipStream_t st);
 
 }  // namespace absorber
 

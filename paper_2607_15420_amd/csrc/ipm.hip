@@ -942,6 +942,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       TRY(upload_reg(true));
       hipLaunchKernelGGL(k_rhs, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.g, W.y, W.c, W.s, h.diags,
                          b, C.kappa_d, gf, nxs, nks, W.rhs);
+      if (o.autotune && !h.tune.done) TRY(autotune(h, W.xt, W.y, W.c, h.diagx, h.diags, W.rhs, st));
       HIP_TRY(launch_factor(h, h.diagx, h.diags, W.rhs, true, st));
       ++nfact;
       ++n_fac_it;
@@ -1200,6 +1201,7 @@ void absorber_ipm_default_options(absorber_ipm_options* o) {
   o->print_level = 0;
   o->use_graph = 0;
   o->feasibility_restart = 1;
+  o->autotune = 1;
 }
 
 static int check_options(const absorber_ipm_options* opts, absorber_ipm_options* o, const char* who) {
@@ -1240,6 +1242,24 @@ int absorber_batch_solve(absorber_t* H, const absorber_ipm_options* opts, const 
   const int rc = check_options(opts, &o, "absorber_batch_solve");
   if (rc) return rc;
   return solve_with_restart(H->h, o, x0_dev, lambda0_dev, x_out_dev, lambda_out_dev, results);
+}
+
+int absorber_tuning_get(const absorber_t* H, absorber_tuning* out) {
+  if (!H || !out) {
+    set_error("absorber_tuning_get: bad argument");
+    return ABS_ERR_ARG;
+  }
+  const Tune& t = H->h.tune;
+  out->tuned = t.done;
+  out->factor_waves_per_simd = t.factor_wpe;
+  out->solve_waves_per_simd = t.solve_wpe;
+  out->eval_block = t.eval_bs;
+  for (int i = 0; i < 3; ++i) {
+    out->factor_ms[i] = t.ms_factor[i];
+    out->solve_ms[i] = t.ms_solve[i];
+    out->eval_ms[i] = t.ms_eval[i];
+  }
+  return ABS_OK;
 }
 
 int absorber_kkt_solve(absorber_t* H, const double* rhs_dev, double* sol_dev, double* rel_resid_host, void* stream) {

@@ -7,6 +7,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "internal.h"
 
 namespace absorber {
@@ -489,8 +491,8 @@ __device__ __forceinline__ void backward_stage(const double* __restrict__ sb, do
   }
 }
 
-template <int WITH_RHS>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void k_factor(
+template <int WITH_RHS, int WPE>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_factor(
     const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
     const double* __restrict__ diagx, const double* __restrict__ diags, const double* __restrict__ dwv,
     const double* __restrict__ dcv, const int* __restrict__ chain0, const int* __restrict__ chain_p,
@@ -584,7 +586,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void 
 }
 
 // Forward and backward substitution with stored pivot columns: solr <- K_w^{-1} rhs.
-__global__ __launch_bounds__(WAVE) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
+template <int WPE>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
                                                 const double* __restrict__ rhs, const int* __restrict__ chain0,
                                                 const int* __restrict__ chain_p, const int* __restrict__ pact,
                                                 int W, int jd, double* __restrict__ solr,
@@ -946,7 +949,8 @@ hipError_t launch_eval(Handle& h, const double* x, int scaled, const double* y, 
 hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling& sc, const double* cs,
                            const double* y, int full, double* c_out, hipStream_t st) {
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, 128)), dim3(128), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
+  const int bs = h.tune.eval_bs;
+  hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, bs)), dim3(bs), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
                      h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, full, c_out, h.rec);
   prof_end(h, 2, st);
   return hipGetLastError();
@@ -976,12 +980,20 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
                          hipStream_t st) {
   const int* fm = mask ? h.fmask : nullptr;
   prof_begin(h, st);
-  if (rhs)
-    hipLaunchKernelGGL(k_factor<1>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, h.dcv,
-                       h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
-  else
-    hipLaunchKernelGGL(k_factor<0>, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, h.dcv,
-                       h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part);
+#define ABS_FACTOR(R, W)                                                                                     \
+  hipLaunchKernelGGL((k_factor<R, W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
+                     h.dcv, h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part)
+  const int wpe = h.tune.factor_wpe;
+  if (rhs) {
+    if (wpe == 2) ABS_FACTOR(1, 2);
+    else if (wpe == 4) ABS_FACTOR(1, 4);
+    else ABS_FACTOR(1, 3);
+  } else {
+    if (wpe == 2) ABS_FACTOR(0, 2);
+    else if (wpe == 4) ABS_FACTOR(0, 4);
+    else ABS_FACTOR(0, 3);
+  }
+#undef ABS_FACTOR
   prof_end(h, 0, st);
   h.factored = true;
   ++h.n_factor;
@@ -990,12 +1002,69 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
 
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_solve, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p,
-                     h.pact_on ? h.pact : nullptr, h.S, h.jac_d_index,
-                     h.solr, h.part);
+  const int* pa = h.pact_on ? h.pact : nullptr;
+#define ABS_SOLVE(W)                                                                                             \
+  hipLaunchKernelGGL((k_solve<W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, h.S, \
+                     h.jac_d_index, h.solr, h.part)
+  if (h.tune.solve_wpe == 2) ABS_SOLVE(2);
+  else if (h.tune.solve_wpe == 4) ABS_SOLVE(4);
+  else ABS_SOLVE(3);
+#undef ABS_SOLVE
   prof_end(h, 1, st);
   ++h.n_solve;
   return hipGetLastError();
+}
+
+// Launch-shape tuning by measurement on the handle's own data: the occupancy
+// target (waves per SIMD: 2, 3 or 4, which sets the register budget) of the
+// factorisation and of the stored-factor solve, and the block size of the
+// stage evaluation.  Each candidate runs twice on the current records (the
+// launches are idempotent) and the fastest median is kept.
+static float time_launch(hipStream_t st, hipEvent_t e0, hipEvent_t e1, const std::function<void()>& f) {
+  float best = 1e30f;
+  for (int r = 0; r < 2; ++r) {
+    (void)hipEventRecord(e0, st);
+    f();
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = fminf(best, ms);
+  }
+  return best;
+}
+
+int autotune(Handle& h, const double* x, const double* y, double* c, const double* diagx, const double* diags,
+             const double* rhs, hipStream_t st) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int prof = h.prof;
+  h.prof = 0;
+  const int bss[3] = {64, 128, 256};
+  for (int i = 0; i < 3; ++i) {
+    h.tune.eval_bs = bss[i];
+    h.tune.ms_eval[i] = time_launch(st, e0, e1, [&] { (void)launch_eval(h, x, 1, y, 1, c, st); });
+  }
+  const int wpes[3] = {2, 3, 4};
+  for (int i = 0; i < 3; ++i) {
+    h.tune.factor_wpe = wpes[i];
+    h.tune.ms_factor[i] = time_launch(st, e0, e1, [&] { (void)launch_factor(h, diagx, diags, rhs, false, st); });
+  }
+  for (int i = 0; i < 3; ++i) {
+    h.tune.solve_wpe = wpes[i];
+    h.tune.ms_solve[i] = time_launch(st, e0, e1, [&] { (void)launch_solve(h, rhs, st); });
+  }
+  auto argmin = [](const float* v) { return v[0] <= v[1] ? (v[0] <= v[2] ? 0 : 2) : (v[1] <= v[2] ? 1 : 2); };
+  h.tune.eval_bs = bss[argmin(h.tune.ms_eval)];
+  h.tune.factor_wpe = wpes[argmin(h.tune.ms_factor)];
+  h.tune.solve_wpe = wpes[argmin(h.tune.ms_solve)];
+  h.tune.done = true;
+  h.prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(hipGetLastError());
+  return ABS_OK;
 }
 
 hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st) {

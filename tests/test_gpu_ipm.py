@@ -89,3 +89,22 @@ def check_full_size(params, w, n_sample, seed):
 
 def test_c2_full_size(params):
     check_full_size(params, CONFIGS["C2"], 6, 1)
+
+
+def test_autotune_keeps_the_result(params):
+    """Launch shapes chosen by measurement change the speed, not the arithmetic:
+    the solve with the tuned shapes is bit-identical to the default shapes."""
+    from paper_2607_15420_amd import Absorber
+    w = CONFIGS["C1"]
+    F = w.feeds(params)
+    h0 = Absorber(params, w.n_stages, F)
+    r0 = h0.ipm_solve(Absorber.default_options(autotune=0))
+    assert not h0.tuning()["tuned"]
+    h0.close()
+    h1 = Absorber(params, w.n_stages, F)
+    r1 = h1.ipm_solve(Absorber.default_options(autotune=1))
+    t = h1.tuning()
+    h1.close()
+    assert t["tuned"] and t["factor_waves_per_simd"] in (2, 3, 4) and t["eval_block"] in (64, 128, 256)
+    assert min(t["factor_ms"]) > 0 and min(t["solve_ms"]) > 0
+    assert r1.status == 0 and r1.iterations == r0.iterations and r1.d == r0.d
