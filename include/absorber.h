@@ -328,26 +328,36 @@ int absorber_mlp_adam_step(absorber_mlp* net, const float* grad_dev, const absor
 int absorber_mlp_train(absorber_mlp* net, const float* X_dev, const float* T_dev, int64_t n,
                        const absorber_mlp_train_options* opts, absorber_mlp_train_result* result);
 
-/* Warm-start encoding of the absorber problem.
+/* Warm-start encoding of the absorber problem (every problem of the handle
+ * must have the same stage count N).  A network row describes one scenario:
+ * its N stage vectors (21 values each: ln of the 13 mole fractions, floored at
+ * 1e-30, then L, V, T and the 5 extents), and for a primal-dual network its N
+ * row-multiplier vectors (22 values each, asinh(lambda / 1e-6)); n_out = 21 N
+ * (primal) or 43 N (primal-dual).
  * features: X_dev [S][3] float = (flue-gas flow, CO2 fraction, temperature) of
  *   each scenario's feed.
- * targets: T_dev [S][21 N] float from a primal vector x_dev[nx]: per stage
- *   vector, ln of the 13 mole fractions (floored at 1e-30), the other 8
- *   entries as they are (the d entry is not encoded).
- * point: the inverse of targets for predicted Y_dev [S][21 N], written to
- *   x0_dev[nx]; d = (1 + d_margin) * the largest hydraulic diameter
- *   sqrt(4 V R T / (pi u_max P)) of the decoded stages (d_margin >= 0).
+ * targets: T_dev [S][n_out] from a primal vector x_dev[nx] and, for n_out = 43 N,
+ *   the row multipliers lambda_dev[nc] (NULL: primal only).
+ * point: decodes Y_dev [S][n_out] into x0_dev[nx]: the stage vectors, and each
+ *   problem's d = (1 + d_margin) * the largest hydraulic diameter
+ *   sqrt(4 V R T / (pi u_max P)) of its decoded stages (d_margin >= 0); with a
+ *   primal-dual row and lambda0_dev[nc] non-NULL, the multipliers of each
+ *   problem's worst scenario (the one holding that largest diameter, the only
+ *   one whose hydraulic rows are active at the optimum) and 0 for the others.
  * warm_start: features -> network -> point, with caller workspaces
- *   X_work_dev [S][3] and Y_work_dev [S][21 N]; the network must have n_in = 3
- *   and n_out = 21 N.  All four are asynchronous on stream. */
+ *   X_work_dev [S][3] and Y_work_dev [S][n_out]; the network must have 3 inputs.
+ * All four are asynchronous on stream. */
 int absorber_warm_features(absorber_t* h, float* X_dev, void* stream);
-int absorber_warm_targets(absorber_t* h, const double* x_dev, float* T_dev, void* stream);
-int absorber_warm_point(absorber_t* h, const float* Y_dev, double d_margin, double* x0_dev, void* stream);
+int absorber_warm_targets(absorber_t* h, const double* x_dev, const double* lambda_dev, float* T_dev,
+                          void* stream);
+int absorber_warm_point(absorber_t* h, const float* Y_dev, int32_t n_out, double d_margin, double* x0_dev,
+                        double* lambda0_dev, void* stream);
 int absorber_warm_start(absorber_t* h, absorber_mlp* net, float* X_work_dev, float* Y_work_dev, double d_margin,
-                        double* x0_dev, void* stream);
+                        double* x0_dev, double* lambda0_dev, void* stream);
 /* Warm-started solve with cold-start fallback: warm_start (workspaces owned by
  * the handle, allocated on the first call), then absorber_ipm_solve with
- * opts->warm_start = 1 and the least-squares multiplier estimate; if that does
+ * opts->warm_start = 1 and the predicted multipliers (primal-dual network) or
+ * the least-squares multiplier estimate (primal network); if that does
  * not reach opts->tol, a cold-started solve from the paper's initial point.
  * *used_warm (may be NULL) is 1 when the warm solve succeeded.  result->seconds
  * covers the whole call and result->iterations both solves.  Blocking. */

@@ -162,9 +162,9 @@ def lib():
                                                   ctypes.POINTER(MlpTrainResult)]),
             "absorber_simulate": (ctypes.c_int, [vp, vp, dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "absorber_warm_features": (ctypes.c_int, [vp, vp, vp]),
-            "absorber_warm_targets": (ctypes.c_int, [vp, vp, vp, vp]),
-            "absorber_warm_point": (ctypes.c_int, [vp, vp, dbl, vp, vp]),
-            "absorber_warm_start": (ctypes.c_int, [vp, vp, vp, vp, dbl, vp, vp]),
+            "absorber_warm_targets": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+            "absorber_warm_point": (ctypes.c_int, [vp, vp, i32, dbl, vp, vp, vp]),
+            "absorber_warm_start": (ctypes.c_int, [vp, vp, vp, vp, dbl, vp, vp, vp]),
             "absorber_warm_solve": (ctypes.c_int, [vp, vp, ctypes.POINTER(IpmOptions), dbl, vp, vp,
                                                    ctypes.POINTER(IpmResult), ctypes.POINTER(ctypes.c_int32)]),
         }
@@ -383,17 +383,18 @@ class Absorber:
         """X: float32 (S, 3) device tensor <- (gas flow, CO2 fraction, gas temperature) per scenario."""
         _check(lib().absorber_warm_features(self.h, _ptr(X), _stream(stream)))
 
-    def warm_targets(self, x, T, stream=None):
-        """T: float32 (S, 21 N) <- network encoding of the primal vector x (float64, nx)."""
-        _check(lib().absorber_warm_targets(self.h, _ptr(x), _ptr(T), _stream(stream)))
+    def warm_targets(self, x, T, lam=None, stream=None):
+        """T: float32 (S, 21 N) or, with lam, (S, 43 N) <- network encoding of x (float64, nx) [and lam (nc)]."""
+        _check(lib().absorber_warm_targets(self.h, _ptr(x), _ptr(lam), _ptr(T), _stream(stream)))
 
-    def warm_point(self, Y, x0, d_margin=1e-3, stream=None):
-        """x0 (float64, nx) <- decoded stage vectors Y (float32, (S, 21 N)) and the starting diameter."""
-        _check(lib().absorber_warm_point(self.h, _ptr(Y), float(d_margin), _ptr(x0), _stream(stream)))
-
-    def warm_start(self, net: "Mlp", X_work, Y_work, x0, d_margin=1e-3, stream=None):
-        _check(lib().absorber_warm_start(self.h, net.h, _ptr(X_work), _ptr(Y_work), float(d_margin), _ptr(x0),
+    def warm_point(self, Y, x0, lam0=None, d_margin=1e-3, stream=None):
+        """x0 (float64, nx) [and lam0 (nc)] <- decoded network rows Y (float32, (S, n_out))."""
+        _check(lib().absorber_warm_point(self.h, _ptr(Y), int(Y.shape[1]), float(d_margin), _ptr(x0), _ptr(lam0),
                                          _stream(stream)))
+
+    def warm_start(self, net: "Mlp", X_work, Y_work, x0, lam0=None, d_margin=1e-3, stream=None):
+        _check(lib().absorber_warm_start(self.h, net.h, _ptr(X_work), _ptr(Y_work), float(d_margin), _ptr(x0),
+                                         _ptr(lam0), _stream(stream)))
 
     def warm_solve(self, net: "Mlp", opts: IpmOptions | None = None, d_margin=1e-3, x_out=None, lam_out=None):
         """Warm-started solve with cold fallback; returns (result, used_warm)."""

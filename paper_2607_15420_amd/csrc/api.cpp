@@ -164,7 +164,7 @@ static void free_handle(Handle& h) {
   if (h.ev1) (void)hipEventDestroy(h.ev1);
   void* ptrs[] = {h.feeds, h.gather, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
-                  h.warm_X, h.warm_Y, h.warm_x0, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
+                  h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
                   h.seg, h.pseg, h.dwv, h.dcv, h.fmask, h.pact};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

@@ -142,6 +142,8 @@ struct Handle {
   float* warm_X = nullptr;                   // warm-start workspaces (allocated on first use)
   float* warm_Y = nullptr;
   double* warm_x0 = nullptr;
+  double* warm_l0 = nullptr;
+  int* warm_w = nullptr;
   long long n_factor = 0, n_solve = 0;       // launch counters
   // optional per-class kernel timing (HIP events on the launch stream)
   int prof = 0;  // bit mask of the profiled kernel classes

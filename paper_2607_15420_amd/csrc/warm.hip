@@ -24,6 +24,7 @@ namespace {
 constexpr int WB = 256;
 constexpr int NLOG = 13;            // stage-local entries encoded by their logarithm
 constexpr double LOG_FLOOR = 1e-30;
+constexpr double DUAL_SCALE = 1e-6;  // multipliers are encoded as asinh(lambda / DUAL_SCALE): signed, log-like
 
 __global__ void k_features(const double* __restrict__ feeds, int S, float* __restrict__ X) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -34,44 +35,87 @@ __global__ void k_features(const double* __restrict__ feeds, int S, float* __res
   X[w * 3 + 2] = (float)F[5];  // flue-gas temperature
 }
 
-__global__ void k_targets(const double* __restrict__ x, long long n, float* __restrict__ T) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int k = (int)(i % NV);
-  const double v = x[i];
-  T[i] = (float)(k < NLOG ? log(fmax(v, LOG_FLOOR)) : v);
+// network row of chain w: its N stage vectors (21 each), then, for a
+// primal-dual network, its N row-multiplier vectors (22 each); ld = 21 N or 43 N
+__global__ void k_targets(const double* __restrict__ x, const double* __restrict__ lam,
+                          const StageInfo* __restrict__ sinfo, long long nst, int ld, float* __restrict__ T) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nst) return;
+  const StageInfo si = sinfo[t];
+  float* row = T + (long long)si.w * ld;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double v = x[t * NV + k];
+    row[si.n * NV + k] = (float)(k < NLOG ? log(fmax(v, LOG_FLOOR)) : v);
+  }
+  if (lam)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) row[si.N * NV + si.n * NR + r] = (float)asinh(lam[t * NR + r] / DUAL_SCALE);
 }
 
 // decode the predicted stage vectors; each stage's hydraulic diameter into dh
-__global__ void k_decode(const float* __restrict__ Y, const double* __restrict__ feeds, ModelParams p,
+__global__ void k_decode(const float* __restrict__ Y, int ld, const double* __restrict__ feeds, ModelParams p,
                          const StageInfo* __restrict__ sinfo, long long nst, double* __restrict__ x0,
                          double* __restrict__ dh) {
   const long long t = (long long)blockIdx.x * WB + threadIdx.x;
   if (t >= nst) return;
-  const float* y = Y + t * NV;
+  const StageInfo si = sinfo[t];
+  const float* y = Y + (long long)si.w * ld + si.n * NV;
   double* z = x0 + t * NV;
 #pragma unroll
   for (int k = 0; k < NV; ++k) z[k] = k < NLOG ? exp((double)y[k]) : (double)y[k];
-  const double P = feeds[(long long)sinfo[t].w * NF + 17];
+  const double P = feeds[(long long)si.w * NF + 17];
   const double V = z[IV], T = z[IT];
   const double a = 4.0 * V * p.R * T / (M_PI * p.u_max * P);
   dh[t] = a > 0.0 ? sqrt(a) : 0.0;
 }
 
-// d_p = (1 + margin) * the largest hydraulic diameter of problem p (one block per problem)
-__global__ void k_decode_d(const double* __restrict__ dh, const long long* __restrict__ pstage, double margin,
-                           double* __restrict__ d0) {
+// per problem (one block each): d_p = (1 + margin) * the largest stage diameter,
+// wmax[p] = the chain holding it (lowest stage index on ties)
+__global__ void k_decode_d(const double* __restrict__ dh, const long long* __restrict__ pstage,
+                           const StageInfo* __restrict__ sinfo, double margin, double* __restrict__ d0,
+                           int* __restrict__ wmax) {
   __shared__ double sm[WB];
+  __shared__ long long si[WB];
   const int pb = blockIdx.x;
-  double m = 0.0;
-  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += WB) m = fmax(m, dh[t]);
+  double m = -1.0;
+  long long at = pstage[pb];
+  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += WB)
+    if (dh[t] > m) {
+      m = dh[t];
+      at = t;
+    }
   sm[threadIdx.x] = m;
+  si[threadIdx.x] = at;
   __syncthreads();
   for (int s = WB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) {
+      const double o = sm[threadIdx.x + s];
+      const long long oi = si[threadIdx.x + s];
+      if (o > sm[threadIdx.x] || (o == sm[threadIdx.x] && oi < si[threadIdx.x])) {
+        sm[threadIdx.x] = o;
+        si[threadIdx.x] = oi;
+      }
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) d0[pb] = (1.0 + margin) * sm[0];
+  if (threadIdx.x == 0) {
+    d0[pb] = (1.0 + margin) * fmax(sm[0], 0.0);
+    if (wmax) wmax[pb] = sinfo[si[0]].w;
+  }
+}
+
+// predicted row multipliers for the worst scenario of each problem (the only one
+// whose hydraulic rows are active at the optimum), zero for the others
+__global__ void k_decode_duals(const float* __restrict__ Y, int ld, const StageInfo* __restrict__ sinfo,
+                               long long nst, const int* __restrict__ wmax, double* __restrict__ lam0) {
+  const long long t = (long long)blockIdx.x * WB + threadIdx.x;
+  if (t >= nst) return;
+  const StageInfo si = sinfo[t];
+  const bool worst = si.w == wmax[si.p];
+  const float* y = Y + (long long)si.w * ld + si.N * NV + si.n * NR;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) lam0[t * NR + r] = worst ? DUAL_SCALE * sinh((double)y[r]) : 0.0;
 }
 
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -80,6 +124,7 @@ inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs)
 }  // namespace absorber
 
 using absorber::Handle;
+using absorber::NR;
 using absorber::NV;
 using absorber::set_error;
 
@@ -97,38 +142,57 @@ int absorber_warm_features(absorber_t* ah, float* X_dev, void* stream) {
   return ABS_OK;
 }
 
-int absorber_warm_targets(absorber_t* ah, const double* x_dev, float* T_dev, void* stream) {
+int absorber_warm_targets(absorber_t* ah, const double* x_dev, const double* lambda_dev, float* T_dev,
+                          void* stream) {
   if (!ah || !x_dev || !T_dev) {
     set_error("absorber_warm_targets: bad argument");
     return ABS_ERR_ARG;
   }
   Handle& h = ah->h;
-  const long long n = h.nst * NV;
-  hipLaunchKernelGGL(absorber::k_targets, dim3(absorber::nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x_dev,
-                     n, T_dev);
+  for (int n : h.pN)
+    if (n != h.N) {
+      set_error("absorber_warm_targets: every problem must have the same stage count");
+      return ABS_ERR_ARG;
+    }
+  const int ld = (lambda_dev ? NV + NR : NV) * h.N;
+  hipLaunchKernelGGL(absorber::k_targets, dim3(absorber::nblk(h.nst, 256)), dim3(256), 0, (hipStream_t)stream, x_dev,
+                     lambda_dev, h.sinfo, h.nst, ld, T_dev);
   HIP_TRY(hipGetLastError());
   return ABS_OK;
 }
 
-int absorber_warm_point(absorber_t* ah, const float* Y_dev, double d_margin, double* x0_dev, void* stream) {
+int absorber_warm_point(absorber_t* ah, const float* Y_dev, int32_t n_out, double d_margin, double* x0_dev,
+                        double* lambda0_dev, void* stream) {
   if (!ah || !Y_dev || !x0_dev || !(d_margin >= 0.0)) {
     set_error("absorber_warm_point: bad argument");
     return ABS_ERR_ARG;
   }
   Handle& h = ah->h;
+  bool same = true;
+  for (int n : h.pN) same = same && n == h.N;
+  const bool pd = n_out == (NV + NR) * h.N;
+  if (!same || !(n_out == NV * h.N || pd) || (lambda0_dev && !pd)) {
+    set_error("absorber_warm_point: n_out must be 21 N (primal) or 43 N (primal-dual, needed for lambda0), "
+              "every problem N stages");
+    return ABS_ERR_ARG;
+  }
+  if (!h.warm_w) HIP_TRY(hipMalloc((void**)&h.warm_w, sizeof(int) * (size_t)h.P));
   const long long nst = h.nst;
   hipStream_t st = (hipStream_t)stream;
   double* dh = h.kden;  // per-stage scratch
   hipLaunchKernelGGL(absorber::k_decode, dim3(absorber::nblk(nst, absorber::WB)), dim3(absorber::WB), 0, st, Y_dev,
-                     h.feeds, h.mp, h.sinfo, nst, x0_dev, dh);
-  hipLaunchKernelGGL(absorber::k_decode_d, dim3(h.P), dim3(absorber::WB), 0, st, dh, h.pstage, d_margin,
-                     x0_dev + nst * NV);
+                     n_out, h.feeds, h.mp, h.sinfo, nst, x0_dev, dh);
+  hipLaunchKernelGGL(absorber::k_decode_d, dim3(h.P), dim3(absorber::WB), 0, st, dh, h.pstage, h.sinfo, d_margin,
+                     x0_dev + nst * NV, h.warm_w);
+  if (lambda0_dev)
+    hipLaunchKernelGGL(absorber::k_decode_duals, dim3(absorber::nblk(nst, absorber::WB)), dim3(absorber::WB), 0, st,
+                       Y_dev, n_out, h.sinfo, nst, h.warm_w, lambda0_dev);
   HIP_TRY(hipGetLastError());
   return ABS_OK;
 }
 
 int absorber_warm_start(absorber_t* ah, absorber_mlp* net, float* X_work_dev, float* Y_work_dev, double d_margin,
-                        double* x0_dev, void* stream) {
+                        double* x0_dev, double* lambda0_dev, void* stream) {
   if (!ah || !net || !X_work_dev || !Y_work_dev || !x0_dev) {
     set_error("absorber_warm_start: bad argument");
     return ABS_ERR_ARG;
@@ -136,15 +200,13 @@ int absorber_warm_start(absorber_t* ah, absorber_mlp* net, float* X_work_dev, fl
   absorber_mlp_config cfg;
   int rc = absorber_mlp_get_config(net, &cfg);
   if (rc) return rc;
-  bool fits = cfg.n_in == 3;
-  for (int n : ah->h.pN) fits = fits && cfg.n_out == NV * n;
-  if (!fits) {
-    set_error("absorber_warm_start: the network needs 3 inputs and 21 N outputs (every problem N stages)");
+  if (cfg.n_in != 3) {
+    set_error("absorber_warm_start: the network needs 3 inputs");
     return ABS_ERR_ARG;
   }
   rc = absorber_warm_features(ah, X_work_dev, stream);
   if (!rc) rc = absorber_mlp_forward(net, X_work_dev, ah->h.S, Y_work_dev, stream);
-  if (!rc) rc = absorber_warm_point(ah, Y_work_dev, d_margin, x0_dev, stream);
+  if (!rc) rc = absorber_warm_point(ah, Y_work_dev, cfg.n_out, d_margin, x0_dev, lambda0_dev, stream);
   return rc;
 }
 
@@ -159,17 +221,22 @@ int absorber_warm_solve(absorber_t* ah, absorber_mlp* net, const absorber_ipm_op
     return ABS_ERR_ARG;
   }
   Handle& h = ah->h;
+  absorber_mlp_config cfg;
+  int rc = absorber_mlp_get_config(net, &cfg);
+  if (rc) return rc;
+  const bool pd = cfg.n_out == (NV + NR) * h.N;  // primal-dual network: predicted multipliers
   if (!h.warm_X) {
     HIP_TRY(hipMalloc((void**)&h.warm_X, sizeof(float) * 3 * (size_t)h.S));
-    HIP_TRY(hipMalloc((void**)&h.warm_Y, sizeof(float) * (size_t)NV * h.nst));
+    HIP_TRY(hipMalloc((void**)&h.warm_Y, sizeof(float) * (size_t)(NV + NR) * h.nst));
     HIP_TRY(hipMalloc((void**)&h.warm_x0, sizeof(double) * (size_t)h.nx));
+    HIP_TRY(hipMalloc((void**)&h.warm_l0, sizeof(double) * (size_t)h.nc));
   }
   const auto t0 = std::chrono::steady_clock::now();
-  int rc = absorber_warm_start(ah, net, h.warm_X, h.warm_Y, d_margin, h.warm_x0, h.stream);
+  rc = absorber_warm_start(ah, net, h.warm_X, h.warm_Y, d_margin, h.warm_x0, pd ? h.warm_l0 : nullptr, h.stream);
   if (rc) return rc;
   absorber_ipm_options ow = *opts;
   ow.warm_start = 1;
-  rc = absorber_ipm_solve(ah, &ow, h.warm_x0, nullptr, x_out_dev, lambda_out_dev, result);
+  rc = absorber_ipm_solve(ah, &ow, h.warm_x0, pd ? h.warm_l0 : nullptr, x_out_dev, lambda_out_dev, result);
   const bool ok = rc == ABS_OK && result->status == ABS_OK;
   if (used_warm) *used_warm = ok ? 1 : 0;
   if (!ok) {  // cold-start fallback

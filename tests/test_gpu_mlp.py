@@ -213,3 +213,64 @@ def test_warm_start_solve(params):
     print(f"warm {rw.iterations} iterations, cold {rc.iterations}; train loss {tr.final_loss:.2e}")
     h.close()
     net.close()
+
+
+def test_primal_dual_encoding_roundtrip(params):
+    """Multipliers are encoded as asinh(lambda / 1e-6); decoding gives them back for
+    the worst scenario (largest hydraulic diameter) and zero for the others."""
+    from paper_2607_15420_amd import Absorber
+    w = CONFIGS["C1"]
+    F = w.feeds(params)
+    N, S = w.n_stages, F.shape[0]
+    h = Absorber(params, N, F)
+    x = torch.empty(h.nx, dtype=torch.float64, device=DEV)
+    lam = torch.empty(h.nc, dtype=torch.float64, device=DEV)
+    r = h.ipm_solve(x_out=x, lam_out=lam)
+    assert r.status == 0
+    T = torch.empty((S, 43 * N), dtype=torch.float32, device=DEV)
+    h.warm_targets(x, T, lam)
+    x0 = torch.empty(h.nx, dtype=torch.float64, device=DEV)
+    l0 = torch.empty(h.nc, dtype=torch.float64, device=DEV)
+    h.warm_point(T, x0, l0, d_margin=0.0)
+    torch.cuda.synchronize()
+    lh, l0h = lam.cpu().numpy().reshape(S, N, 22), l0.cpu().numpy().reshape(S, N, 22)
+    Z = x.cpu().numpy()[:-1].reshape(S, N, 21)
+    P = M.OracleParams(params)
+    dh = [simulate.hydraulic_diameter(Z[s], F[s], P) for s in range(S)]
+    worst = int(np.argmax(dh))
+    assert np.allclose(l0h[worst], lh[worst], rtol=1e-5, atol=1e-10)
+    assert np.all(l0h[np.arange(S) != worst] == 0.0)
+    assert x0.cpu().numpy()[-1] == pytest.approx(max(dh), rel=1e-6)
+    h.close()
+
+
+def test_primal_dual_network_from_batched_single_scenario_solves(params):
+    """Training data from the batched solver (one single-scenario problem per
+    training scenario, primal and dual solutions), a 43 N-output network, and the
+    warm start with predicted multipliers reaches the closed form faster than cold."""
+    from paper_2607_15420_amd import Absorber, Mlp
+    N, n_train = 10, 2048
+    Ftr = feed_table(perturbations(n_train, 0.2, 4), params)
+    hb = Absorber.batch(params, [(N, Ftr[i:i + 1]) for i in range(n_train)])
+    x = torch.empty(hb.nx, dtype=torch.float64, device=DEV)
+    lam = torch.empty(hb.nc, dtype=torch.float64, device=DEV)
+    rc, res = hb.batch_solve(x_out=x, lam_out=lam)
+    assert rc == 0
+    X = torch.empty((n_train, 3), dtype=torch.float32, device=DEV)
+    T = torch.empty((n_train, 43 * N), dtype=torch.float32, device=DEV)
+    hb.warm_features(X)
+    hb.warm_targets(x, T, lam)
+    hb.close()
+    net = Mlp(3, 256, 3, 43 * N, max_batch=512, seed=0)
+    tr = net.train(X, T, net.default_train_options(epochs=150, batch=256, lr=2e-3))
+    Fte = feed_table(perturbations(300, 0.2, 3), params)
+    h = Absorber(params, N, Fte)
+    rc_ = h.ipm_solve()
+    rw, used = h.warm_solve(net)
+    dstar, _, _, ok = simulate.closed_form_diameter(Fte, N, params)
+    assert ok.all() and used, (tr.final_loss, rw.as_dict())
+    assert rw.status == 0 and rw.E0 <= 1e-8 and abs(rw.d - dstar) / dstar <= 1e-6
+    assert rw.iterations < rc_.iterations, (rw.iterations, rc_.iterations)
+    print(f"primal-dual warm {rw.iterations} iterations, cold {rc_.iterations}; train loss {tr.final_loss:.2e}")
+    h.close()
+    net.close()
