@@ -371,7 +371,7 @@ class Absorber:
         _check(lib().absorber_kkt_solve(self.h, _ptr(rhs), _ptr(sol), ctypes.byref(rel), _stream(stream)))
         return rel.value
 
-    def simulate(self, x, tol=1e-10, max_iter=100):
+    def simulate(self, x, tol=1e-12, max_iter=100):
         """Process simulation of every scenario from x (in/out); returns (converged per problem, iterations)."""
         conv = np.zeros(self.P, np.int32)
         it = ctypes.c_int32()

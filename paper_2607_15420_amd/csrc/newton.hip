@@ -13,6 +13,9 @@
 // is capped at 5, and each chain backtracks on its own scaled residual
 // inf-norm with a sufficient-decrease test.
 //
+// A scenario whose Newton iteration stalls starts again (at most twice) from the
+// converged states of the closest scenario (in feed) of the same problem.
+//
 // Used by the interior-point driver as a feasibility restart: a problem whose
 // cold-started solve stops (line-search failure, inertia failure, iteration
 // limit) is solved again from its simulated states.
@@ -87,6 +90,18 @@ __global__ void k_newton_trial(const double* __restrict__ x, const double* __res
   const double a = aw[sinfo[i / NV].w];
   const int k = (int)(i % NV);
   xt[i] = k < NLOG ? x[i] * exp(a * dx[i] / x[i]) : x[i] + a * dx[i];
+}
+
+// restart chains from the states of another chain of the same stage count:
+// xt[stage n of chain w] = xt[stage n of chain src[w]] for src[w] >= 0
+__global__ void k_copy_chain(double* __restrict__ xt, const int* __restrict__ src, const int* __restrict__ chain0,
+                             const StageInfo* __restrict__ sinfo, long long nxs) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nxs) return;
+  const StageInfo si = sinfo[i / NV];
+  const int s = src[si.w];
+  if (s < 0) return;
+  xt[i] = xt[((long long)chain0[s] + si.n) * NV + (i % NV)];
 }
 
 __global__ void k_scale(const double* __restrict__ x, Scaling sc, long long nx, long long nxs, int divide,
@@ -175,6 +190,9 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
   double *aw_h, *st_h;
   HIP_TRY(B.h(&aw_h, W));
   HIP_TRY(B.h(&st_h, 2LL * W));
+  int *src, *src_h;
+  HIP_TRY(B.d(&src, W));
+  HIP_TRY(B.h(&src_h, W));
   std::vector<int> wp((size_t)W);  // problem of each chain
   for (int p = 0; p < P; ++p)
     for (long long w = h.pchain_h[(size_t)p]; w < h.pchain_h[(size_t)p + 1]; ++w) wp[(size_t)w] = p;
@@ -209,56 +227,93 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
   for (int w = 0; w < W; ++w) nr[(size_t)w] = st_h[2 * w];
   std::vector<char> stalled((size_t)W, 0);  // backtracking exhausted without decrease
   auto wanted = [&](int w) { return (!pmask || pmask[wp[(size_t)w]]) && !stalled[(size_t)w]; };
-  int it = 0;
-  for (; it < max_iter; ++it) {
-    bool any = false;
-    for (int w = 0; w < W; ++w) any = any || (wanted(w) && !(nr[(size_t)w] <= tol));
-    if (!any) break;
-    hipLaunchKernelGGL(k_newton_rhs, dim3(nblk(nkkt, BS)), dim3(BS), 0, st, c, nks, nkkt, rhs);
-    HIP_TRY(launch_factor(h, h.diagx, h.diags, rhs, true, st));
-    HIP_TRY(launch_schur(h, h.diagx, rhs, 1, sol, st));
-    double rel = 0.0;
-    {
-      const int rc = kkt_solve_refined(h, rhs, sol, true, &rel, st);
-      if (rc) return rc;
-    }
-    hipLaunchKernelGGL(k_primal_of, dim3(nblk(nx, BS)), dim3(BS), 0, st, sol, nxs, nx, nks, dx);
-    hipLaunchKernelGGL(k_chain_stats, dim3(nblk(W, 64)), dim3(64), 0, st, c, xt, dx, h.chain0, W, stats);
-    HIP_TRY(hipMemcpyAsync(st_h, stats, sizeof(double) * 2 * W, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    std::vector<char> searching((size_t)W, 0);
-    for (int w = 0; w < W; ++w) {
-      const bool go = wanted(w) && !(nr[(size_t)w] <= tol);
-      const double big = st_h[2 * w + 1];
-      aw_h[w] = go ? (big > 5.0 ? 5.0 / big : 1.0) : 0.0;
-      searching[(size_t)w] = go;
-    }
-    while (true) {  // backtracking, every chain on its own residual
-      HIP_TRY(hipMemcpyAsync(aw, aw_h, sizeof(double) * W, hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_newton_trial, dim3(nblk(nx, BS)), dim3(BS), 0, st, xt, dx, aw, h.sinfo, nxs, nx, xtt);
-      HIP_TRY(launch_eval(h, xtt, 1, nullptr, 0, ct, st));
-      hipLaunchKernelGGL(k_chain_stats, dim3(nblk(W, 64)), dim3(64), 0, st, ct, xtt, nullptr, h.chain0, W, stats);
+  int it = 0, it_total = 0;
+  for (int round = 0; round < 3; ++round) {
+    for (it = 0; it < max_iter; ++it, ++it_total) {
+      bool any = false;
+      for (int w = 0; w < W; ++w) any = any || (wanted(w) && !(nr[(size_t)w] <= tol));
+      if (!any) break;
+      hipLaunchKernelGGL(k_newton_rhs, dim3(nblk(nkkt, BS)), dim3(BS), 0, st, c, nks, nkkt, rhs);
+      HIP_TRY(launch_factor(h, h.diagx, h.diags, rhs, true, st));
+      HIP_TRY(launch_schur(h, h.diagx, rhs, 1, sol, st));
+      double rel = 0.0;
+      {
+        const int rc = kkt_solve_refined(h, rhs, sol, true, &rel, st);
+        if (rc) return rc;
+      }
+      hipLaunchKernelGGL(k_primal_of, dim3(nblk(nx, BS)), dim3(BS), 0, st, sol, nxs, nx, nks, dx);
+      hipLaunchKernelGGL(k_chain_stats, dim3(nblk(W, 64)), dim3(64), 0, st, c, xt, dx, h.chain0, W, stats);
       HIP_TRY(hipMemcpyAsync(st_h, stats, sizeof(double) * 2 * W, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
-      bool more = false;
+      std::vector<char> searching((size_t)W, 0);
       for (int w = 0; w < W; ++w) {
-        if (!searching[(size_t)w]) continue;
-        const double a = aw_h[w], nt = st_h[2 * w];
-        const bool dec = std::isfinite(nt) && nt < (1.0 - 1e-4 * a) * nr[(size_t)w];
-        if (dec || a < 1e-10) {
-          searching[(size_t)w] = 0;
-          if (!dec) stalled[(size_t)w] = 1;  // no decrease even for a tiny step: give up on this chain
-          nr[(size_t)w] = nt;
-          continue;
-        }
-        aw_h[w] = 0.5 * a;
-        more = true;
+        const bool go = wanted(w) && !(nr[(size_t)w] <= tol);
+        const double big = st_h[2 * w + 1];
+        aw_h[w] = go ? (big > 5.0 ? 5.0 / big : 1.0) : 0.0;
+        searching[(size_t)w] = go;
       }
-      if (!more) break;
+      while (true) {  // backtracking, every chain on its own residual
+        HIP_TRY(hipMemcpyAsync(aw, aw_h, sizeof(double) * W, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_newton_trial, dim3(nblk(nx, BS)), dim3(BS), 0, st, xt, dx, aw, h.sinfo, nxs, nx, xtt);
+        HIP_TRY(launch_eval(h, xtt, 1, nullptr, 0, ct, st));
+        hipLaunchKernelGGL(k_chain_stats, dim3(nblk(W, 64)), dim3(64), 0, st, ct, xtt, nullptr, h.chain0, W, stats);
+        HIP_TRY(hipMemcpyAsync(st_h, stats, sizeof(double) * 2 * W, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        bool more = false;
+        for (int w = 0; w < W; ++w) {
+          if (!searching[(size_t)w]) continue;
+          const double a = aw_h[w], nt = st_h[2 * w];
+          const bool dec = std::isfinite(nt) && nt < (1.0 - 1e-4 * a) * nr[(size_t)w];
+          if (dec || a < 1e-10) {
+            searching[(size_t)w] = 0;
+            if (!dec) stalled[(size_t)w] = 1;  // no decrease even for a tiny step: give up on this chain
+            nr[(size_t)w] = nt;
+            continue;
+          }
+          aw_h[w] = 0.5 * a;
+          more = true;
+        }
+        if (!more) break;
+      }
+      std::swap(xt, xtt);
+      HIP_TRY(launch_eval(h, xt, 1, nullptr, 1, c, st));
     }
-    std::swap(xt, xtt);
+    // chains that did not converge start again from the states of the converged
+    // chain of the same problem whose feed is closest (scenarios differ only in
+    // their feeds, so a neighbour's solution is a close starting point)
+    bool any_src = false;
+    for (int w = 0; w < W; ++w) {
+      src_h[w] = -1;
+      if (!(!pmask || pmask[wp[(size_t)w]]) || nr[(size_t)w] <= tol) continue;
+      const int p = wp[(size_t)w];
+      const double* fw = &h.feeds_h[(size_t)w * NF];
+      double best = INFINITY;
+      for (long long v = h.pchain_h[(size_t)p]; v < h.pchain_h[(size_t)p + 1]; ++v) {
+        if (!(nr[(size_t)v] <= tol)) continue;
+        const double* fv = &h.feeds_h[(size_t)v * NF];
+        const double dist = fabs(fv[0] - fw[0]) / fabs(fw[0]) + fabs(fv[1] - fw[1]) / fabs(fw[1]) +
+                            fabs(fv[5] - fw[5]) / fabs(fw[5]);
+        if (dist < best) {
+          best = dist;
+          src_h[w] = (int)v;
+        }
+      }
+      any_src = any_src || src_h[w] >= 0;
+    }
+    if (!any_src) break;
+    HIP_TRY(hipMemcpyAsync(src, src_h, sizeof(int) * W, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_copy_chain, dim3(nblk(nxs, BS)), dim3(BS), 0, st, xt, src, h.chain0, h.sinfo, nxs);
     HIP_TRY(launch_eval(h, xt, 1, nullptr, 1, c, st));
+    hipLaunchKernelGGL(k_chain_stats, dim3(nblk(W, 64)), dim3(64), 0, st, c, xt, nullptr, h.chain0, W, stats);
+    HIP_TRY(hipMemcpyAsync(st_h, stats, sizeof(double) * 2 * W, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int w = 0; w < W; ++w)
+      if (src_h[w] >= 0) {
+        nr[(size_t)w] = st_h[2 * w];
+        stalled[(size_t)w] = 0;
+      }
   }
+  it = it_total;
   hipLaunchKernelGGL(k_scale, dim3(nblk(nx, BS)), dim3(BS), 0, st, xt, h.sc, nx, nxs, 0, x_dev);
   HIP_TRY(hipStreamSynchronize(st));
   if (conv)
