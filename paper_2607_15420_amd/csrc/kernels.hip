@@ -267,33 +267,29 @@ __device__ __forceinline__ double rowsel(const double (&v)[FR], int p) {
   }
 }
 
-// Wave maximum of a non-negative double with its lane: the lane is packed into
-// the 6 lowest mantissa bits (as 63 - lane, so ties go to the lowest lane) and
-// the 64-bit patterns, ordered like the values, are max-reduced with DPP row
-// shifts and row broadcasts; lane 63 ends with the maximum.
-#define ABS_DPP_MAX_U64(v, ctrl, rm, bm)                                                \
-  do {                                                                                 \
-    const unsigned lo_ = (unsigned)(v), hi_ = (unsigned)((v) >> 32);                   \
-    const unsigned olo_ = __builtin_amdgcn_update_dpp(0u, lo_, ctrl, rm, bm, false);   \
-    const unsigned ohi_ = __builtin_amdgcn_update_dpp(0u, hi_, ctrl, rm, bm, false);   \
-    const unsigned long long o_ = ((unsigned long long)ohi_ << 32) | olo_;              \
-    (v) = o_ > (v) ? o_ : (v);                                                          \
+// Wave maximum of a non-negative double and its lane.  The key is the high
+// word of the value (sign, exponent, 20 mantissa bits) with its 6 lowest bits
+// replaced by 63 - lane (ties go to the lowest lane); keys are max-reduced with
+// DPP row shifts and row broadcasts and lane 63 ends with the maximum.  The
+// returned value keeps 14 mantissa bits (relative truncation below 2^-14),
+// which is all the pivot tests compare.
+#define ABS_DPP_MAX_U32(k, ctrl, rm, bm)                                                          \
+  do {                                                                                           \
+    const unsigned o_ = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(k), ctrl, rm, bm, false); \
+    (k) = o_ > (k) ? o_ : (k);                                                                   \
   } while (0)
 
 __device__ __forceinline__ double wave_max_lane(double a, int lane, int& idx) {
-  unsigned long long b = (unsigned long long)__double_as_longlong(a);
-  b = (b & ~63ull) | (unsigned long long)(63 - lane);
-  ABS_DPP_MAX_U64(b, 0x111, 0xf, 0xf);  // row_shr:1
-  ABS_DPP_MAX_U64(b, 0x112, 0xf, 0xf);  // row_shr:2
-  ABS_DPP_MAX_U64(b, 0x114, 0xf, 0xf);  // row_shr:4
-  ABS_DPP_MAX_U64(b, 0x118, 0xf, 0xf);  // row_shr:8
-  ABS_DPP_MAX_U64(b, 0x142, 0xa, 0xf);  // row_bcast:15
-  ABS_DPP_MAX_U64(b, 0x143, 0xc, 0xf);  // row_bcast:31
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, 63);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), 63);
-  const unsigned long long m = ((unsigned long long)hi << 32) | lo;
-  idx = 63 - (int)(m & 63ull);
-  return __longlong_as_double((long long)(m & ~63ull));
+  unsigned key = ((unsigned)__double2hiint(a) & ~63u) | (unsigned)(63 - lane);
+  ABS_DPP_MAX_U32(key, 0x111, 0xf, 0xf);  // row_shr:1
+  ABS_DPP_MAX_U32(key, 0x112, 0xf, 0xf);  // row_shr:2
+  ABS_DPP_MAX_U32(key, 0x114, 0xf, 0xf);  // row_shr:4
+  ABS_DPP_MAX_U32(key, 0x118, 0xf, 0xf);  // row_shr:8
+  ABS_DPP_MAX_U32(key, 0x142, 0xa, 0xf);  // row_bcast:15
+  ABS_DPP_MAX_U32(key, 0x143, 0xc, 0xf);  // row_bcast:31
+  const unsigned m = (unsigned)__builtin_amdgcn_readlane((int)key, 63);
+  idx = 63 - (int)(m & 63u);
+  return __hiloint2double((int)(m & ~63u), 0);
 }
 
 // Eliminate the 43 own pivots of one stage (Bunch-Kaufman inside the stage);
@@ -311,7 +307,11 @@ __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restr
     const int k = __builtin_ctzll(act);
     const bool own_act = lane < NK && ((act >> lane) & 1ull);
     const double rowk = rowsel(v, k);  // F[k][lane] = F[lane][k]
-    const double akk = fabs(rdl(rowk, k));
+    const double dkk = rdl(rowk, k);
+    // 1/d for the usual 1x1 pivot at k, started before the search so that the
+    // two dependency chains overlap
+    const double dinv_k = dkk == 0.0 ? 0.0 : 1.0 / dkk;
+    const double akk = fabs(dkk);
     int r;
     const double lam = wave_max_lane(own_act && lane != k ? fabs(rowk) : 0.0, lane, r);
     int ptype = 1;  // 1: 1x1 at k, 2: 1x1 at r, 3: 2x2 (k, r)
@@ -334,8 +334,11 @@ __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restr
     double t1 = 0.0, t2 = 0.0;
     bool zero = false;
     if (!two) {
-      const double d = rdl(rk, p0);
-      const double dinv = d == 0.0 ? 0.0 : 1.0 / d;
+      double d = dkk, dinv = dinv_k;
+      if (ptype == 2) {
+        d = rdl(rk, p0);
+        dinv = d == 0.0 ? 0.0 : 1.0 / d;
+      }
       double sv = ca ? rk : 0.0;
       if (lane == FR) sv = (double)(p0 + 64 * (d == 0.0 ? 0 : 1));
       else if (lane == FR + 1) sv = d;
