@@ -130,6 +130,65 @@ static int build_tables(Handle& h) {
   for (auto& e : h.jac_down) jt.push_back(e.row | (e.col << 8) | (e.blk << 16));
   HIP_TRY(dalloc(&h.jtab, jt.size()));
   HIP_TRY(hipMemcpy(h.jtab, jt.data(), jt.size() * sizeof(int), hipMemcpyHostToDevice));
+  // Residual terms: for each KKT row i of a stage, the products K_ij x_j that
+  // make up (K x)_i, as (coefficient, unknown) codes.  The same matrix as the
+  // frontal gather above (own block, couplings to both neighbours, border),
+  // without the factorisation's right-hand side and Schur contributions.
+  enum { X0, XDN, XUP, XD };
+  std::vector<std::vector<std::pair<int, int>>> terms(NK);
+  auto rterm = [&](int row, int coef, int xkind, int xidx) {  // coef: record offset (may lie in a neighbour)
+    const int xc = xkind == XD ? RT_XDTERM
+                               : (xidx + (xkind == XDN ? -NK : (xkind == XUP ? NK : 0)) + RT_XOFF) |
+                                     (xkind == XDN ? RT_NBDN : (xkind == XUP ? RT_NBUP : 0));
+    terms[(size_t)row].push_back({coef + RT_COFF, xc});
+  };
+  auto dterm = [&](int row, int didx) { terms[(size_t)row].push_back({RT_DIAG + didx, row + RT_XOFF}); };
+  for (int e = 0; e < NJO; ++e) {
+    const JacEntry& je = h.jac_own[(size_t)e];
+    if (je.blk == BLK_D) {
+      rterm(NK - 1, REC_OWN + e, XD, 0);  // hydraulic row x border (the d row is reduced separately)
+      continue;
+    }
+    const int lr = je.row < NE ? NV + je.row : NK - 1;
+    rterm(lr, REC_OWN + e, X0, je.col);
+    rterm(je.col, REC_OWN + e, X0, lr);
+  }
+  for (int e = 0; e < NJU; ++e) {  // own rows x the stage above; our variables' rows see the stage below's
+    const JacEntry& je = h.jac_up[(size_t)e];
+    rterm(NV + je.row, REC_UP + e, XUP, je.col);
+    rterm(je.col, REC_UP + e - REC, XDN, NV + je.row);
+  }
+  for (int e = 0; e < NJD; ++e) {  // own rows x the stage below; our variables' rows see the stage above's
+    const JacEntry& je = h.jac_down[(size_t)e];
+    rterm(NV + je.row, REC_DOWN + e, XDN, je.col);
+    rterm(je.col, REC_DOWN + e + REC, XUP, NV + je.row);
+  }
+  for (int e = 0; e < NH; ++e) {
+    rterm(h.hpos[e].r, REC_H + e, X0, h.hpos[e].c);
+    if (h.hpos[e].r != h.hpos[e].c) rterm(h.hpos[e].c, REC_H + e, X0, h.hpos[e].r);
+  }
+  for (int k = 0; k < NV; ++k) dterm(k, k);                 // Sigma_x + delta_w
+  for (int r = 0; r < NE; ++r) dterm(NV + r, NV);           // -delta_c
+  dterm(NK - 1, NV + 1);                                    // -(1/(Sigma_s + delta_w) + delta_c)
+  std::vector<int> order(NK);
+  for (int i = 0; i < NK; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return terms[(size_t)a].size() > terms[(size_t)b].size(); });
+  std::vector<int> rt(order.begin(), order.end());
+  rt.push_back(0);
+  for (int i = 0; i < NK; ++i) rt.push_back(rt.back() + (int)terms[(size_t)order[(size_t)i]].size());
+  for (int i = 0; i < NK; ++i)
+    for (auto& pr : terms[(size_t)order[(size_t)i]]) {
+      rt.push_back(pr.first);
+      rt.push_back(pr.second);
+    }
+  if ((int)rt.size() > RT_MAX) {
+    set_error("internal: residual term table too large");
+    return ABS_ERR_ARG;
+  }
+  HIP_TRY(dalloc(&h.rtab, rt.size()));
+  HIP_TRY(hipMemcpy(h.rtab, rt.data(), rt.size() * sizeof(int), hipMemcpyHostToDevice));
+  h.rtab_n = (int)rt.size();
   return ABS_OK;
 }
 
@@ -162,7 +221,7 @@ void prof_end(Handle& h, int cls, hipStream_t st) {
 static void free_handle(Handle& h) {
   if (h.ev0) (void)hipEventDestroy(h.ev0);
   if (h.ev1) (void)hipEventDestroy(h.ev1);
-  void* ptrs[] = {h.feeds, h.gather, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
+  void* ptrs[] = {h.feeds, h.gather, h.rtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
                   h.seg, h.pseg, h.dwv, h.dcv, h.fmask, h.pact};

@@ -39,6 +39,15 @@ constexpr int SRC_DHYD = SRC_DC + 1;          // -(1/(Sigma_s+delta_w) + delta_c
 constexpr int SRC_CTB = SRC_DHYD + 1;         // contribution block 16 x 18
 constexpr int NSRC = SRC_CTB + NC * (NC + 2); // 569
 
+// Residual term table (one list of products K_ij x_j per KKT row of a stage):
+// [NK] rows in decreasing term count, [NK + 1] starts of their lists, then per
+// term a coefficient code (LDS offset from the stage's record + RT_COFF, or
+// RT_DIAG + index of the stage's diagonal block) and an unknown code (LDS
+// offset from the stage's unknowns + RT_XOFF, RT_XDTERM for d; RT_NBDN / RT_NBUP
+// mark a neighbour below / above).
+constexpr int RT_COFF = 256, RT_DIAG = 1024, RT_XOFF = 64, RT_XDTERM = 256, RT_NBDN = 512, RT_NBUP = 1024;
+constexpr int RT_MAX = 2048;
+
 // the 16 stage-local KKT indices that receive the contribution of the stage below
 __host__ __device__ constexpr int coupling_index(int a) {
   return a < 9 ? a : (a == 9 ? IL : (a == 10 ? IT : (a < 15 ? NV + 7 + (a - 11) : NV + 20)));
@@ -113,6 +122,8 @@ struct Handle {
   HessPos hpos[NH];
   int* gather = nullptr;                     // device [FR][64] packed gather table
   int* jtab = nullptr;                       // device packed Jacobian structure (row, col) per entry
+  int* rtab = nullptr;                       // device residual term table (RT_*)
+  int rtab_n = 0;
   Scaling sc{};
   double* cs = nullptr;                      // device [S][N][NR] row scaling
   double sf = 1.0;

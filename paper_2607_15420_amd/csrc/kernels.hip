@@ -765,118 +765,113 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
 // this stage's unknowns to the rows of the stage above, which that stage adds.
 // Per chain: part[2w] = sum b u_hyd, part[2w+1] = sum |b u_hyd| (d rows),
 // omc[w] = largest componentwise backward error |res_i| / (|K||sol| + |rhs|)_i.
-struct ResLDS {
-  double xf[WAVE];  // broadcast unknowns (first: reachable by immediate offsets)
-  double src[NSRC];
-  double cy[WAVE];  // contribution to the stage above, by stage-local index
-  double ca[WAVE];  // its magnitude sum
-};
+// Residual of the bordered KKT system, res = rhs - K sol, and the componentwise
+// backward error max_i |res_i| / (sum_j |K_ij sol_j| + |rhs_i|).  One block per
+// IPM segment (at most SEG consecutive stages of one problem), one thread per
+// (stage, row).  The block stages the segment's records and unknowns, plus one
+// neighbour on each side, in LDS and each thread walks its row's term list
+// (K_ij from a record or the diagonal, times an unknown of its stage, of a
+// neighbour or d).  Threads are assigned rows in decreasing term count, so
+// that the lanes of a wave walk lists of similar length.
+// part[2 s] = sum over the segment of b_t . sol_hyd(t) and part[2 s + 1] its
+// magnitude (for the d row); omb[s] = the segment's largest backward error.
+constexpr int RBS = ((NK * SEG + WAVE - 1) / WAVE) * WAVE;  // threads per block
+constexpr int RDG = 24;                                      // diagonal coefficients per stage in LDS
 
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3))) void k_residual(
-    const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ diagx,
+__global__ __launch_bounds__(RBS) void k_residual(
+    const double* __restrict__ rec, const int* __restrict__ rtab, int rtab_n, const double* __restrict__ diagx,
     const double* __restrict__ diags, const double* __restrict__ dwv, const double* __restrict__ dcv,
-    const double* __restrict__ sol, const double* __restrict__ rhs, const int* __restrict__ chain0,
-    const int* __restrict__ chain_p, const int* __restrict__ pact, int W, long long nks, int jd,
-    double* __restrict__ res, double* __restrict__ part, double* __restrict__ omc) {
-  __shared__ ResLDS L;
-  const int w = blockIdx.x;
-  if (w >= W) return;
-  const int pw = chain_p[w];
-  const long long t0 = chain0[w];
-  const int N = chain0[w + 1] - (int)t0;
-  const int lane = lane_id();
-  if (pact && !pact[pw]) {  // problem not being worked on: zero residual
-    for (long long i = t0 * NK + lane; i < (t0 + N) * NK; i += WAVE) res[i] = 0.0;
-    if (lane == 0) {
-      part[2 * w] = 0.0;
-      part[2 * w + 1] = 0.0;
-      omc[w] = 0.0;
+    const double* __restrict__ sol, const double* __restrict__ rhs, const Seg* __restrict__ segs,
+    const StageInfo* __restrict__ sinfo, long long nst, const int* __restrict__ pact, long long nks, int jd,
+    double* __restrict__ res, double* __restrict__ part, double* __restrict__ omb) {
+  __shared__ double cf[(SEG + 2) * REC + SEG * RDG];  // records of stages t0-1 .. t1, then diagonals
+  __shared__ double sx[(SEG + 2) * NK];               // unknowns of the same stages
+  __shared__ int tab[RT_MAX];
+  __shared__ double dsum[2 * SEG];
+  __shared__ double wred[RBS / WAVE];
+  const int tid = threadIdx.x;
+  const Seg sg = segs[blockIdx.x];
+  const long long t0 = sg.t0;
+  const int ns = sg.t1 - sg.t0;
+  if (pact && !pact[sg.p]) {  // problem not being worked on: zero residual
+    for (long long i = t0 * NK + tid; i < (long long)sg.t1 * NK; i += RBS) res[i] = 0.0;
+    if (tid == 0) {
+      part[2 * blockIdx.x] = 0.0;
+      part[2 * blockIdx.x + 1] = 0.0;
+      omb[blockIdx.x] = 0.0;
     }
     return;
   }
-  const double dw = dwv[pw], dc = dcv[pw];
-  const double ud = sol[nks + pw];
-  for (int i = lane; i < NC * (NC + 2); i += WAVE) L.src[SRC_CTB + i] = 0.0;
-  if (lane == 0) L.src[SRC_ZERO] = 0.0;
-  if (lane < NK) L.src[SRC_RHS + lane] = 0.0;
-  L.cy[lane] = 0.0;
-  L.ca[lane] = 0.0;
-  double dp = 0.0, da = 0.0, om = 0.0;
-  for (int n = 0; n < N; ++n) {
-    const long long t = t0 + n;
-    const double* R = rec + t * REC;
-    for (int i = lane; i < REC; i += WAVE) L.src[SRC_REC + i] = R[i];
-    if (lane < NJD) L.src[SRC_DOWN1 + lane] = (n < N - 1) ? rec[(t + 1) * REC + REC_DOWN + lane] : 0.0;
-    if (lane < NV) L.src[SRC_DIAGX + lane] = diagx[t * NV + lane] + dw;
-    if (lane == 0) {
-      L.src[SRC_BRD] = R[jd];
-      L.src[SRC_DC] = -dc;
-      L.src[SRC_DHYD] = -(1.0 / (diags[t] + dw) + dc);
-    }
-    // unknowns of the frontal: own (0-42), the stage above at its coupling indices (43-58), d (60)
-    double xv = 0.0;
-    if (lane < NK) xv = sol[t * NK + lane];
-    else if (lane < NK + NC) xv = n < N - 1 ? sol[(t + 1) * NK + coupling_index(lane - NK)] : 0.0;
-    else if (lane == FR_B) xv = ud;
-    L.xf[lane] = xv;
-    __syncthreads();
-    // keep the table loads inside the stage loop (hoisting them would pin ~120 registers)
-    const int* gt = gather;
-    __asm__ volatile("" : "+s"(gt));
-    double v[FR];
-#pragma unroll
-    for (int i = 0; i < FR; ++i) {
-      const int g = gt[i * WAVE + lane];
-      v[i] = L.src[g & 1023] + L.src[(g >> 10) & 1023] + L.src[(g >> 20) & 1023];
-      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-    }
+  const double dw = dwv[sg.p], dc = dcv[sg.p];
+  const long long la = t0 > 0 ? t0 - 1 : 0, lb = sg.t1 + 1 < nst ? sg.t1 + 1 : nst;
+  const int s0 = (int)(la - (t0 - 1));  // LDS slot of stage la (slot s holds stage t0 - 1 + s)
+  for (int i = tid; i < (int)(lb - la) * REC; i += RBS) cf[s0 * REC + i] = rec[la * REC + i];
+  for (int i = tid; i < (int)(lb - la) * NK; i += RBS) sx[s0 * NK + i] = sol[la * NK + i];
+  for (int i = tid; i < rtab_n; i += RBS) tab[i] = rtab[i];
+  for (int i = tid; i < ns * RDG; i += RBS) {
+    const int l = i / RDG, k = i - l * RDG;
+    const long long t = t0 + l;
+    double v = 0.0;
+    if (k < NV) v = diagx[t * NV + k] + dw;
+    else if (k == NV) v = -dc;
+    else if (k == NV + 1) v = -(1.0 / (diags[t] + dw) + dc);
+    cf[(SEG + 2) * REC + i] = v;
+  }
+  if (tid < 2 * SEG) dsum[tid] = 0.0;
+  __syncthreads();
+  const int j = tid / SEG, ls = tid - j * SEG;
+  double om = 0.0;
+  if (j < NK && ls < ns) {
+    const long long t = t0 + ls;
+    const StageInfo si = sinfo[t];
+    const bool has_dn = si.n > 0, has_up = si.n < si.N - 1;
+    const double xd = sol[nks + sg.p];
+    const int row = tab[j];
+    const int s = ls + 1;
+    const int cbase = s * REC - RT_COFF, dbase = (SEG + 2) * REC + ls * RDG - RT_DIAG, xbase = s * NK - RT_XOFF;
+    const int* tl = tab + 2 * NK + 1;
     double y = 0.0, ya = 0.0;
-#pragma unroll
-    for (int i = 0; i < FR; ++i) {
-      if (i == FR_R) continue;  // the right-hand-side row is not part of K
-      const double pr = (i == FR_B && lane == FR_B) ? 0.0 : v[i] * L.xf[i];
+    for (int q = tab[NK + j]; q < tab[NK + j + 1]; ++q) {
+      const int c = tl[2 * q], xc = tl[2 * q + 1];
+      const double cv = cf[c >= RT_DIAG ? dbase + c : cbase + c];
+      const double xv = (xc & RT_XDTERM) ? xd : sx[xbase + (xc & (RT_XDTERM - 1))];
+      // a neighbour that is not in the chain contributes nothing
+      const bool ok = !(((xc & RT_NBDN) && !has_dn) || ((xc & RT_NBUP) && !has_up));
+      const double pr = ok ? cv * xv : 0.0;
       y += pr;
       ya += fabs(pr);
     }
-    // rows of this stage also see the stage below (its coupling lanes, by our local index)
-    if (lane < NK) {
-      y += L.cy[lane];
-      ya += L.ca[lane];
+    const double r = rhs[t * NK + row];
+    const double rr = r - y;
+    res[t * NK + row] = rr;
+    const double den = ya + fabs(r);
+    om = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
+    if (row == NK - 1) {  // this stage's share of the d row: b . sol_hyd
+      const double pr = cf[s * REC + jd] * sx[s * NK + NK - 1];
+      dsum[2 * ls] = pr;
+      dsum[2 * ls + 1] = fabs(pr);
     }
-    __syncthreads();
-    L.cy[lane] = 0.0;
-    L.ca[lane] = 0.0;
-    __syncthreads();
-    if (lane >= NK && lane < NK + NC) {
-      L.cy[coupling_index(lane - NK)] = y;
-      L.ca[coupling_index(lane - NK)] = ya;
-    }
-    if (lane < NK) {
-      const double r = rhs[t * NK + lane];
-      const double rr = r - y;
-      res[t * NK + lane] = rr;
-      const double den = ya + fabs(r);
-      om = fmax(om, den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY));
-    }
-    if (lane == FR_B) {  // b . u_hyd of this stage (the d row)
-      dp += y;
-      da += ya;
-    }
-    __syncthreads();
   }
-  // fixed-order wave maximum of the backward errors
 #pragma unroll
   for (int m = 1; m < WAVE; m <<= 1) om = fmax(om, __shfl_xor(om, m, WAVE));
-  if (lane == FR_B) {
-    part[2 * w] = dp;
-    part[2 * w + 1] = da;
+  if ((tid & (WAVE - 1)) == 0) wred[tid / WAVE] = om;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0, a = 0.0, b = 0.0;
+    for (int i = 0; i < RBS / WAVE; ++i) m = fmax(m, wred[i]);
+    for (int l = 0; l < ns; ++l) {  // fixed order
+      a += dsum[2 * l];
+      b += dsum[2 * l + 1];
+    }
+    omb[blockIdx.x] = m;
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
   }
-  if (lane == 0) omc[w] = om;
 }
 
 // d row of each problem's residual (one block per problem, fixed order over
-// its chains): res_d = rhs_d - sum b u_hyd - kdd u_d; omd[p] = its backward error
-__global__ void k_residual_d(const double* __restrict__ part, const int* __restrict__ pchain,
+// its segments): res_d = rhs_d - sum b u_hyd - kdd u_d; omd[p] = its backward error
+__global__ void k_residual_d(const double* __restrict__ part, const int* __restrict__ pseg,
                              const DevScalars* __restrict__ scv, const double* __restrict__ sol,
                              const double* __restrict__ rhs, long long nkk, const int* __restrict__ pact,
                              double* __restrict__ res, double* __restrict__ omd) {
@@ -890,9 +885,9 @@ __global__ void k_residual_d(const double* __restrict__ part, const int* __restr
     return;
   }
   double a = 0, b = 0;
-  for (int w = pchain[pb] + threadIdx.x; w < pchain[pb + 1]; w += blockDim.x) {
-    a += part[2 * w];
-    b += part[2 * w + 1];
+  for (int g = pseg[pb] + threadIdx.x; g < pseg[pb + 1]; g += blockDim.x) {
+    a += part[2 * g];
+    b += part[2 * g + 1];
   }
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = b;
@@ -916,7 +911,7 @@ __global__ void k_residual_d(const double* __restrict__ part, const int* __restr
   }
 }
 
-// omega_out[0] = max over the chains, omega_out[1] = max over the problems' d rows
+// omega_out[0] = max over the segments, omega_out[1] = max over the problems' d rows
 __global__ void k_residual_max(const double* __restrict__ omc, int W, const double* __restrict__ omd, int P,
                                double* __restrict__ omega_out) {
   __shared__ double s1[256], s2[256];
@@ -1086,15 +1081,16 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
                            const double* rhs, double* res, double* omega_out, hipStream_t st) {
   const long long nks = h.nst * NK;
   const int* pa = h.pact_on ? h.pact : nullptr;
-  double* part = h.kden;            // 2 per chain
-  double* omc = h.kden + 2LL * h.S;  // 1 per chain
-  double* omd = omc + h.S;          // 1 per problem
+  const int nb = h.nseg;
+  double* part = h.kden;            // 2 per segment
+  double* omb = h.kden + 2LL * nb;  // 1 per segment
+  double* omd = omb + nb;           // 1 per problem
   prof_begin(h, st);
-  hipLaunchKernelGGL(k_residual, dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, diagx, diags, h.dwv, h.dcv, sol, rhs,
-                     h.chain0, h.chain_p, pa, h.S, nks, h.jac_d_index, res, part, omc);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RBS), 0, st, h.rec, h.rtab, h.rtab_n, diagx, diags, h.dwv, h.dcv, sol,
+                     rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, res, part, omb);
   prof_end(h, 3, st);
-  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pchain, h.scal, sol, rhs, nks, pa, res, omd);
-  hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(256), 0, st, omc, h.S, omd, h.P, omega_out);
+  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pseg, h.scal, sol, rhs, nks, pa, res, omd);
+  hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(256), 0, st, omb, nb, omd, h.P, omega_out);
   return hipGetLastError();
 }
 
