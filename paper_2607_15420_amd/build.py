@@ -20,6 +20,8 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed FP32 instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fully unroll the pivot loops marked for it (static register indices) even in large kernels
+    "-mllvm", "-pragma-unroll-threshold=500000",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -494,6 +494,80 @@ __device__ __forceinline__ void backward_stage(const double* __restrict__ sb, do
   }
 }
 
+// Sum over the wave of a double, fixed order (DPP row shifts and row
+// broadcasts on the two halves; lane 63 ends with the total), returned to
+// every lane.
+#define ABS_DPP_ADD_F64(v, ctrl, rm)                                                     \
+  do {                                                                                  \
+    const int lo_ = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, rm, 0xf, false); \
+    const int hi_ = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, rm, 0xf, false); \
+    (v) += __hiloint2double(hi_, lo_);                                                  \
+  } while (0)
+
+__device__ __forceinline__ double wave_total(double v) {
+  ABS_DPP_ADD_F64(v, 0x111, 0xf);  // row_shr:1
+  ABS_DPP_ADD_F64(v, 0x112, 0xf);  // row_shr:2
+  ABS_DPP_ADD_F64(v, 0x114, 0xf);  // row_shr:4
+  ABS_DPP_ADD_F64(v, 0x118, 0xf);  // row_shr:8
+  ABS_DPP_ADD_F64(v, 0x142, 0xa);  // row_bcast:15
+  ABS_DPP_ADD_F64(v, 0x143, 0xc);  // row_bcast:31
+  return rdl(v, 63);
+}
+
+// Backward sweep of one stage for R right-hand sides with rows on lanes:
+// lane i loads row i of every stored pivot column (coalesced), and pivot s
+// (descending) takes x = dinv_s (y_s - sum_i F_s[i] x_i) with one wave sum per
+// right-hand side.  Rows eliminated before s are zero in column s and rows not
+// yet solved hold x = 0, so the sums run over all lanes.  ys[r]: lane s holds
+// the forward value of slot s; xc[r]: solution of the stage above by
+// stage-local index (read at the 16 coupling indices).  On return lane i < 43
+// holds the solution of row i in xl[r].
+template <int R>
+__device__ __forceinline__ void backward_rows(const double* __restrict__ sb, const double (&ys)[R],
+                                              const double* const (&xc)[R], double (&xl)[R]) {
+  const int lane = lane_id();
+  double col[NK];
+#pragma unroll
+  for (int q = 0; q < NK; ++q) col[q] = sb[q * SLOT + lane];
+  const bool cpl = lane >= NK && lane < NK + NC;
+  const int ci = coupling_index(cpl ? lane - NK : 0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) xl[r] = cpl ? xc[r][ci] : 0.0;
+  bool skip = false;
+#pragma unroll
+  for (int s = NK - 1; s >= 0; --s) {
+    if (skip) {
+      skip = false;
+      continue;
+    }
+    const int code = (int)rdl(col[s], FR);
+    const int type = code >> 6, p = code & 63;
+    if (s > 0 && type == 3) {  // second slot of a 2x2 pivot: solve the pair (s-1, s)
+      const int s0 = s > 0 ? s - 1 : 0;
+      const int pa = ((int)rdl(col[s0], FR)) & 63;
+      const double e11 = rdl(col[s0], FR + 1), e12 = rdl(col[s0], FR + 2), e22 = rdl(col[s], FR + 1);
+      const double idet = 1.0 / (e11 * e22 - e12 * e12);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double za = rdl(ys[r], s0) - wave_total(col[s0] * xl[r]);
+        const double zb = rdl(ys[r], s) - wave_total(col[s] * xl[r]);
+        const double xa = (e22 * za - e12 * zb) * idet, xb = (e11 * zb - e12 * za) * idet;
+        if (lane == pa) xl[r] = xa;
+        if (lane == p) xl[r] = xb;
+      }
+      skip = true;
+    } else {
+      const double dinv = rdl(col[s], FR + 2);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double dot = wave_total(col[s] * xl[r]);
+        const double x = type ? (rdl(ys[r], s) - dot) * dinv : 0.0;
+        if (lane == p) xl[r] = x;
+      }
+    }
+  }
+}
+
 template <int WITH_RHS, int WPE>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_factor(
     const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
@@ -661,14 +735,14 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
   for (int n = N - 1; n >= 0; --n) {
     const long long t = t0 + n;
     const double* sb = slots + t * NK * SLOT;
-    const double y = lane < NK ? solr[t * NK + lane] : 0.0;
-    double x_s, unused;
-    int p_s;
-    backward_stage(sb, y, 0.0, sh, sh, false, x_s, unused, p_s);
+    const double y[1] = {lane < NK ? solr[t * NK + lane] : 0.0};
+    const double* const xc[1] = {sh};
+    double x[1];
+    backward_rows<1>(sb, y, xc, x);
     __syncthreads();
     if (lane < NK) {
-      solr[t * NK + p_s] = x_s;
-      sh[p_s] = x_s;
+      solr[t * NK + lane] = x[0];
+      sh[lane] = x[0];
     }
     __syncthreads();
     if (lane == NK - 1) sig += rec[t * REC + jd] * sh[NK - 1];
