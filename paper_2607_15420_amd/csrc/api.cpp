@@ -224,11 +224,12 @@ static void free_handle(Handle& h) {
   void* ptrs[] = {h.feeds, h.gather, h.rtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
-                  h.seg, h.pseg, h.dwv, h.dcv, h.fmask, h.pact};
+                  h.seg, h.pseg, h.ctl};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);
   if (h.redbuf_h) (void)hipHostFree(h.redbuf_h);
+  if (h.ctl_h) (void)hipHostFree(h.ctl_h);
 }
 
 // (re)allocate the scaled row-scale vector as ones
@@ -390,23 +391,27 @@ int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const 
   ALLOC(h.pstage, h.P + 1);
   ALLOC(h.seg, h.nseg);
   ALLOC(h.pseg, h.P + 1);
-  ALLOC(h.dwv, h.P);
-  ALLOC(h.dcv, h.P);
-  ALLOC(h.fmask, h.P);
-  ALLOC(h.pact, h.P);
+  h.ctl_bytes = ctl_size(h.P);
+  ALLOC(h.ctl, h.ctl_bytes);
+  h.dwv = reinterpret_cast<double*>(h.ctl);
+  h.dcv = h.dwv + h.P;
+  h.fmask = reinterpret_cast<int*>(h.ctl + ctl_off_fmask(h.P));
+  h.pact = reinterpret_cast<int*>(h.ctl + ctl_off_pact(h.P));
+  h.slot_area = h.ctl + ctl_off_slot(h.P);
   ALLOC(h.omega_d, 8);
   ALLOC(h.diagx, h.nx);
   ALLOC(h.diags, nst);
   ALLOC(h.kres, h.nkkt);
   ALLOC(h.kcor, h.nkkt);
-  ALLOC(h.kden, 3 * nst + h.P + 64);
+  ALLOC(h.kden, 3 * nst + 5LL * h.nseg + 4LL * h.P + 64);  // per-stage scratch; residual partials
   h.red_cap = (int)std::max<long long>(
       64 * 1024, std::max<long long>(9 * ((std::max<long long>(h.nx, std::max(h.nc, h.nkkt)) + 255) / 256),
                                      9LL * (h.nseg + h.P)) + 64);
   ALLOC(h.redbuf, h.red_cap);
 #undef ALLOC
   if (hipHostMalloc((void**)&h.scal_h, sizeof(DevScalars) * h.P, 0) != hipSuccess ||
-      hipHostMalloc((void**)&h.redbuf_h, sizeof(double) * h.red_cap, 0) != hipSuccess) {
+      hipHostMalloc((void**)&h.redbuf_h, sizeof(double) * h.red_cap, 0) != hipSuccess ||
+      hipHostMalloc((void**)&h.ctl_h, h.ctl_bytes, 0) != hipSuccess) {
     set_error("absorber_create: pinned host allocation failed");
     return fail(ABS_ERR_OOM);
   }

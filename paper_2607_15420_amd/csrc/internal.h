@@ -55,6 +55,12 @@ __host__ __device__ constexpr int coupling_index(int a) {
 
 struct JacEntry { int8_t row, blk, col; };
 
+constexpr int CTL_SLOT = 64;  // bytes of solver scalars per problem in the control block
+inline size_t ctl_off_fmask(int P) { return 16 * (size_t)P; }
+inline size_t ctl_off_pact(int P) { return 20 * (size_t)P; }
+inline size_t ctl_off_slot(int P) { return ((24 * (size_t)P + 63) / 64) * 64; }
+inline size_t ctl_size(int P) { return ctl_off_slot(P) + (size_t)CTL_SLOT * P; }
+
 // A handle holds P independent problems (P = 1 for absorber_create).  Their
 // scenarios ("chains" of stages) are stored problem after problem, each chain's
 // stages contiguous and bottom to top; the primal vector is [21 entries per
@@ -108,10 +114,17 @@ struct Handle {
   Seg* seg = nullptr;                        // device [nseg]
   int* pseg = nullptr;                       // device [P+1]
   int nseg = 0;
+  // per-problem control arrays, one device block (ctl) with a pinned host copy
+  // (ctl_h) of the same layout, so that they travel in one transfer:
+  // [dwv P doubles][dcv P doubles][fmask P ints][pact P ints][CTL_SLOT bytes per problem]
+  char* ctl = nullptr;
+  char* ctl_h = nullptr;
+  size_t ctl_bytes = 0;
   double* dwv = nullptr;                     // device [P] delta_w of the stored factorisation
   double* dcv = nullptr;                     // device [P] delta_c
   int* fmask = nullptr;                      // device [P] problems to (re)factorise (null: all)
   int* pact = nullptr;                       // device [P] problems the per-stage kernels work on
+  char* slot_area = nullptr;                 // device [P][CTL_SLOT] the solver's per-problem scalars
   bool pact_on = false;                      // false: every problem
   ModelParams mp{};
   double xL[NV], xU[NV], dL = 0, dU = 0;     // unscaled bounds per local variable
@@ -141,7 +154,7 @@ struct Handle {
   double* kres = nullptr;                    // [nkkt] refinement residual
   double* kcor = nullptr;                    // [nkkt] refinement correction
   double* kden = nullptr;                    // residual partials: 2 per stage, block maxima, per-problem d rows
-  double* omega_d = nullptr;                 // [2] backward errors of the last residual
+  double* omega_d = nullptr;                 // [4] of the last residual: backward errors (rows, d rows), max |res|, max |rhs|
   Tune tune;
   double* redbuf = nullptr;                  // device reduction partials
   double* redbuf_h = nullptr;                // pinned host mirror

@@ -303,15 +303,17 @@ __global__ void k_direction(const Seg* __restrict__ seg, const PS* __restrict__ 
   const SegView V(seg);
   const PS q = ps[V.p];
   const double mu = q.mu, tau = q.tau, dw = dwv[V.p];
-  Part<3> p;
+  Part<4> p;
   p.v[0] = 1.0;
   p.v[1] = 1.0;
   p.v[2] = 0.0;
+  p.v[3] = 0.0;
   const long long i = V.xi(nxs);
   if (i >= 0) {
     const int k = lidx(i, nxs);
     const double d = sol[kkt_of_primal(i, nxs, nks)];
     dx[i] = d;
+    if (i >= nxs) p.v[3] = d;  // the problem's diameter step (its owner thread only)
     const double xi = x[i];
     double a = 0.0, bz = 0.0;
     if (isfinite(b.lo[k])) {
@@ -346,7 +348,7 @@ __global__ void k_direction(const Seg* __restrict__ seg, const PS* __restrict__ 
     if (dv < 0.0) p.v[1] = fmin(p.v[1], -tau * vU[t] / dv);
     p.v[2] += (mu / si - kd * mu) * d;
   }
-  block_reduce<3>(p, Ops<3>{{2, 2, 0}}, out);
+  block_reduce<4>(p, Ops<4>{{2, 2, 0, 0}}, out);
 }
 
 // trial point of the problems in the line search
@@ -512,14 +514,6 @@ __global__ void k_fill(double* __restrict__ p, double v, long long n) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_absmax_parts(const double* __restrict__ v, long long n, double* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  Part<1> p;
-  p.v[0] = i < n ? fabs(v[i]) : 0.0;
-  if (i < n && !isfinite(v[i])) p.v[0] = INFINITY;
-  block_reduce<1>(p, Ops<1>{{1}}, out);
-}
-
 // final iterate of the problems flagged "write": x = D * xt and y = y~ * cs
 __global__ void k_output(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ xt,
                          const double* __restrict__ y, const double* __restrict__ cs, Scaling sc, long long nxs,
@@ -563,8 +557,8 @@ struct Work {
          *vU = nullptr, *c = nullptr, *ct = nullptr, *g = nullptr, *dpart = nullptr, *rhs = nullptr, *sol = nullptr,
          *dx = nullptr, *dy = nullptr, *dzL = nullptr, *dzU = nullptr, *ds = nullptr, *dvU = nullptr,
          *rowmax = nullptr;
-  PS* ps = nullptr;        // device [P]
-  PS* ps_h = nullptr;      // pinned [P]
+  PS* ps = nullptr;        // device [P] (in the handle's control block)
+  PS* ps_h = nullptr;      // pinned [P] (its host copy)
   double* dw_h = nullptr;  // pinned [P]
   double* dc_h = nullptr;  // pinned [P]
   int* fm_h = nullptr;     // pinned [P]
@@ -620,21 +614,6 @@ struct Prob {
 
 }  // namespace
 
-// host-side reduction of per-block partials (global)
-static int reduce_parts(Handle& h, int nblocks, int K, const int* ops, double* outv, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(h.redbuf_h, h.redbuf, sizeof(double) * nblocks * K, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  for (int k = 0; k < K; ++k) {
-    double a = ops[k] == 0 ? 0.0 : (ops[k] == 1 ? -INFINITY : INFINITY);
-    for (int b = 0; b < nblocks; ++b) {
-      const double v = h.redbuf_h[b * K + k];
-      a = ops[k] == 0 ? a + v : (ops[k] == 1 ? fmax(a, v) : fmin(a, v));
-    }
-    outv[k] = a;
-  }
-  return ABS_OK;
-}
-
 // per-problem results of the segment partials in h.redbuf -> h.redbuf_h[p * K + k]
 template <int K>
 static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
@@ -646,15 +625,19 @@ static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
   return ABS_OK;
 }
 
-static int absmax(Handle& h, const double* v, long long n, double* out, hipStream_t st) {
-  const int nb = (int)grid_for(n, BS);
-  if (nb > h.red_cap) {
-    set_error("reduction buffer too small");
-    return ABS_ERR_ARG;
-  }
-  hipLaunchKernelGGL(k_absmax_parts, dim3(nb), dim3(BS), 0, st, v, n, h.redbuf);
-  const int ops[1] = {1};
-  return reduce_parts(h, nb, 1, ops, out, st);
+// two sets of segment partials reduced at once: K1 per segment at h.redbuf,
+// K2 per segment after them; results -> h.redbuf_h[p * K1 + k], then
+// h.redbuf_h[K1 * P + p * K2 + k]
+template <int K1, int K2>
+static int seg_reduce2(Handle& h, const Ops<K1>& ops1, const Ops<K2>& ops2, hipStream_t st) {
+  double* out = h.redbuf + (long long)h.nseg * (K1 + K2);
+  hipLaunchKernelGGL(k_seg_reduce<K1>, dim3(h.P), dim3(BS), 0, st, h.redbuf, h.pseg, ops1, out);
+  hipLaunchKernelGGL(k_seg_reduce<K2>, dim3(h.P), dim3(BS), 0, st, h.redbuf + (long long)h.nseg * K1, h.pseg, ops2,
+                     out + (long long)h.P * K1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * h.P * (K1 + K2), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return ABS_OK;
 }
 
 int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st) {
@@ -662,20 +645,15 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     HIP_TRY(launch_solve(h, rhs, st));
     HIP_TRY(launch_schur(h, h.diagx, rhs, 2, sol, st));
   }
-  double rn = 0.0;
-  int rc = absmax(h, rhs, h.nkkt, &rn, st);
-  if (rc) return rc;
   double best_om = INFINITY, best_rel = INFINITY;
   bool have_best = false;
-  double* om = h.redbuf_h + h.red_cap - 2;  // two pinned doubles past the partials
+  double* om = h.redbuf_h + h.red_cap - 4;  // four pinned doubles past the partials
   for (int it = 0; it <= 10; ++it) {
     HIP_TRY(launch_residual(h, h.diagx, h.diags, sol, rhs, h.kres, h.omega_d, st));
-    HIP_TRY(hipMemcpyAsync(om, h.omega_d, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    double resn = 0.0;
-    rc = absmax(h, h.kres, h.nkkt, &resn, st);  // synchronises the stream
-    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     const double omega = fmax(om[0], om[1]);
-    const double relr = rn > 0.0 ? resn / rn : resn;
+    const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];  // ||res||_inf / ||rhs||_inf
     if (!(omega < best_om)) {  // no further improvement: restore the best iterate
       if (have_best) HIP_TRY(hipMemcpyAsync(sol, h.kcor, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
       break;
@@ -689,7 +667,6 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st));  // correction in place
     HIP_TRY(launch_axpy(sol, h.kres, 1.0, h.nkkt, st));
   }
-  HIP_TRY(hipStreamSynchronize(st));
   if (rel) *rel = best_rel;
   return ABS_OK;
 }
@@ -703,7 +680,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   const long long nx = h.nx, nc = h.nc, nst = h.nst, nkkt = h.nkkt;
   const long long nxs = nst * NV, nks = nst * NK;
   const int nseg = h.nseg;
-  if (9LL * (nseg + P) > h.red_cap - 2) {
+  if (9LL * (nseg + P) > h.red_cap - 4) {
     set_error("ipm_solve: problem too large for the reduction buffer");
     return ABS_ERR_ARG;
   }
@@ -716,16 +693,19 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   for (double** p : bufs_ns) HIP_TRY(W.alloc(p, nst));
   HIP_TRY(W.alloc(&W.rhs, nkkt));
   HIP_TRY(W.alloc(&W.sol, nkkt));
-  HIP_TRY(W.alloc(&W.ps, P));
-  HIP_TRY(W.host(&W.ps_h, P));
-  HIP_TRY(W.host(&W.dw_h, P));
-  HIP_TRY(W.host(&W.dc_h, P));
-  HIP_TRY(W.host(&W.fm_h, P));
+  // per-problem scalars live in the handle's control block (one transfer for all of them)
+  static_assert(sizeof(PS) <= CTL_SLOT, "solver scalars exceed the control block slot");
+  W.ps = reinterpret_cast<PS*>(h.slot_area);
+  W.ps_h = reinterpret_cast<PS*>(h.ctl_h + ctl_off_slot(P));
+  W.dw_h = reinterpret_cast<double*>(h.ctl_h);
+  W.dc_h = W.dw_h + P;
+  W.fm_h = reinterpret_cast<int*>(h.ctl_h + ctl_off_fmask(P));
+  int* pa_h = reinterpret_cast<int*>(h.ctl_h + ctl_off_pact(P));
   HIP_TRY(W.host(&W.dd_h, P));
-  int* pa_h = nullptr;
-  HIP_TRY(W.host(&pa_h, P));
   std::vector<Prob> pr((size_t)P);
-  auto upload_ps = [&]() -> int {
+  // scalars, activity, regularisation and the refactorisation mask of every
+  // problem -> device, in one transfer
+  auto upload = [&]() -> int {
     for (int p = 0; p < P; ++p) {
       const Prob& q = pr[(size_t)p];
       PS& d = W.ps_h[p];
@@ -739,9 +719,11 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       d.zero_y = 0;
       d.write = !active0 || active0[p];
       pa_h[p] = q.active;
+      W.dw_h[p] = q.dw;
+      W.dc_h[p] = q.dc;
+      W.fm_h[p] = q.need ? 1 : 0;
     }
-    HIP_TRY(hipMemcpyAsync(W.ps, W.ps_h, sizeof(PS) * P, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(h.pact, pa_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h.ctl, h.ctl_h, h.ctl_bytes, hipMemcpyHostToDevice, st));
     return ABS_OK;
   };
   // the per-stage kernels skip problems that are done (or not asked for)
@@ -749,17 +731,6 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     Handle& h;
     ~PactGuard() { h.pact_on = false; }
   } pact_guard{h};
-  auto upload_reg = [&](bool mask) -> int {
-    for (int p = 0; p < P; ++p) {
-      W.dw_h[p] = pr[(size_t)p].dw;
-      W.dc_h[p] = pr[(size_t)p].dc;
-      W.fm_h[p] = mask ? (pr[(size_t)p].need ? 1 : 0) : 1;
-    }
-    HIP_TRY(hipMemcpyAsync(h.dwv, W.dw_h, sizeof(double) * P, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(h.dcv, W.dc_h, sizeof(double) * P, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(h.fmask, W.fm_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
-    return ABS_OK;
-  };
   auto read_d = [&](const double* v) -> int {  // d entries of a primal vector -> W.dd_h
     HIP_TRY(hipMemcpyAsync(W.dd_h, v + nxs, sizeof(double) * P, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -810,7 +781,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   hipLaunchKernelGGL(k_fill, dim3(gc), dim3(BS), 0, st, W.y, 0.0, nc);
   double rel = 0.0, max_rel = 0.0;
   int nfact = 0;
-  TRY(upload_ps());
+  TRY(upload());
   if (warm && y0_dev) {
     // multipliers of the unscaled rows -> multipliers of the scaled rows
     hipLaunchKernelGGL(k_mul, dim3(gc), dim3(BS), 0, st, y0_dev, h.cs, nc, 1, W.y);
@@ -826,7 +797,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       q.dw = 1.0;
       q.dc = 0.0;
     }
-    TRY(upload_reg(false));
+    TRY(upload());
     HIP_TRY(launch_factor(h, h.diagx, h.diags, W.rhs, false, st));
     ++nfact;
     HIP_TRY(launch_schur(h, h.diagx, W.rhs, 1, W.sol, st));
@@ -875,7 +846,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       n_active += active0[p] != 0;
     }
   }
-  TRY(upload_ps());
+  TRY(upload());
   h.pact_on = true;
   auto now = [] { return std::chrono::steady_clock::now(); };
   auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
@@ -891,6 +862,9 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pstage, gf, nxs, W.g);
     hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s, W.vU,
                        b, nxs, h.redbuf);
+    // the barrier Hessian diagonals at x_k need no decision of the host: queue them now
+    hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nxs, nst, h.diagx,
+                       h.diags);
     TRY(seg_reduce<9>(h, Ops<9>{{1, 1, 1, 1, 2, 1, 0, 0, 0}}, st));
     for (int p = 0; p < P; ++p) {
       Prob& q = pr[(size_t)p];
@@ -929,17 +903,15 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     }
     if (n_active == 0) break;
     const auto ph1 = now();
-    TRY(upload_ps());
     // ---- search direction with inertia correction (each problem its own delta_w)
-    hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nxs, nst, h.diagx,
-                       h.diags);
     for (auto& q : pr) {
       q.dw = 0.0;
       q.dc = 0.0;
       q.need = q.active;
     }
-    while (true) {
-      TRY(upload_reg(true));
+    TRY(upload());
+    for (bool first = true;; first = false) {
+      if (!first) TRY(upload());
       hipLaunchKernelGGL(k_rhs, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.g, W.y, W.c, W.s, h.diags,
                          b, C.kappa_d, gf, nxs, nks, W.rhs);
       if (o.autotune && !h.tune.done) TRY(autotune(h, W.xt, W.y, W.c, h.diagx, h.diags, W.rhs, st));
@@ -976,31 +948,29 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     }
     if (n_active == 0) break;
     const auto ph2 = now();
-    TRY(upload_ps());
+    TRY(upload());
     TRY(kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st));
     max_rel = std::max(max_rel, rel);
     const auto ph3 = now();
     // ---- step pieces and fraction to the boundary
+    // and, reduced together, theta and the barrier function at the current point
     hipLaunchKernelGGL(k_direction, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.zL, W.zU, W.y, W.s,
                        W.vU, h.diags, W.sol, b, C.kappa_d, gf, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
                        h.redbuf);
-    TRY(seg_reduce<3>(h, Ops<3>{{2, 2, 0}}, st));
-    for (int p = 0; p < P; ++p) {
-      Prob& q = pr[(size_t)p];
-      q.alpha_max = h.redbuf_h[p * 3 + 0];
-      q.alpha_z = h.redbuf_h[p * 3 + 1];
-      q.gdx = h.redbuf_h[p * 3 + 2];
-    }
-    TRY(read_d(W.dx));
     hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
-                       h.redbuf);
-    TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
+                       h.redbuf + 4LL * nseg);
+    TRY((seg_reduce2<4, 3>(h, Ops<4>{{2, 2, 0, 0}}, Ops<3>{{0, 0, 0}}, st)));
     for (int p = 0; p < P; ++p) {
       Prob& q = pr[(size_t)p];
-      q.dxd = W.dd_h[p];
+      const double* dv = h.redbuf_h + p * 4;
+      const double* lv = h.redbuf_h + 4 * P + p * 3;
+      q.alpha_max = dv[0];
+      q.alpha_z = dv[1];
+      q.gdx = dv[2];
+      q.dxd = dv[3];
       if (!q.active) continue;
-      q.th = h.redbuf_h[p * 3 + 0];
-      q.phi = h.sf * h.sc.Dd * q.xd + h.redbuf_h[p * 3 + 1];
+      q.th = lv[0];
+      q.phi = h.sf * h.sc.Dd * q.xd + lv[1];
       const double th = q.th, gdx = q.gdx;
       if (gdx < 0 && th <= q.theta_min)
         q.amin = C.gamma_alpha * std::min({C.gamma_theta, C.gamma_phi * th / (-gdx),
@@ -1018,7 +988,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     const auto ph4 = now();
     while (true) {
       ++n_ls_it;
-      TRY(upload_ps());
+      TRY(upload());
       hipLaunchKernelGGL(k_trial, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.dx, W.s, W.ds, nxs, W.xtt, W.st);
       HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
       hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d, nxs,
@@ -1075,7 +1045,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       q.xd = q.xd + q.alpha * q.dxd;
       ++q.it;
     }
-    TRY(upload_ps());
+    TRY(upload());
     hipLaunchKernelGGL(k_accept, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.xtt, W.s, W.st, W.y, W.dy, W.zL,
                        W.dzL, W.zU, W.dzU, W.vU, W.dvU, b, C.kappa_sigma, nxs);
     ++iter;
@@ -1102,7 +1072,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   }
   HIP_TRY(hipStreamSynchronize(st));
   if (xout || yout) {
-    TRY(upload_ps());
+    TRY(upload());
     hipLaunchKernelGGL(k_output, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.y, h.cs, h.sc, nxs, xout, yout);
   }
 #undef TRY
@@ -1279,6 +1249,7 @@ int absorber_kkt_solve(absorber_t* H, const double* rhs_dev, double* sol_dev, do
   double rel = 0.0;
   const int rc = kkt_solve_refined(h, rhs_dev, sol_dev, false, &rel, (hipStream_t)stream);
   if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   if (rel_resid_host) *rel_resid_host = rel;
   return ABS_OK;
 }

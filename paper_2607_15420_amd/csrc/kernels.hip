@@ -847,8 +847,9 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
 // (K_ij from a record or the diagonal, times an unknown of its stage, of a
 // neighbour or d).  Threads are assigned rows in decreasing term count, so
 // that the lanes of a wave walk lists of similar length.
-// part[2 s] = sum over the segment of b_t . sol_hyd(t) and part[2 s + 1] its
-// magnitude (for the d row); omb[s] = the segment's largest backward error.
+// part[2 g] = sum over segment g of b_t . sol_hyd(t) and part[2 g + 1] its
+// magnitude (for the d row); omb[3 g .. 3 g + 2] = the segment's largest
+// backward error, largest |res_i| and largest |rhs_i|.
 constexpr int RBS = ((NK * SEG + WAVE - 1) / WAVE) * WAVE;  // threads per block
 constexpr int RDG = 24;                                      // diagonal coefficients per stage in LDS
 
@@ -862,7 +863,7 @@ __global__ __launch_bounds__(RBS) void k_residual(
   __shared__ double sx[(SEG + 2) * NK];               // unknowns of the same stages
   __shared__ int tab[RT_MAX];
   __shared__ double dsum[2 * SEG];
-  __shared__ double wred[RBS / WAVE];
+  __shared__ double wred[3][RBS / WAVE];
   const int tid = threadIdx.x;
   const Seg sg = segs[blockIdx.x];
   const long long t0 = sg.t0;
@@ -872,7 +873,9 @@ __global__ __launch_bounds__(RBS) void k_residual(
     if (tid == 0) {
       part[2 * blockIdx.x] = 0.0;
       part[2 * blockIdx.x + 1] = 0.0;
-      omb[blockIdx.x] = 0.0;
+      omb[3 * blockIdx.x] = 0.0;
+      omb[3 * blockIdx.x + 1] = 0.0;
+      omb[3 * blockIdx.x + 2] = 0.0;
     }
     return;
   }
@@ -894,7 +897,7 @@ __global__ __launch_bounds__(RBS) void k_residual(
   if (tid < 2 * SEG) dsum[tid] = 0.0;
   __syncthreads();
   const int j = tid / SEG, ls = tid - j * SEG;
-  double om = 0.0;
+  double om = 0.0, rmax = 0.0, bmax = 0.0;
   if (j < NK && ls < ns) {
     const long long t = t0 + ls;
     const StageInfo si = sinfo[t];
@@ -920,6 +923,10 @@ __global__ __launch_bounds__(RBS) void k_residual(
     res[t * NK + row] = rr;
     const double den = ya + fabs(r);
     om = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
+    rmax = fabs(rr);
+    bmax = fabs(r);
+    if (!isfinite(rr)) om = rmax = INFINITY;  // maxima below ignore NaN: report it as infinite
+    if (!isfinite(r)) bmax = INFINITY;
     if (row == NK - 1) {  // this stage's share of the d row: b . sol_hyd
       const double pr = cf[s * REC + jd] * sx[s * NK + NK - 1];
       dsum[2 * ls] = pr;
@@ -927,17 +934,28 @@ __global__ __launch_bounds__(RBS) void k_residual(
     }
   }
 #pragma unroll
-  for (int m = 1; m < WAVE; m <<= 1) om = fmax(om, __shfl_xor(om, m, WAVE));
-  if ((tid & (WAVE - 1)) == 0) wred[tid / WAVE] = om;
+  for (int m = 1; m < WAVE; m <<= 1) {
+    om = fmax(om, __shfl_xor(om, m, WAVE));
+    rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
+    bmax = fmax(bmax, __shfl_xor(bmax, m, WAVE));
+  }
+  if ((tid & (WAVE - 1)) == 0) {
+    wred[0][tid / WAVE] = om;
+    wred[1][tid / WAVE] = rmax;
+    wred[2][tid / WAVE] = bmax;
+  }
   __syncthreads();
+  if (tid < 3) {
+    double m = 0.0;
+    for (int i = 0; i < RBS / WAVE; ++i) m = fmax(m, wred[tid][i]);
+    omb[3 * blockIdx.x + tid] = m;
+  }
   if (tid == 0) {
-    double m = 0.0, a = 0.0, b = 0.0;
-    for (int i = 0; i < RBS / WAVE; ++i) m = fmax(m, wred[i]);
+    double a = 0.0, b = 0.0;
     for (int l = 0; l < ns; ++l) {  // fixed order
       a += dsum[2 * l];
       b += dsum[2 * l + 1];
     }
-    omb[blockIdx.x] = m;
     part[2 * blockIdx.x] = a;
     part[2 * blockIdx.x + 1] = b;
   }
@@ -954,7 +972,7 @@ __global__ void k_residual_d(const double* __restrict__ part, const int* __restr
   if (pact && !pact[pb]) {
     if (threadIdx.x == 0) {
       res[nkk + pb] = 0.0;
-      omd[pb] = 0.0;
+      omd[3 * pb] = omd[3 * pb + 1] = omd[3 * pb + 2] = 0.0;
     }
     return;
   }
@@ -981,31 +999,40 @@ __global__ void k_residual_d(const double* __restrict__ part, const int* __restr
     const double rr = rhs[i] - ku;
     res[i] = rr;
     const double den = ka + fabs(rhs[i]);
-    omd[pb] = den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY);
+    const bool fin = isfinite(rr);
+    omd[3 * pb] = !fin ? INFINITY : (den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY));
+    omd[3 * pb + 1] = fin ? fabs(rr) : INFINITY;
+    omd[3 * pb + 2] = isfinite(rhs[i]) ? fabs(rhs[i]) : INFINITY;
   }
 }
 
-// omega_out[0] = max over the segments, omega_out[1] = max over the problems' d rows
-__global__ void k_residual_max(const double* __restrict__ omc, int W, const double* __restrict__ omd, int P,
-                               double* __restrict__ omega_out) {
-  __shared__ double s1[256], s2[256];
-  double a = 0, b = 0;
-  for (int i = threadIdx.x; i < W; i += blockDim.x) a = fmax(a, omc[i]);
-  for (int i = threadIdx.x; i < P; i += blockDim.x) b = fmax(b, omd[i]);
-  s1[threadIdx.x] = a;
-  s2[threadIdx.x] = b;
+// out[0] = largest backward error over the segments, out[1] over the problems'
+// d rows, out[2] = largest |res_i| and out[3] = largest |rhs_i| over both
+__global__ void k_residual_max(const double* __restrict__ omb, int G, const double* __restrict__ omd, int P,
+                               double* __restrict__ out) {
+  __shared__ double sm[4][256];
+  double a = 0, b = 0, r = 0, q = 0;
+  for (int i = threadIdx.x; i < G; i += blockDim.x) {
+    a = fmax(a, omb[3 * i]);
+    r = fmax(r, omb[3 * i + 1]);
+    q = fmax(q, omb[3 * i + 2]);
+  }
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    b = fmax(b, omd[3 * i]);
+    r = fmax(r, omd[3 * i + 1]);
+    q = fmax(q, omd[3 * i + 2]);
+  }
+  sm[0][threadIdx.x] = a;
+  sm[1][threadIdx.x] = b;
+  sm[2][threadIdx.x] = r;
+  sm[3][threadIdx.x] = q;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + s]);
-      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + s]);
-    }
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 4; ++k) sm[k][threadIdx.x] = fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    omega_out[0] = s1[0];
-    omega_out[1] = s2[0];
-  }
+  if (threadIdx.x < 4) out[threadIdx.x] = sm[threadIdx.x][0];
 }
 
 inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -1157,8 +1184,8 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   const int* pa = h.pact_on ? h.pact : nullptr;
   const int nb = h.nseg;
   double* part = h.kden;            // 2 per segment
-  double* omb = h.kden + 2LL * nb;  // 1 per segment
-  double* omd = omb + nb;           // 1 per problem
+  double* omb = h.kden + 2LL * nb;  // 3 per segment
+  double* omd = omb + 3LL * nb;     // 3 per problem
   prof_begin(h, st);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RBS), 0, st, h.rec, h.rtab, h.rtab_n, diagx, diags, h.dwv, h.dcv, sol,
                      rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, res, part, omb);
