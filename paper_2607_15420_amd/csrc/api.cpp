@@ -189,6 +189,33 @@ static int build_tables(Handle& h) {
   HIP_TRY(dalloc(&h.rtab, rt.size()));
   HIP_TRY(hipMemcpy(h.rtab, rt.data(), rt.size() * sizeof(int), hipMemcpyHostToDevice));
   h.rtab_n = (int)rt.size();
+  // Lagrangian gradient terms J^T y for the NV variables of a stage: the terms
+  // of the residual rows 0..NV-1 whose unknown is a multiplier, with the
+  // unknown re-indexed into the row vector (row r of this stage or a neighbour)
+  std::vector<int> gt(NV + 1, 0);
+  std::vector<int> gterms;
+  for (int k = 0; k < NV; ++k) {
+    for (auto& pr : terms[(size_t)k]) {
+      const int xc = pr.second;
+      if (xc & RT_XDTERM) continue;
+      const int nb = xc & (RT_NBDN | RT_NBUP);
+      const int off = (xc & (RT_XDTERM - 1)) - RT_XOFF;                    // offset in KKT unknowns
+      const int local = off - (nb == RT_NBDN ? -NK : (nb == RT_NBUP ? NK : 0));  // index in the stage
+      if (local < NV) continue;                                          // Hessian or diagonal term
+      const int yoff = (local - NV) + (nb == RT_NBDN ? -NR : (nb == RT_NBUP ? NR : 0));
+      gterms.push_back(pr.first);
+      gterms.push_back((yoff + RT_XOFF) | nb);
+    }
+    gt[(size_t)k + 1] = (int)gterms.size() / 2;
+  }
+  gt.insert(gt.end(), gterms.begin(), gterms.end());
+  if ((int)gt.size() > RT_MAX) {
+    set_error("internal: gradient term table too large");
+    return ABS_ERR_ARG;
+  }
+  HIP_TRY(dalloc(&h.gtab, gt.size()));
+  HIP_TRY(hipMemcpy(h.gtab, gt.data(), gt.size() * sizeof(int), hipMemcpyHostToDevice));
+  h.gtab_n = (int)gt.size();
   return ABS_OK;
 }
 
@@ -221,7 +248,7 @@ void prof_end(Handle& h, int cls, hipStream_t st) {
 static void free_handle(Handle& h) {
   if (h.ev0) (void)hipEventDestroy(h.ev0);
   if (h.ev1) (void)hipEventDestroy(h.ev1);
-  void* ptrs[] = {h.feeds, h.gather, h.rtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
+  void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
                   h.seg, h.pseg, h.ctl};

@@ -137,6 +137,8 @@ struct Handle {
   int* jtab = nullptr;                       // device packed Jacobian structure (row, col) per entry
   int* rtab = nullptr;                       // device residual term table (RT_*)
   int rtab_n = 0;
+  int* gtab = nullptr;                       // device J^T y term table: [NV + 1] starts, then (coef, row) codes
+  int gtab_n = 0;
   Scaling sc{};
   double* cs = nullptr;                      // device [S][N][NR] row scaling
   double sf = 1.0;

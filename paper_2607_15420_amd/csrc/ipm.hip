@@ -126,56 +126,66 @@ struct SegView {
   __device__ long long ci() const { return tid < NR * ns ? NR * t0 + tid : -1; }
   __device__ long long ti() const { return tid < ns ? t0 + tid : -1; }
 };
-
-// ---- Lagrangian gradient g = grad f~ + J~^T y for the stage primals; the
-// stage's contribution to the d entry in dpart
-__global__ void k_lag_grad(const double* __restrict__ rec, const int* __restrict__ jtab,
-                           const double* __restrict__ y, const StageInfo* __restrict__ sinfo, long long nst,
-                           double* __restrict__ g, double* __restrict__ dpart) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nst) return;
-  const StageInfo si = sinfo[t];
-  const int n = si.n, N = si.N;
-  double acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  const double* R = rec + t * REC;
-  const double* yy = y + t * NR;
-  double dp = 0.0;
-  for (int e = 0; e < NJO; ++e) {
-    const int rc = jtab[e];
-    const int r = rc & 255, col = (rc >> 8) & 255, blk = rc >> 16;
-    if (blk == BLK_D) dp += R[REC_OWN + e] * yy[r];
-    else acc[col] += R[REC_OWN + e] * yy[r];
-  }
-  if (n > 0) {  // rows of stage n-1 depend on this stage through the liquid it receives
-    const double* R0 = R - REC;
-    const double* y0 = yy - NR;
-    for (int e = 0; e < NJU; ++e) {
-      const int rc = jtab[NJO + e];
-      acc[(rc >> 8) & 255] += R0[REC_UP + e] * y0[rc & 255];
+// Lagrangian gradient J^T y of the stage variables (the objective's only
+// term, on d, is added in k_grad_d).  One block per IPM segment stages the
+// segment's records and multipliers, with one neighbour on each side, in LDS;
+// one thread per (stage, variable) walks that variable's term list (J entries
+// of its stage and of both neighbours times the rows' multipliers).
+// dpart[g] = sum over segment g of b_t y_hyd(t) (the d column of J^T y).
+constexpr int GBS = 256;  // >= NV * SEG threads
+__global__ __launch_bounds__(GBS) void k_lag_grad(const double* __restrict__ rec, const int* __restrict__ gtab,
+                                                   int gtab_n, const double* __restrict__ y,
+                                                   const Seg* __restrict__ segs, const StageInfo* __restrict__ sinfo,
+                                                   long long nst, int jd, double* __restrict__ g,
+                                                   double* __restrict__ dpart) {
+  __shared__ double cf[(SEG + 2) * REC];
+  __shared__ double sy[(SEG + 2) * NR];
+  __shared__ int tab[RT_MAX];
+  __shared__ double dsum[SEG];
+  const int tid = threadIdx.x;
+  const Seg sg = segs[blockIdx.x];
+  const long long t0 = sg.t0;
+  const int ns = sg.t1 - sg.t0;
+  const long long la = t0 > 0 ? t0 - 1 : 0, lb = sg.t1 + 1 < nst ? sg.t1 + 1 : nst;
+  const int s0 = (int)(la - (t0 - 1));  // LDS slot of stage la (slot s holds stage t0 - 1 + s)
+  for (int i = tid; i < (int)(lb - la) * REC; i += GBS) cf[s0 * REC + i] = rec[la * REC + i];
+  for (int i = tid; i < (int)(lb - la) * NR; i += GBS) sy[s0 * NR + i] = y[la * NR + i];
+  for (int i = tid; i < gtab_n; i += GBS) tab[i] = gtab[i];
+  __syncthreads();
+  const int k = tid / SEG, ls = tid - k * SEG;
+  if (k < NV && ls < ns) {
+    const long long t = t0 + ls;
+    const StageInfo si = sinfo[t];
+    const bool has_dn = si.n > 0, has_up = si.n < si.N - 1;
+    const int s = ls + 1;
+    const int cbase = s * REC - RT_COFF, ybase = s * NR - RT_XOFF;
+    const int* tl = tab + NV + 1;
+    double a = 0.0;
+    for (int q = tab[k]; q < tab[k + 1]; ++q) {
+      const int c = tl[2 * q], yc = tl[2 * q + 1];
+      const bool ok = !(((yc & RT_NBDN) && !has_dn) || ((yc & RT_NBUP) && !has_up));
+      const double pr = cf[cbase + c] * sy[ybase + (yc & (RT_XDTERM - 1))];
+      a += ok ? pr : 0.0;
     }
+    g[t * NV + k] = a;
+    if (k == 0) dsum[ls] = cf[s * REC + jd] * sy[s * NR + NR - 1];
   }
-  if (n < N - 1) {  // rows of stage n+1 depend on this stage through the vapour it receives
-    const double* R1 = R + REC;
-    const double* y1 = yy + NR;
-    for (int e = 0; e < NJD; ++e) {
-      const int rc = jtab[NJO + NJU + e];
-      acc[(rc >> 8) & 255] += R1[REC_DOWN + e] * y1[rc & 255];
-    }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0;
+    for (int l = 0; l < ns; ++l) a += dsum[l];  // fixed order
+    dpart[blockIdx.x] = a;
   }
-#pragma unroll
-  for (int k = 0; k < NV; ++k) g[t * NV + k] = acc[k];
-  dpart[t] = dp;
 }
 
-// g_d = sf * D_d + the problem's hydraulic-row terms (one block per problem, fixed order)
-__global__ void k_grad_d(const double* __restrict__ dpart, const long long* __restrict__ pstage, double gf,
-                         long long nxs, double* __restrict__ g) {
+// g_d = sf * D_d + the problem's hydraulic-row terms (one block per problem,
+// fixed order over its segments)
+__global__ void k_grad_d(const double* __restrict__ dpart, const int* __restrict__ pseg, double gf, long long nxs,
+                         double* __restrict__ g) {
   __shared__ double sm[BS];
   const int p = blockIdx.x;
   double a = 0.0;
-  for (long long t = pstage[p] + threadIdx.x; t < pstage[p + 1]; t += BS) a += dpart[t];
+  for (int i = pseg[p] + threadIdx.x; i < pseg[p + 1]; i += BS) a += dpart[i];
   sm[threadIdx.x] = a;
   __syncthreads();
   for (int s = BS / 2; s > 0; s >>= 1) {
@@ -857,9 +867,9 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     int n_fac_it = 0, n_ls_it = 0;
     // ---- evaluation at (x_k, y_k): residuals, Jacobian, Hessian, Lagrangian gradient
     HIP_TRY(launch_eval(h, W.xt, 1, W.y, 1, W.c, st));
-    hipLaunchKernelGGL(k_lag_grad, dim3(grid_for(nst, 128)), dim3(128), 0, st, h.rec, h.jtab, W.y, h.sinfo, nst,
-                       W.g, W.dpart);
-    hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pstage, gf, nxs, W.g);
+    hipLaunchKernelGGL(k_lag_grad, dim3(nseg), dim3(GBS), 0, st, h.rec, h.gtab, h.gtab_n, W.y, h.seg, h.sinfo, nst,
+                       h.jac_d_index, W.g, W.dpart);
+    hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, gf, nxs, W.g);
     hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s, W.vU,
                        b, nxs, h.redbuf);
     // the barrier Hessian diagonals at x_k need no decision of the host: queue them now
