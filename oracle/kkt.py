@@ -32,7 +32,7 @@ import scipy.linalg.lapack as lapack
 from .model import NR, NV
 
 ZERO_PIVOT = 1e-20  # |eigenvalue| of an equilibrated pivot block counted as zero
-OMEGA_STOP = 1e-13  # refinement stops at this componentwise backward error (or when it stalls)
+REFINE_TOL = 1e-10  # refinement stops at this relative residual ||r - Kx||_inf / ||r||_inf (or when it stalls)
 
 
 def scenario_kkt(J: np.ndarray, H: np.ndarray, sig_x: np.ndarray, sig_s: np.ndarray,
@@ -154,21 +154,24 @@ class BorderedKKT:
 
     def solve(self, rs, rd: float, refine: int = 10):
         """Solve with per-scenario right-hand sides rs (list) and the d entry rd,
-        refining on the whole bordered system until the componentwise backward
-        error is at most OMEGA_STOP or stops improving."""
+        refining on the whole bordered system until the relative residual
+        ||r - Kx||_inf / ||r||_inf is at most REFINE_TOL or stops improving."""
         xs, xd = self._solve_once(rs, rd)
+        rn = max([abs(rd)] + [float(np.abs(r).max()) for r in rs])
         best = None
         for _ in range(refine):
             res, resd, omega = self.residual(xs, xd, rs, rd)
-            if best is not None and omega >= best[0]:
+            num = max([abs(resd)] + [float(np.abs(r).max()) for r in res])
+            rel = num / rn if rn > 0 else num
+            if best is not None and not rel < best[0]:
                 xs, xd = best[1], best[2]
                 break
-            best = (omega, xs, xd)
-            if omega <= OMEGA_STOP:
+            best = (rel, xs, xd, omega)
+            if rel <= REFINE_TOL:
                 break
             cs, cd = self._solve_once(res, resd)
             xs, xd = [x + c for x, c in zip(xs, cs)], xd + cd
-        self.last_omega = best[0]
+        self.last_rel, self.last_omega = best[0], best[3]
         return xs, xd
 
     def rel_residual(self, xs, xd: float, rs, rd: float) -> float:

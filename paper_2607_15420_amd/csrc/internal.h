@@ -157,6 +157,7 @@ struct Handle {
   double* kcor = nullptr;                    // [nkkt] refinement correction
   double* kden = nullptr;                    // residual partials: 2 per stage, block maxima, per-problem d rows
   double* omega_d = nullptr;                 // [4] of the last residual: backward errors (rows, d rows), max |res|, max |rhs|
+  double last_omega = 0.0;                   // componentwise backward error of the last refined solve
   Tune tune;
   double* redbuf = nullptr;                  // device reduction partials
   double* redbuf_h = nullptr;                // pinned host mirror

@@ -655,22 +655,21 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     HIP_TRY(launch_solve(h, rhs, st));
     HIP_TRY(launch_schur(h, h.diagx, rhs, 2, sol, st));
   }
-  double best_om = INFINITY, best_rel = INFINITY;
+  double best_rel = INFINITY;
   bool have_best = false;
   double* om = h.redbuf_h + h.red_cap - 4;  // four pinned doubles past the partials
   for (int it = 0; it <= 10; ++it) {
     HIP_TRY(launch_residual(h, h.diagx, h.diags, sol, rhs, h.kres, h.omega_d, st));
     HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const double omega = fmax(om[0], om[1]);
     const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];  // ||res||_inf / ||rhs||_inf
-    if (!(omega < best_om)) {  // no further improvement: restore the best iterate
+    if (!(relr < best_rel)) {  // no further improvement: restore the best iterate
       if (have_best) HIP_TRY(hipMemcpyAsync(sol, h.kcor, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
       break;
     }
-    best_om = omega;
     best_rel = relr;
-    if (omega <= 1e-13 || it == 10) break;  // same stop rule as the reference solve
+    h.last_omega = fmax(om[0], om[1]);  // componentwise backward error of the kept iterate
+    if (relr <= 1e-10 || it == 10) break;  // relative residual target of the refinement
     HIP_TRY(hipMemcpyAsync(h.kcor, sol, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
     have_best = true;
     HIP_TRY(launch_solve(h, h.kres, st));
