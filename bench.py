@@ -46,7 +46,7 @@ def factor_algorithmic(N: int, S: int) -> dict:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "model.h", "internal.h"):
+    for f in ("factor.hip", "model.h"):
         with open(os.path.join(ROOT, "paper_2607_15420_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

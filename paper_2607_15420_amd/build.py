@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabsorber.so")
-SOURCES = ["kernels.hip", "ipm.hip", "newton.hip", "mlp.hip", "warm.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "factor.hip", "ipm.hip", "newton.hip", "mlp.hip", "warm.hip", "api.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1,0 +1,674 @@
+// HIP kernels for gfx950: the per-scenario block LDL^T of the primal-dual KKT
+// system (one wavefront per scenario chain, Bunch-Kaufman pivoting inside each
+// stage), the solve with the stored factor and the Schur complement on the
+// shared diameter.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace absorber {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- block LDL^T
+// Frontal matrix of stage n held one column per lane: lane j owns column j,
+// v[i] is row i.  Columns/rows 0-42 are the stage's KKT unknowns, 43-58 the
+// coupling unknowns of stage n+1, 59 the right-hand side r, 60 the border b
+// (both carried as symmetric extra rows and columns).  Eliminating the 43 own
+// pivots leaves in rows/cols 43-60 the contribution to stage n+1's block and
+// right-hand sides.  The pivot loop uses no LDS: column entries reach every
+// lane through v_readlane (uniform operands), the pivot row is selected by a
+// uniform switch, and the diagonal is kept up to date per lane.
+struct WaveLDS {
+  double bc[WAVE];  // pivot row of the current elimination step (first: reachable by immediate offsets)
+  double src[NSRC];
+  double xr[WAVE];
+  double xb[WAVE];
+};
+
+// value of lane l (l uniform) broadcast to the wave
+__device__ __forceinline__ double rdl(double v, int l) {
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// register i of this lane for a uniform i < NK
+__device__ __forceinline__ double rowsel(const double (&v)[FR], int p) {
+  switch (p) {
+#define ABS_CASE(i) \
+  case i:           \
+    return v[i];
+    ABS_CASE(0) ABS_CASE(1) ABS_CASE(2) ABS_CASE(3) ABS_CASE(4) ABS_CASE(5) ABS_CASE(6) ABS_CASE(7)
+    ABS_CASE(8) ABS_CASE(9) ABS_CASE(10) ABS_CASE(11) ABS_CASE(12) ABS_CASE(13) ABS_CASE(14) ABS_CASE(15)
+    ABS_CASE(16) ABS_CASE(17) ABS_CASE(18) ABS_CASE(19) ABS_CASE(20) ABS_CASE(21) ABS_CASE(22) ABS_CASE(23)
+    ABS_CASE(24) ABS_CASE(25) ABS_CASE(26) ABS_CASE(27) ABS_CASE(28) ABS_CASE(29) ABS_CASE(30) ABS_CASE(31)
+    ABS_CASE(32) ABS_CASE(33) ABS_CASE(34) ABS_CASE(35) ABS_CASE(36) ABS_CASE(37) ABS_CASE(38) ABS_CASE(39)
+    ABS_CASE(40) ABS_CASE(41) ABS_CASE(42)
+#undef ABS_CASE
+    default:
+      return 0.0;
+  }
+}
+
+// Wave maximum of a non-negative double and its lane.  The key is the high
+// word of the value (sign, exponent, 20 mantissa bits) with its 6 lowest bits
+// replaced by 63 - lane (ties go to the lowest lane); keys are max-reduced with
+// DPP row shifts and row broadcasts and lane 63 ends with the maximum.  The
+// returned value keeps 14 mantissa bits (relative truncation below 2^-14),
+// which is all the pivot tests compare.
+#define ABS_DPP_MAX_U32(k, ctrl, rm, bm)                                                          \
+  do {                                                                                           \
+    const unsigned o_ = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(k), ctrl, rm, bm, false); \
+    (k) = o_ > (k) ? o_ : (k);                                                                   \
+  } while (0)
+
+__device__ __forceinline__ double wave_max_lane(double a, int lane, int& idx) {
+  unsigned key = ((unsigned)__double2hiint(a) & ~63u) | (unsigned)(63 - lane);
+  ABS_DPP_MAX_U32(key, 0x111, 0xf, 0xf);  // row_shr:1
+  ABS_DPP_MAX_U32(key, 0x112, 0xf, 0xf);  // row_shr:2
+  ABS_DPP_MAX_U32(key, 0x114, 0xf, 0xf);  // row_shr:4
+  ABS_DPP_MAX_U32(key, 0x118, 0xf, 0xf);  // row_shr:8
+  ABS_DPP_MAX_U32(key, 0x142, 0xa, 0xf);  // row_bcast:15
+  ABS_DPP_MAX_U32(key, 0x143, 0xc, 0xf);  // row_bcast:31
+  const unsigned m = (unsigned)__builtin_amdgcn_readlane((int)key, 63);
+  idx = 63 - (int)(m & 63u);
+  return __hiloint2double((int)(m & ~63u), 0);
+}
+
+// Eliminate the 43 own pivots of one stage (Bunch-Kaufman inside the stage);
+// stores one pivot column per slot (rows still active, code, d or 2x2 block,
+// 1/d).  The matrix is symmetric, so the pivot candidates' columns are read
+// as rows (register p of every lane) with a uniform switch.
+__device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restrict__ sb, double* bc,
+                                                int& npos, int& nneg, int& nzero) {
+  int lane = lane_id();
+  __asm__ volatile("" : "+v"(lane));
+  const double alpha = (1.0 + sqrt(17.0)) * 0.125;
+  uint64_t act = (1ull << NK) - 1ull;
+  int slot = 0;
+  while (act) {
+    const int k = __builtin_ctzll(act);
+    const bool own_act = lane < NK && ((act >> lane) & 1ull);
+    const double rowk = rowsel(v, k);  // F[k][lane] = F[lane][k]
+    const double dkk = rdl(rowk, k);
+    // 1/d for the usual 1x1 pivot at k, started before the search so that the
+    // two dependency chains overlap
+    const double dinv_k = dkk == 0.0 ? 0.0 : 1.0 / dkk;
+    const double akk = fabs(dkk);
+    int r;
+    const double lam = wave_max_lane(own_act && lane != k ? fabs(rowk) : 0.0, lane, r);
+    int ptype = 1;  // 1: 1x1 at k, 2: 1x1 at r, 3: 2x2 (k, r)
+    double rowr = 0.0;
+    if (!(akk >= alpha * lam) && lam > 0.0) {
+      rowr = rowsel(v, r);
+      int r2;
+      const double sig = wave_max_lane(own_act && lane != r ? fabs(rowr) : 0.0, lane, r2);
+      if (akk * sig >= alpha * lam * lam) ptype = 1;
+      else if (fabs(rdl(rowr, r)) >= alpha * sig) ptype = 2;
+      else ptype = 3;
+    }
+    const bool in_col = lane < FR && (lane >= NK || ((act >> lane) & 1ull));
+    const bool two = ptype == 3;
+    const int p0 = ptype == 2 ? r : k;
+    const int p1 = two ? r : p0;
+    const double rk = ptype == 2 ? rowr : rowk;  // F[p0][lane]
+    const double rr = two ? rowr : 0.0;          // F[p1][lane]
+    const bool ca = in_col && lane != p0 && lane != p1;
+    double t1 = 0.0, t2 = 0.0;
+    bool zero = false;
+    if (!two) {
+      double d = dkk, dinv = dinv_k;
+      if (ptype == 2) {
+        d = rdl(rk, p0);
+        dinv = d == 0.0 ? 0.0 : 1.0 / d;
+      }
+      double sv = ca ? rk : 0.0;
+      if (lane == FR) sv = (double)(p0 + 64 * (d == 0.0 ? 0 : 1));
+      else if (lane == FR + 1) sv = d;
+      else if (lane > FR + 1) sv = dinv;
+      sb[slot * SLOT + lane] = sv;
+      slot += 1;
+      if (d == 0.0) {
+        ++nzero;
+        zero = true;
+      } else {
+        const int pos = d > 0.0 ? 1 : 0;  // branch-free: keeps the counters in registers
+        npos += pos;
+        nneg += 1 - pos;
+        t1 = ca ? rk * dinv : 0.0;
+      }
+    } else {
+      const double e11 = rdl(rk, p0), e12 = rdl(rk, p1), e22 = rdl(rr, p1);
+      const double det = e11 * e22 - e12 * e12;
+      double s0 = ca ? rk : 0.0, s1 = ca ? rr : 0.0;
+      if (lane == FR) {
+        s0 = (double)(p0 + 64 * 2);
+        s1 = (double)(p1 + 64 * 3);
+      } else if (lane == FR + 1) {
+        s0 = e11;
+        s1 = e22;
+      } else if (lane == FR + 2) {
+        s0 = e12;
+        s1 = e12;
+      }
+      sb[slot * SLOT + lane] = s0;
+      sb[(slot + 1) * SLOT + lane] = s1;
+      slot += 2;
+      if (det < 0.0) {
+        ++npos;
+        ++nneg;
+      } else if (det > 0.0) {
+        const int pos = e11 + e22 > 0.0 ? 2 : 0;
+        npos += pos;
+        nneg += 2 - pos;
+      } else {
+        nzero += 2;
+        zero = true;
+      }
+      if (!zero) {
+        const double idet = 1.0 / det;
+        const double i11 = e22 * idet, i12 = -e12 * idet, i22 = e11 * idet;
+        t1 = ca ? i11 * rk + i12 * rr : 0.0;
+        t2 = ca ? i12 * rk + i22 * rr : 0.0;
+      }
+    }
+    act &= ~((1ull << p0) | (1ull << p1));
+    if (zero) continue;
+    // The pivot row reaches every lane through LDS (all lanes read the same
+    // address, a broadcast).  Rows already eliminated (and p0/p1 themselves)
+    // are updated too: they are never read again.  A 2x2 pivot is applied as
+    // two rank-1 passes (c1 t1^T, then c2 t2^T).
+    for (int pass = 0; pass < (two ? 2 : 1); ++pass) {
+      const double tt = pass ? t2 : t1;
+      bc[lane] = pass ? rr : rk;
+      __syncthreads();
+      // software pipelined: the next eight entries are read while eight rows update
+      double qa[8], qb[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) qa[j] = bc[j];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c < 7) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) qb[j] = bc[8 * (c + 1) + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (8 * c + j < FR) v[8 * c + j] = fma(-qa[j], tt, v[8 * c + j]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) qa[j] = qb[j];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Backward sweep of one stage for two right-hand sides.  The stage's pivot
+// columns are gathered into registers in pivot order (lane s holds slot s;
+// reg[q] = its entry at the row eliminated q-th), so that each step is a
+// static-register update.  zr/zb enter as y (forward values by slot) and the
+// solutions of the stage above (LDS, by stage-local index; read at the 16
+// coupling indices) are applied first.
+// On return lane s holds the solution of pivot s in xr_s/xb_s and p_s its index.
+__device__ __forceinline__ void backward_stage(const double* __restrict__ sb, double zr, double zb,
+                                               const double* xcr, const double* xcb, bool two,
+                                               double& xr_s, double& xb_s, int& p_s) {
+  int lane = lane_id();
+  __asm__ volatile("" : "+v"(lane));
+  const int ls = lane < NK ? lane : 0;
+  const double code_l = sb[ls * SLOT + FR];
+  const double a_l = sb[ls * SLOT + FR + 1];   // d, or e11 / e22 of a 2x2 pair
+  const double b_l = sb[ls * SLOT + FR + 2];   // 1/d, or e12
+  p_s = ((int)code_l) & 63;
+  double reg[NK];
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    const int pq = ((int)rdl(code_l, q)) & 63;
+    reg[q] = sb[ls * SLOT + pq];
+    if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    const double c = sb[ls * SLOT + NK + a];
+    zr = fma(-c, xcr[coupling_index(a)], zr);
+    if (two) zb = fma(-c, xcb[coupling_index(a)], zb);
+  }
+  xr_s = 0.0;
+  xb_s = 0.0;
+  bool skip = false;
+#pragma unroll
+  for (int s = NK - 1; s >= 0; --s) {
+    if (skip) {
+      skip = false;
+      continue;
+    }
+    const int code = (int)rdl(code_l, s);
+    const int type = code >> 6;
+    if (s > 0 && type == 3) {
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int s0 = s > 0 ? s - 1 : 0;
+      const double e11 = rdl(a_l, s0), e12 = rdl(b_l, s0), e22 = rdl(a_l, s);
+      const double idet = 1.0 / (e11 * e22 - e12 * e12);
+      const double zk = rdl(zr, s0), zq = rdl(zr, s);
+      const double xk = (e22 * zk - e12 * zq) * idet, xq = (e11 * zq - e12 * zk) * idet;
+      zr = fma(-reg[s0], xk, fma(-reg[s], xq, zr));
+      if (lane == s0) xr_s = xk;
+      if (lane == s) xr_s = xq;
+      if (two) {
+        const double wk = rdl(zb, s0), wq = rdl(zb, s);
+        const double yk = (e22 * wk - e12 * wq) * idet, yq = (e11 * wq - e12 * wk) * idet;
+        zb = fma(-reg[s0], yk, fma(-reg[s], yq, zb));
+        if (lane == s0) xb_s = yk;
+        if (lane == s) xb_s = yq;
+      }
+      skip = true;
+    } else {
+      const double dinv = rdl(b_l, s);
+      const double x = type ? rdl(zr, s) * dinv : 0.0;
+      zr = fma(-reg[s], x, zr);
+      if (lane == s) xr_s = x;
+      if (two) {
+        const double y = type ? rdl(zb, s) * dinv : 0.0;
+        zb = fma(-reg[s], y, zb);
+        if (lane == s) xb_s = y;
+      }
+    }
+  }
+}
+
+// Sum over the wave of a double, fixed order (DPP row shifts and row
+// broadcasts on the two halves; lane 63 ends with the total), returned to
+// every lane.
+#define ABS_DPP_ADD_F64(v, ctrl, rm)                                                     \
+  do {                                                                                  \
+    const int lo_ = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, rm, 0xf, false); \
+    const int hi_ = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, rm, 0xf, false); \
+    (v) += __hiloint2double(hi_, lo_);                                                  \
+  } while (0)
+
+__device__ __forceinline__ double wave_total(double v) {
+  ABS_DPP_ADD_F64(v, 0x111, 0xf);  // row_shr:1
+  ABS_DPP_ADD_F64(v, 0x112, 0xf);  // row_shr:2
+  ABS_DPP_ADD_F64(v, 0x114, 0xf);  // row_shr:4
+  ABS_DPP_ADD_F64(v, 0x118, 0xf);  // row_shr:8
+  ABS_DPP_ADD_F64(v, 0x142, 0xa);  // row_bcast:15
+  ABS_DPP_ADD_F64(v, 0x143, 0xc);  // row_bcast:31
+  return rdl(v, 63);
+}
+
+// Backward sweep of one stage for R right-hand sides with rows on lanes:
+// lane i loads row i of every stored pivot column (coalesced), and pivot s
+// (descending) takes x = dinv_s (y_s - sum_i F_s[i] x_i) with one wave sum per
+// right-hand side.  Rows eliminated before s are zero in column s and rows not
+// yet solved hold x = 0, so the sums run over all lanes.  ys[r]: lane s holds
+// the forward value of slot s; xc[r]: solution of the stage above by
+// stage-local index (read at the 16 coupling indices).  On return lane i < 43
+// holds the solution of row i in xl[r].
+template <int R>
+__device__ __forceinline__ void backward_rows(const double* __restrict__ sb, const double (&ys)[R],
+                                              const double* const (&xc)[R], double (&xl)[R]) {
+  const int lane = lane_id();
+  double col[NK];
+#pragma unroll
+  for (int q = 0; q < NK; ++q) col[q] = sb[q * SLOT + lane];
+  const bool cpl = lane >= NK && lane < NK + NC;
+  const int ci = coupling_index(cpl ? lane - NK : 0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) xl[r] = cpl ? xc[r][ci] : 0.0;
+  bool skip = false;
+#pragma unroll
+  for (int s = NK - 1; s >= 0; --s) {
+    if (skip) {
+      skip = false;
+      continue;
+    }
+    const int code = (int)rdl(col[s], FR);
+    const int type = code >> 6, p = code & 63;
+    if (s > 0 && type == 3) {  // second slot of a 2x2 pivot: solve the pair (s-1, s)
+      const int s0 = s > 0 ? s - 1 : 0;
+      const int pa = ((int)rdl(col[s0], FR)) & 63;
+      const double e11 = rdl(col[s0], FR + 1), e12 = rdl(col[s0], FR + 2), e22 = rdl(col[s], FR + 1);
+      const double idet = 1.0 / (e11 * e22 - e12 * e12);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double za = rdl(ys[r], s0) - wave_total(col[s0] * xl[r]);
+        const double zb = rdl(ys[r], s) - wave_total(col[s] * xl[r]);
+        const double xa = (e22 * za - e12 * zb) * idet, xb = (e11 * zb - e12 * za) * idet;
+        if (lane == pa) xl[r] = xa;
+        if (lane == p) xl[r] = xb;
+      }
+      skip = true;
+    } else {
+      const double dinv = rdl(col[s], FR + 2);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double dot = wave_total(col[s] * xl[r]);
+        const double x = type ? (rdl(ys[r], s) - dot) * dinv : 0.0;
+        if (lane == p) xl[r] = x;
+      }
+    }
+  }
+}
+
+template <int WITH_RHS, int WPE>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_factor(
+    const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
+    const double* __restrict__ diagx, const double* __restrict__ diags, const double* __restrict__ dwv,
+    const double* __restrict__ dcv, const int* __restrict__ chain0, const int* __restrict__ chain_p,
+    const int* __restrict__ fmask, int W, int jd, double* __restrict__ slots, double* __restrict__ solr,
+    double* __restrict__ solb, int* __restrict__ inert, double* __restrict__ part) {
+  __shared__ WaveLDS L;
+  const int w = blockIdx.x;
+  if (w >= W) return;
+  const int pw = chain_p[w];
+  if (fmask && !fmask[pw]) return;  // this problem keeps its factorisation
+  const long long t0 = chain0[w];
+  const int N = chain0[w + 1] - (int)t0;
+  const double dw = dwv[pw], dc = dcv[pw];
+  const int lane = lane_id();
+  for (int i = lane; i < NC * (NC + 2); i += WAVE) L.src[SRC_CTB + i] = 0.0;
+  if (lane == 0) L.src[SRC_ZERO] = 0.0;
+  int npos = 0, nneg = 0, nzero = 0;
+  for (int n = 0; n < N; ++n) {
+    const long long t = t0 + n;
+    const double* R = rec + t * REC;
+    double v[FR];
+    for (int i = lane; i < REC; i += WAVE) L.src[SRC_REC + i] = R[i];
+    if (lane < NJD) L.src[SRC_DOWN1 + lane] = (n < N - 1) ? rec[(t + 1) * REC + REC_DOWN + lane] : 0.0;
+    if (lane < NK) L.src[SRC_RHS + lane] = WITH_RHS ? rhs[t * NK + lane] : 0.0;
+    if (lane < NV) L.src[SRC_DIAGX + lane] = diagx[t * NV + lane] + dw;
+    if (lane == 0) {
+      L.src[SRC_BRD] = R[jd];
+      L.src[SRC_DC] = -dc;
+      L.src[SRC_DHYD] = -(1.0 / (diags[t] + dw) + dc);
+    }
+    __syncthreads();
+    // keep the table loads inside the stage loop (hoisting them would pin ~120 registers)
+    const int* gt = gather;
+    __asm__ volatile("" : "+s"(gt));
+#pragma unroll
+    for (int i = 0; i < FR; ++i) {
+      const int g = gt[i * WAVE + lane];
+      v[i] = L.src[g & 1023] + L.src[(g >> 10) & 1023] + L.src[(g >> 20) & 1023];
+      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    eliminate_stage(v, slots + t * NK * SLOT, L.bc, npos, nneg, nzero);
+    // contribution block to stage n+1 (rows/cols 43..60 of the coupling lanes)
+    if (lane >= NK && lane < NK + NC) {
+      const int a = lane - NK;
+#pragma unroll
+      for (int b = 0; b < NC + 2; ++b) L.src[SRC_CTB + a * (NC + 2) + b] = v[NK + b];
+    }
+    __syncthreads();
+  }
+  // ---------------- backward substitution over the stages, top to bottom
+  L.xr[lane] = 0.0;  // solution of the stage above (none above the top stage)
+  L.xb[lane] = 0.0;
+  __syncthreads();
+  double sigb = 0.0, sigr = 0.0, wdd = 0.0;
+  for (int n = N - 1; n >= 0; --n) {
+    const long long t = t0 + n;
+    const double* sb = slots + t * NK * SLOT;
+    const int ls = lane < NK ? lane : 0;
+    const double yr = sb[ls * SLOT + FR_R], yb = sb[ls * SLOT + FR_B];
+    double xr_s, xb_s;
+    int p_s;
+    backward_stage(sb, yr, yb, L.xr, L.xb, true, xr_s, xb_s, p_s);
+    __syncthreads();
+    if (lane < NK) {
+      solr[t * NK + p_s] = xr_s;
+      solb[t * NK + p_s] = xb_s;
+      L.xr[p_s] = xr_s;
+      L.xb[p_s] = xb_s;
+    }
+    __syncthreads();
+    if (lane == NK - 1) {
+      const double b = rec[t * REC + jd];
+      sigb += b * L.xb[NK - 1];
+      sigr += b * L.xr[NK - 1];
+      wdd += rec[t * REC + REC_WDD];
+    }
+  }
+  if (lane == NK - 1) {
+    part[(long long)w * 4 + 0] = sigb;
+    part[(long long)w * 4 + 1] = sigr;
+    part[(long long)w * 4 + 2] = wdd;
+    part[(long long)w * 4 + 3] = 0.0;
+  }
+  if (lane == 0) {
+    inert[w * 4 + 0] = npos;
+    inert[w * 4 + 1] = nneg;
+    inert[w * 4 + 2] = nzero;
+    inert[w * 4 + 3] = 0;
+  }
+}
+
+// Forward and backward substitution with stored pivot columns: solr <- K_w^{-1} rhs.
+template <int WPE>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
+                                                const double* __restrict__ rhs, const int* __restrict__ chain0,
+                                                const int* __restrict__ chain_p, const int* __restrict__ pact,
+                                                int W, int jd, double* __restrict__ solr,
+                                                double* __restrict__ part) {
+  __shared__ double sh[WAVE];
+  const int w = blockIdx.x;
+  if (w >= W) return;
+  if (pact && !pact[chain_p[w]]) {  // problem not being worked on: zero solution
+    if (threadIdx.x == 0) part[(long long)w * 4 + 1] = 0.0;
+    for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE)
+      solr[i] = 0.0;
+    return;
+  }
+  const long long t0 = chain0[w];
+  const int N = chain0[w + 1] - (int)t0;
+  const int lane = lane_id();
+  double ctb = 0.0;  // contribution carried by coupling lane 43+a to stage n+1's index R[a]
+  for (int n = 0; n < N; ++n) {
+    const long long t = t0 + n;
+    const double* sb = slots + t * NK * SLOT;
+    sh[lane] = 0.0;
+    __syncthreads();
+    if (lane >= NK && lane < NK + NC) sh[coupling_index(lane - NK)] = ctb;
+    __syncthreads();
+    double r = (lane < NK ? rhs[t * NK + lane] + sh[lane] : 0.0);
+    double ys = 0.0;  // lane s keeps the forward value of slot s
+    // the stage's 43 pivot columns, all loads in flight at once (lane = row)
+    double col[NK];
+#pragma unroll
+    for (int q = 0; q < NK; ++q) col[q] = sb[q * SLOT + lane];
+    bool skip = false;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+      if (skip) {  // second slot of a 2x2 pivot, applied with the first
+        skip = false;
+        continue;
+      }
+      const double c = col[q];
+      const int code = (int)rdl(c, FR);
+      const int type = code >> 6, p = code & 63;
+      const double cr = lane < FR_R ? c : 0.0;
+      if (q + 1 < NK && type == 2) {
+        const double cn = col[q + 1 < NK ? q + 1 : q];
+        const int pq = ((int)rdl(cn, FR)) & 63;
+        const double e11 = rdl(c, FR + 1), e12 = rdl(c, FR + 2), e22 = rdl(cn, FR + 1);
+        const double yk = rdl(r, p), yq = rdl(r, pq);
+        if (lane == q) ys = yk;
+        if (lane == q + 1) ys = yq;
+        const double idet = 1.0 / (e11 * e22 - e12 * e12);
+        const double t1 = (e22 * yk - e12 * yq) * idet, t2 = (e11 * yq - e12 * yk) * idet;
+        const double c1r = lane < FR_R ? cn : 0.0;
+        r = fma(-cr, t1, fma(-c1r, t2, r));
+        skip = true;
+        continue;
+      }
+      const double yp = rdl(r, p);
+      if (lane == q) ys = yp;
+      if (type == 1) r = fma(-cr, yp * rdl(c, FR + 2), r);
+    }
+    if (lane < NK) solr[t * NK + lane] = ys;  // forward values in slot order
+    ctb = (lane >= NK && lane < NK + NC) ? r : 0.0;
+    __syncthreads();
+  }
+  // backward sweep
+  sh[lane] = 0.0;
+  __syncthreads();
+  double sig = 0.0;
+  for (int n = N - 1; n >= 0; --n) {
+    const long long t = t0 + n;
+    const double* sb = slots + t * NK * SLOT;
+    const double y[1] = {lane < NK ? solr[t * NK + lane] : 0.0};
+    const double* const xc[1] = {sh};
+    double x[1];
+    backward_rows<1>(sb, y, xc, x);
+    __syncthreads();
+    if (lane < NK) {
+      solr[t * NK + lane] = x[0];
+      sh[lane] = x[0];
+    }
+    __syncthreads();
+    if (lane == NK - 1) sig += rec[t * REC + jd] * sh[NK - 1];
+  }
+  if (lane == NK - 1) part[(long long)w * 4 + 1] = sig;
+}
+
+// Schur complement on d.  Fixed-order reduction of the per-scenario partials:
+// sigma_b = sum b^T K^{-1} b, sigma_r = sum b^T K^{-1} r, W_dd and the inertia.
+// One block per problem: sums over the problem's chains (fixed order), then
+// S_d = k_dd - sigma_b with k_dd = sum W_dd + Sigma_d + delta_w, the inertia
+// (Haynsworth: the chains' counts plus the sign of S_d) and
+// dd = (r_d - sigma_r) / S_d.
+__global__ void k_schur(const double* __restrict__ part, const int* __restrict__ inert, const int* __restrict__ pchain,
+                        const double* __restrict__ diagd, const double* __restrict__ dwv, const double* __restrict__ rd,
+                        int mode, DevScalars* __restrict__ outv) {
+  // mode 0: factor only; 1: factor with a right-hand side; 2: right-hand side only
+  __shared__ double sb[256], sr[256], sw[256];
+  __shared__ long long ip[256], in_[256], iz[256];
+  const int pb = blockIdx.x;
+  const int w0 = pchain[pb], w1 = pchain[pb + 1];
+  DevScalars* out = outv + pb;
+  double ab = 0, ar = 0, aw = 0;
+  long long p = 0, q = 0, z = 0;
+  for (int w = w0 + threadIdx.x; w < w1; w += blockDim.x) {
+    ab += part[w * 4 + 0];
+    ar += part[w * 4 + 1];
+    aw += part[w * 4 + 2];
+    p += inert[w * 4 + 0];
+    q += inert[w * 4 + 1];
+    z += inert[w * 4 + 2];
+  }
+  sb[threadIdx.x] = ab;
+  sr[threadIdx.x] = ar;
+  sw[threadIdx.x] = aw;
+  ip[threadIdx.x] = p;
+  in_[threadIdx.x] = q;
+  iz[threadIdx.x] = z;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      sw[threadIdx.x] += sw[threadIdx.x + s];
+      ip[threadIdx.x] += ip[threadIdx.x + s];
+      in_[threadIdx.x] += in_[threadIdx.x + s];
+      iz[threadIdx.x] += iz[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (mode != 2) {
+      out->sig_b = sb[0];
+      out->wdd = sw[0];
+      out->kdd = sw[0] + diagd[pb] + dwv[pb];
+      out->sd = out->kdd - sb[0];
+      long long np = ip[0], nn = in_[0], nz = iz[0];
+      if (out->sd > 0.0) ++np;
+      else if (out->sd < 0.0) ++nn;
+      else ++nz;
+      out->npos = np;
+      out->nneg = nn;
+      out->nzero = nz;
+    }
+    if (mode != 0) {
+      out->sig_r = sr[0];
+      out->rd = rd[pb];
+      out->dd = (rd[pb] - sr[0]) / out->sd;
+    }
+  }
+}
+
+// sol = solr - solb * dd_p on the stage entries, sol[d_p] = dd_p
+__global__ void k_combine(const double* __restrict__ solr, const double* __restrict__ solb,
+                          const DevScalars* __restrict__ sc, const StageInfo* __restrict__ sinfo, long long nk,
+                          int P, double* __restrict__ sol) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nk) sol[i] = solr[i] - solb[i] * sc[sinfo[i / NK].p].dd;
+  else if (i < nk + P) sol[i] = sc[i - nk].dd;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launch wrappers
+hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
+                         hipStream_t st) {
+  const int* fm = mask ? h.fmask : nullptr;
+  prof_begin(h, st);
+#define ABS_FACTOR(R, W)                                                                                     \
+  hipLaunchKernelGGL((k_factor<R, W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
+                     h.dcv, h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part)
+  const int wpe = h.tune.factor_wpe;
+  if (rhs) {
+    if (wpe == 2) ABS_FACTOR(1, 2);
+    else if (wpe == 4) ABS_FACTOR(1, 4);
+    else ABS_FACTOR(1, 3);
+  } else {
+    if (wpe == 2) ABS_FACTOR(0, 2);
+    else if (wpe == 4) ABS_FACTOR(0, 4);
+    else ABS_FACTOR(0, 3);
+  }
+#undef ABS_FACTOR
+  prof_end(h, 0, st);
+  h.factored = true;
+  ++h.n_factor;
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
+  prof_begin(h, st);
+  const int* pa = h.pact_on ? h.pact : nullptr;
+#define ABS_SOLVE(W)                                                                                             \
+  hipLaunchKernelGGL((k_solve<W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, h.S, \
+                     h.jac_d_index, h.solr, h.part)
+  if (h.tune.solve_wpe == 2) ABS_SOLVE(2);
+  else if (h.tune.solve_wpe == 4) ABS_SOLVE(4);
+  else ABS_SOLVE(3);
+#undef ABS_SOLVE
+  prof_end(h, 1, st);
+  ++h.n_solve;
+  return hipGetLastError();
+}
+
+hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st) {
+  const double* rd = rhs ? rhs + h.nst * NK : nullptr;
+  hipLaunchKernelGGL(k_schur, dim3(h.P), dim3(256), 0, st, h.part, h.inert, h.pchain, diagx + h.nst * NV, h.dwv, rd,
+                     mode, h.scal);
+  if (mode != 0 && sol) {
+    const long long nk = h.nst * NK;
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(nk + h.P, 256)), dim3(256), 0, st, h.solr, h.solb, h.scal, h.sinfo,
+                       nk, h.P, sol);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace absorber
