@@ -203,7 +203,12 @@ hipError_t launch_eval(Handle& h, const double* x, int scaled, const double* y, 
 hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling& sc, const double* cs,
                            const double* y, int full, double* c_out, hipStream_t st);
 // solve with the stored factors, Schur combine and iterative refinement
-int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st);
+// Solve with the stored factorisation and refine on the bordered system until
+// ||r - K x||_inf <= 1e-10 ||r||_inf (at most 10 corrections, keeping the best).
+// first_residual_read: the residual of the fused solution has been computed and
+// its norms copied to the last four doubles of redbuf_h.
+int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st,
+                      bool first_residual_read = false);
 // res[P]; active0 (host [P], may be null): only these problems iterate and
 // are written to xout/yout/res
 int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0, const double* y0, double* xout,

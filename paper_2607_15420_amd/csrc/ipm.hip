@@ -374,6 +374,23 @@ __global__ void k_trial(const Seg* __restrict__ seg, const PS* __restrict__ ps, 
   if (t >= 0) st[t] = s[t] + q.alpha * dsl[t];
 }
 
+// first trial point of every active problem, at the step alpha_max that the
+// direction reduction left on the device (aout[4 p]); queued before the host
+// has read that reduction
+__global__ void k_trial_first(const Seg* __restrict__ seg, const PS* __restrict__ ps,
+                              const double* __restrict__ aout, const double* __restrict__ x,
+                              const double* __restrict__ dx, const double* __restrict__ s,
+                              const double* __restrict__ dsl, long long nxs, double* __restrict__ xt,
+                              double* __restrict__ st) {
+  const SegView V(seg);
+  if (!ps[V.p].active) return;
+  const double a = aout[4 * V.p];
+  const long long i = V.xi(nxs);
+  if (i >= 0) xt[i] = x[i] + a * dx[i];
+  const long long t = V.ti();
+  if (t >= 0) st[t] = s[t] + a * dsl[t];
+}
+
 // line-search partials at a point: 0 theta (1-norm), 1 barrier sum, 2 infeasible count
 __global__ void k_ls_parts(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ xt,
                            const double* __restrict__ st, const double* __restrict__ c, Bnd b, double kd,
@@ -635,22 +652,8 @@ static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
   return ABS_OK;
 }
 
-// two sets of segment partials reduced at once: K1 per segment at h.redbuf,
-// K2 per segment after them; results -> h.redbuf_h[p * K1 + k], then
-// h.redbuf_h[K1 * P + p * K2 + k]
-template <int K1, int K2>
-static int seg_reduce2(Handle& h, const Ops<K1>& ops1, const Ops<K2>& ops2, hipStream_t st) {
-  double* out = h.redbuf + (long long)h.nseg * (K1 + K2);
-  hipLaunchKernelGGL(k_seg_reduce<K1>, dim3(h.P), dim3(BS), 0, st, h.redbuf, h.pseg, ops1, out);
-  hipLaunchKernelGGL(k_seg_reduce<K2>, dim3(h.P), dim3(BS), 0, st, h.redbuf + (long long)h.nseg * K1, h.pseg, ops2,
-                     out + (long long)h.P * K1);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * h.P * (K1 + K2), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  return ABS_OK;
-}
-
-int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st) {
+int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st,
+                      bool first_residual_read) {
   if (!fused_first) {
     HIP_TRY(launch_solve(h, rhs, st));
     HIP_TRY(launch_schur(h, h.diagx, rhs, 2, sol, st));
@@ -659,9 +662,11 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
   bool have_best = false;
   double* om = h.redbuf_h + h.red_cap - 4;  // four pinned doubles past the partials
   for (int it = 0; it <= 10; ++it) {
-    HIP_TRY(launch_residual(h, h.diagx, h.diags, sol, rhs, h.kres, h.omega_d, st));
-    HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    if (it > 0 || !first_residual_read) {  // else the caller has read the first residual's norms into om
+      HIP_TRY(launch_residual(h, h.diagx, h.diags, sol, rhs, h.kres, h.omega_d, st));
+      HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
     const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];  // ||res||_inf / ||rhs||_inf
     if (!(relr < best_rel)) {  // no further improvement: restore the best iterate
       if (have_best) HIP_TRY(hipMemcpyAsync(sol, h.kcor, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
@@ -928,6 +933,10 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       ++nfact;
       ++n_fac_it;
       HIP_TRY(launch_schur(h, h.diagx, W.rhs, 1, W.sol, st));
+      // the first residual of this solve is queued with the inertia read (one round trip
+      // for both; it is wasted only when the inertia asks for another factorisation)
+      HIP_TRY(launch_residual(h, h.diagx, h.diags, W.sol, W.rhs, h.kres, h.omega_d, st));
+      HIP_TRY(hipMemcpyAsync(h.redbuf_h + h.red_cap - 4, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(h.scal_h, h.scal, sizeof(DevScalars) * P, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
       bool again = false;
@@ -958,7 +967,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     if (n_active == 0) break;
     const auto ph2 = now();
     TRY(upload());
-    TRY(kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st));
+    TRY(kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st, true));
     max_rel = std::max(max_rel, rel);
     const auto ph3 = now();
     // ---- step pieces and fraction to the boundary
@@ -968,7 +977,24 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
                        h.redbuf);
     hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
                        h.redbuf + 4LL * nseg);
-    TRY((seg_reduce2<4, 3>(h, Ops<4>{{2, 2, 0, 0}}, Ops<3>{{0, 0, 0}}, st)));
+    {
+      // per problem: [4] direction values, [3] the current point's theta/phi parts, then
+      // [3] those of the first trial point (at alpha_max, queued without a round trip)
+      double* out = h.redbuf + 7LL * nseg;
+      hipLaunchKernelGGL(k_seg_reduce<4>, dim3(P), dim3(BS), 0, st, h.redbuf, h.pseg, Ops<4>{{2, 2, 0, 0}}, out);
+      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(BS), 0, st, h.redbuf + 4LL * nseg, h.pseg,
+                         Ops<3>{{0, 0, 0}}, out + 4LL * P);
+      hipLaunchKernelGGL(k_trial_first, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, out, W.xt, W.dx, W.s, W.ds, nxs,
+                         W.xtt, W.st);
+      HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
+      hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d,
+                         nxs, h.redbuf);
+      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(BS), 0, st, h.redbuf, h.pseg, Ops<3>{{0, 0, 0}},
+                         out + 7LL * P);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * 10 * P, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
     for (int p = 0; p < P; ++p) {
       Prob& q = pr[(size_t)p];
       const double* dv = h.redbuf_h + p * 4;
@@ -995,19 +1021,23 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     }
     // ---- filter line search, all searching problems at once
     const auto ph4 = now();
-    while (true) {
+    for (bool first = true;; first = false) {
       ++n_ls_it;
-      TRY(upload());
-      hipLaunchKernelGGL(k_trial, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.dx, W.s, W.ds, nxs, W.xtt, W.st);
-      HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
-      hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d, nxs,
-                         h.redbuf);
-      TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
+      if (!first) {  // the first trial (alpha_max) was evaluated with the direction
+        TRY(upload());
+        hipLaunchKernelGGL(k_trial, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.dx, W.s, W.ds, nxs, W.xtt,
+                           W.st);
+        HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
+        hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d,
+                           nxs, h.redbuf);
+        TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
+      }
+      const double* tvs = first ? h.redbuf_h + 7 * P : h.redbuf_h;
       bool any = false;
       for (int p = 0; p < P; ++p) {
         Prob& q = pr[(size_t)p];
         if (!q.searching) continue;
-        const double* tv = h.redbuf_h + p * 3;
+        const double* tv = tvs + p * 3;
         ++q.nls;
         const double tht = tv[0];
         const double phit = tv[2] > 0 ? INFINITY : h.sf * h.sc.Dd * (q.xd + q.alpha * q.dxd) + tv[1];
