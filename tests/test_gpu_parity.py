@@ -169,6 +169,12 @@ def test_kkt_factor_and_solve(small, dw, dc):
     rs, rd = _to_oracle_order(rhs, S, N)
     xs, xd = F.solve(rs, rd)
     gs, gd = _to_oracle_order(sol.cpu().numpy(), S, N)
+    # the relative residual the device reports is that of the returned solution (oracle's K),
+    # up to the rounding of evaluating a residual: a few eps times max_i (|K||x|)_i / ||r||
+    mag = max(float((np.abs(B.K) @ np.abs(xb) + np.abs(bb) * abs(gd)).max())
+              for B, bb, xb in zip(F.blocks, F.borders, gs))
+    bound = 64 * np.finfo(float).eps * mag / np.abs(rhs).max()
+    assert abs(rel - F.rel_residual(gs, gd, rs, rd)) <= bound, (rel, bound)
     ref = max(np.abs(np.concatenate(xs)).max(), abs(xd))
     assert abs(gd - xd) <= 1e-9 * ref
     for a, b in zip(gs, xs):
