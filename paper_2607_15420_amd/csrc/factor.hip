@@ -85,18 +85,42 @@ __device__ __forceinline__ double wave_max_lane(double a, int lane, int& idx) {
   return __hiloint2double((int)(m & ~63u), 0);
 }
 
-// Eliminate the 43 own pivots of one stage (Bunch-Kaufman inside the stage);
-// stores one pivot column per slot (rows still active, code, d or 2x2 block,
-// 1/d).  The matrix is symmetric, so the pivot candidates' columns are read
-// as rows (register p of every lane) with a uniform switch.
-__device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restrict__ sb, double* bc,
-                                                int& npos, int& nneg, int& nzero) {
+// Rank-1 update of rows 8*C0..60: v[i] -= bc[i] * tt, software pipelined (the
+// next QN entries of the broadcast pivot column are read while QN rows update).
+template <int C0>
+__device__ __forceinline__ void rank1_rows(double (&v)[FR], const double* bc, double tt) {
+  constexpr int QN = 4;
+  constexpr int NQ = (FR + QN - 1) / QN;
+  double qa[QN], qb[QN];
+#pragma unroll
+  for (int j = 0; j < QN; ++j) qa[j] = bc[8 * C0 + j];
+#pragma unroll
+  for (int c = 8 * C0 / QN; c < NQ; ++c) {
+    if (c < NQ - 1) {
+#pragma unroll
+      for (int j = 0; j < QN; ++j) qb[j] = bc[QN * (c + 1) + j];
+    }
+#pragma unroll
+    for (int j = 0; j < QN; ++j)
+      if (QN * c + j < FR) v[QN * c + j] = fma(-qa[j], tt, v[QN * c + j]);
+#pragma unroll
+    for (int j = 0; j < QN; ++j) qa[j] = qb[j];
+  }
+}
+
+// Pivots of one stage taken while the lowest remaining pivot is below LIMIT
+// (Bunch-Kaufman inside the stage); stores one pivot column per slot (rows
+// still active, code, d or 2x2 block, 1/d).  The matrix is symmetric, so the
+// pivot candidates' columns are read as rows (register p of every lane) with a
+// uniform switch.  The rank-1 updates start at row 8*C0.
+template <int C0, int LIMIT>
+__device__ __forceinline__ void eliminate_phase(double (&v)[FR], double* __restrict__ sb, double* bc,
+                                                uint64_t& act, int& slot, int& npos, int& nneg,
+                                                int& nzero) {
   int lane = lane_id();
   __asm__ volatile("" : "+v"(lane));
   const double alpha = (1.0 + sqrt(17.0)) * 0.125;
-  uint64_t act = (1ull << NK) - 1ull;
-  int slot = 0;
-  while (act) {
+  while (act && __builtin_ctzll(act) < LIMIT) {
     const int k = __builtin_ctzll(act);
     const bool own_act = lane < NK && ((act >> lane) & 1ull);
     const double rowk = rowsel(v, k);  // F[k][lane] = F[lane][k]
@@ -185,32 +209,32 @@ __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restr
     act &= ~((1ull << p0) | (1ull << p1));
     if (zero) continue;
     // The pivot row reaches every lane through LDS (all lanes read the same
-    // address, a broadcast).  Rows already eliminated (and p0/p1 themselves)
-    // are updated too: they are never read again.  A 2x2 pivot is applied as
-    // two rank-1 passes (c1 t1^T, then c2 t2^T).
+    // address, a broadcast).  Rows below 8*C0 are never updated: all their
+    // pivots were eliminated before this phase and they are never read again.
+    // Eliminated rows above (and p0/p1 themselves) are updated too, harmlessly.
+    // A 2x2 pivot is applied as two rank-1 passes (c1 t1^T, then c2 t2^T).
     for (int pass = 0; pass < (two ? 2 : 1); ++pass) {
       const double tt = pass ? t2 : t1;
       bc[lane] = pass ? rr : rk;
       __syncthreads();
-      // software pipelined: the next eight entries are read while eight rows update
-      double qa[8], qb[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) qa[j] = bc[j];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (c < 7) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) qb[j] = bc[8 * (c + 1) + j];
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (8 * c + j < FR) v[8 * c + j] = fma(-qa[j], tt, v[8 * c + j]);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) qa[j] = qb[j];
-      }
+      rank1_rows<C0>(v, bc, tt);
       __syncthreads();
     }
   }
+}
+
+
+// Eliminate the 43 own pivots of one stage.  The lowest remaining pivot only
+// grows, so the stage runs in three phases whose rank-1 updates skip the rows
+// 0-15 (then 0-31) once all their pivots are gone: those rows are never read
+// again.
+__device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restrict__ sb, double* bc,
+                                                int& npos, int& nneg, int& nzero) {
+  uint64_t act = (1ull << NK) - 1ull;
+  int slot = 0;
+  eliminate_phase<0, 16>(v, sb, bc, act, slot, npos, nneg, nzero);
+  eliminate_phase<2, 32>(v, sb, bc, act, slot, npos, nneg, nzero);
+  eliminate_phase<4, 64>(v, sb, bc, act, slot, npos, nneg, nzero);
 }
 
 // Backward sweep of one stage for two right-hand sides.  The stage's pivot
