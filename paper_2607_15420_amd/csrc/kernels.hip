@@ -82,10 +82,8 @@ __device__ __forceinline__ void load_inflow(const double* __restrict__ x, const 
   }
 }
 
-// One thread per stage and part: residuals (scaled by cs) and, if full, the
-// scaled stage record: Jacobian blocks (blockIdx.y == 1) and the Lagrangian
-// Hessian block (blockIdx.y == 2) from threads of their own, so that a full
-// evaluation runs three times as many threads, each with a third of the work.
+// One thread per stage: residuals (scaled by cs) and, if full, the scaled stage
+// record: Jacobian blocks and the Lagrangian Hessian block.
 __global__ void k_eval(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ y,
                        const double* __restrict__ cs, const double* __restrict__ feeds, ModelParams p,
                        const StageInfo* __restrict__ sinfo, long long nst, const int* __restrict__ pact, int full,
@@ -106,20 +104,14 @@ __global__ void k_eval(const double* __restrict__ x, Scaling sc, int scaled, con
   double csr[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) csr[r] = cs ? cs[t * NR + r] : 1.0;
-  const int part = full ? (int)blockIdx.y : 0;
-  if (part == 0) {
-    double c[NR];
-    stage_residuals(p, z, f, P, d, c);
+  double c[NR];
+  stage_residuals(p, z, f, P, d, c);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) cout[t * NR + r] = csr[r] * c[r];
-    return;
-  }
+  for (int r = 0; r < NR; ++r) cout[t * NR + r] = csr[r] * c[r];
+  if (!full) return;
   double* R = rec + t * REC;
-  if (part == 1) {
-    RecSink sink{R, csr, sc.D, sc.Dd};
-    stage_jacobian(p, z, f, P, d, n < N - 1, n > 0, sink);
-    return;
-  }
+  RecSink sink{R, csr, sc.D, sc.Dd};
+  stage_jacobian(p, z, f, P, d, n < N - 1, n > 0, sink);
   double lam[NR], lamd[NR], lamu[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -425,7 +417,7 @@ hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling
                            const double* y, int full, double* c_out, hipStream_t st) {
   prof_begin(h, st);
   const int bs = h.tune.eval_bs;
-  hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, bs), full ? 3 : 1), dim3(bs), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
+  hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, bs)), dim3(bs), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
                      h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, full, c_out, h.rec);
   prof_end(h, 2, st);
   return hipGetLastError();
