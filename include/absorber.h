@@ -223,8 +223,10 @@ int absorber_ipm_solve(absorber_t* h, const absorber_ipm_options* opts, const do
  * launched on.  Classes: 0 block LDL^T factorisation (with its fused solve),
  * 1 solve with stored factors, 2 stage evaluation, 3 bordered residual.
  * absorber_profile_enable(h, mask) resets the counters and times the classes
- * whose bit is set in mask (bit k = class k; it adds a stream synchronisation
- * after each timed launch); mask 0 stops timing. */
+ * whose bit is set in mask (bit k = class k); mask 0 stops timing.  The events
+ * add no host synchronisation to the timed work: their times are read (waiting
+ * for the recorded launches) by absorber_profile_get and absorber_profile_enable,
+ * and every 512 timed launches. */
 typedef struct {
   double ms[4];        /* summed kernel time per class */
   int64_t calls[4];    /* launches per class */

@@ -229,25 +229,57 @@ int initial_point(Handle& h, double* x_dev, hipStream_t st) {
   return ABS_OK;
 }
 
-void prof_begin(Handle& h, hipStream_t st) {
-  if (h.prof) (void)hipEventRecord(h.ev0, st);
+static hipEvent_t prof_event(Handle& h) {
+  if (!h.prof_pool.empty()) {
+    hipEvent_t e = h.prof_pool.back();
+    h.prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  // timing only: no system-scope fence (no cache writeback) when the event is recorded
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(Handle& h, int cls, hipStream_t st) {
+  if (!(h.prof & (1 << cls))) return;
+  if (!h.prof_open) h.prof_open = prof_event(h);
+  if (h.prof_open) (void)hipEventRecord(h.prof_open, st);
 }
 
 void prof_end(Handle& h, int cls, hipStream_t st) {
-  if (!(h.prof & (1 << cls))) return;
-  (void)hipEventRecord(h.ev1, st);
-  if (hipEventSynchronize(h.ev1) == hipSuccess) {
+  if (!(h.prof & (1 << cls)) || !h.prof_open) return;
+  hipEvent_t e1 = prof_event(h);
+  if (!e1) return;
+  (void)hipEventRecord(e1, st);
+  h.prof_pending.push_back({h.prof_open, e1, cls});
+  h.prof_open = nullptr;
+  if (h.prof_pending.size() >= 512) (void)prof_flush(h);
+}
+
+int prof_flush(Handle& h) {
+  for (const auto& q : h.prof_pending) {
+    HIP_TRY(hipEventSynchronize(q.e1));  // returns at once for an event already reached
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, h.ev0, h.ev1) == hipSuccess) {
-      h.prof_ms[cls] += ms;
-      h.prof_calls[cls] += 1;
+    if (hipEventElapsedTime(&ms, q.e0, q.e1) == hipSuccess) {
+      h.prof_ms[q.cls] += ms;
+      h.prof_calls[q.cls] += 1;
     }
+    h.prof_pool.push_back(q.e0);
+    h.prof_pool.push_back(q.e1);
   }
+  h.prof_pending.clear();
+  return ABS_OK;
 }
 
 static void free_handle(Handle& h) {
-  if (h.ev0) (void)hipEventDestroy(h.ev0);
-  if (h.ev1) (void)hipEventDestroy(h.ev1);
+  if (!h.prof_pending.empty()) (void)hipEventSynchronize(h.prof_pending.back().e1);
+  for (const auto& q : h.prof_pending) {
+    (void)hipEventDestroy(q.e0);
+    (void)hipEventDestroy(q.e1);
+  }
+  for (hipEvent_t e : h.prof_pool) (void)hipEventDestroy(e);
+  if (h.prof_open) (void)hipEventDestroy(h.prof_open);
   void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
@@ -510,10 +542,8 @@ int absorber_profile_enable(absorber_t* H, int32_t on) {
     return ABS_ERR_ARG;
   }
   Handle& h = H->h;
-  if (on && !h.ev0) {
-    HIP_TRY(hipEventCreate(&h.ev0));
-    HIP_TRY(hipEventCreate(&h.ev1));
-  }
+  const int rc = prof_flush(h);  // pending times belong to the previous setting
+  if (rc != ABS_OK) return rc;
   for (int k = 0; k < 4; ++k) {
     h.prof_ms[k] = 0.0;
     h.prof_calls[k] = 0;
@@ -527,7 +557,9 @@ int absorber_profile_get(const absorber_t* H, absorber_profile* out) {
     set_error("absorber_profile_get: bad argument");
     return ABS_ERR_ARG;
   }
-  const Handle& h = H->h;
+  Handle& h = const_cast<Handle&>(H->h);
+  const int rc = prof_flush(h);
+  if (rc != ABS_OK) return rc;
   for (int k = 0; k < 4; ++k) {
     out->ms[k] = h.prof_ms[k];
     out->calls[k] = h.prof_calls[k];

@@ -647,7 +647,7 @@ __global__ void k_combine(const double* __restrict__ solr, const double* __restr
 hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
                          hipStream_t st) {
   const int* fm = mask ? h.fmask : nullptr;
-  prof_begin(h, st);
+  prof_begin(h, 0, st);
 #define ABS_FACTOR(R, W)                                                                                     \
   hipLaunchKernelGGL((k_factor<R, W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
                      h.dcv, h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part)
@@ -669,7 +669,7 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
 }
 
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
-  prof_begin(h, st);
+  prof_begin(h, 1, st);
   const int* pa = h.pact_on ? h.pact : nullptr;
 #define ABS_SOLVE(W)                                                                                             \
   hipLaunchKernelGGL((k_solve<W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, h.S, \

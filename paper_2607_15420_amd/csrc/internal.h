@@ -172,17 +172,26 @@ struct Handle {
   double* warm_l0 = nullptr;
   int* warm_w = nullptr;
   long long n_factor = 0, n_solve = 0;       // launch counters
-  // optional per-class kernel timing (HIP events on the launch stream)
+  // optional per-class kernel timing: event pairs recorded on the launch stream
+  // and read back only when the profile is fetched (or the pending list is full)
   int prof = 0;  // bit mask of the profiled kernel classes
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t prof_open = nullptr;  // begin event of the launch being timed
+  struct ProfPair {
+    hipEvent_t e0, e1;
+    int cls;
+  };
+  std::vector<ProfPair> prof_pending;
+  std::vector<hipEvent_t> prof_pool;  // recorded events whose times have been read
   double prof_ms[4] = {0, 0, 0, 0};
   long long prof_calls[4] = {0, 0, 0, 0};
 };
 
 void set_error(const std::string& msg);
-// bracket a launch with profiling events (no-ops unless profiling is enabled)
-void prof_begin(Handle& h, hipStream_t st);
+// bracket a launch of class cls with profiling events (no-ops unless the class
+// is profiled); prof_flush waits for the pending events and sums their times
+void prof_begin(Handle& h, int cls, hipStream_t st);
 void prof_end(Handle& h, int cls, hipStream_t st);
+int prof_flush(Handle& h);
 int initial_point(Handle& h, double* x_dev, hipStream_t st);
 
 #define HIP_TRY(expr)                                                                   \

@@ -415,7 +415,7 @@ hipError_t launch_eval(Handle& h, const double* x, int scaled, const double* y, 
 
 hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling& sc, const double* cs,
                            const double* y, int full, double* c_out, hipStream_t st) {
-  prof_begin(h, st);
+  prof_begin(h, 2, st);
   const int bs = h.tune.eval_bs;
   hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, bs)), dim3(bs), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
                      h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, full, c_out, h.rec);
@@ -503,7 +503,7 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   double* part = h.kden;            // 2 per segment
   double* omb = h.kden + 2LL * nb;  // 3 per segment
   double* omd = omb + 3LL * nb;     // 3 per problem
-  prof_begin(h, st);
+  prof_begin(h, 3, st);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RBS), 0, st, h.rec, h.rtab, h.rtab_n, diagx, diags, h.dwv, h.dcv, sol,
                      rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, res, part, omb);
   prof_end(h, 3, st);

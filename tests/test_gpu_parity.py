@@ -189,3 +189,26 @@ def test_kkt_solve_before_factor_is_an_error(params):
     with pytest.raises(AbsorberError):
         h.kkt_solve(rhs, torch.empty_like(rhs))
     h.close()
+
+
+def test_profile_counts_timed_launches(small):
+    """Event timing per kernel class: launches of the enabled classes are counted
+    and timed; times are read when the profile is fetched."""
+    h, params, feeds, N, S, Z, d, x = small
+    lam = torch.zeros(S * N * M.NR, dtype=torch.float64, device=DEV)
+    sig_x = torch.ones(h.nx, dtype=torch.float64, device=DEV)
+    sig_s = torch.ones(S * N, dtype=torch.float64, device=DEV)
+    h.profile_enable(True, mask=0b11)
+    for _ in range(3):
+        h.kkt_factor(_t(x), lam, sig_x, sig_s, 1e-2, 0.0)
+    rhs = torch.ones(h.nkkt, dtype=torch.float64, device=DEV)
+    h.kkt_solve(rhs, torch.empty_like(rhs))
+    p = h.profile()
+    assert p["factor"]["calls"] == 3 and p["factor"]["ms"] > 0.0
+    assert p["solve"]["calls"] >= 1 and p["solve"]["ms"] > 0.0
+    h.profile_enable(True, mask=0b01)  # resets; only the factorisation is timed now
+    h.kkt_factor(_t(x), lam, sig_x, sig_s, 1e-2, 0.0)
+    h.kkt_solve(rhs, torch.empty_like(rhs))
+    p = h.profile()
+    assert p["factor"]["calls"] == 1 and p["solve"]["calls"] == 0
+    h.profile_enable(False)
