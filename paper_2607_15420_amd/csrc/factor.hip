@@ -573,50 +573,70 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
 // S_d = k_dd - sigma_b with k_dd = sum W_dd + Sigma_d + delta_w, the inertia
 // (Haynsworth: the chains' counts plus the sign of S_d) and
 // dd = (r_d - sigma_r) / S_d.
-__global__ void k_schur(const double* __restrict__ part, const int* __restrict__ inert, const int* __restrict__ pchain,
-                        const double* __restrict__ diagd, const double* __restrict__ dwv, const double* __restrict__ rd,
-                        int mode, DevScalars* __restrict__ outv) {
+constexpr int SCHUR_BS = 1024;
+__global__ __launch_bounds__(SCHUR_BS) void k_schur(const double* __restrict__ part, const int* __restrict__ inert,
+                                                    const int* __restrict__ pchain, const double* __restrict__ diagd,
+                                                    const double* __restrict__ dwv, const double* __restrict__ rd,
+                                                    int mode, DevScalars* __restrict__ outv) {
   // mode 0: factor only; 1: factor with a right-hand side; 2: right-hand side only
-  __shared__ double sb[256], sr[256], sw[256];
-  __shared__ long long ip[256], in_[256], iz[256];
+  // The six sums (three of them integer counts, exact in double) run in a fixed
+  // order: thread i takes chains i, i + SCHUR_BS, ... four at a time, then a
+  // shuffle tree inside each wave and across the waves.
+  __shared__ double sm[6][SCHUR_BS / 64];
   const int pb = blockIdx.x;
   const int w0 = pchain[pb], w1 = pchain[pb + 1];
   DevScalars* out = outv + pb;
-  double ab = 0, ar = 0, aw = 0;
-  long long p = 0, q = 0, z = 0;
-  for (int w = w0 + threadIdx.x; w < w1; w += blockDim.x) {
-    ab += part[w * 4 + 0];
-    ar += part[w * 4 + 1];
-    aw += part[w * 4 + 2];
-    p += inert[w * 4 + 0];
-    q += inert[w * 4 + 1];
-    z += inert[w * 4 + 2];
-  }
-  sb[threadIdx.x] = ab;
-  sr[threadIdx.x] = ar;
-  sw[threadIdx.x] = aw;
-  ip[threadIdx.x] = p;
-  in_[threadIdx.x] = q;
-  iz[threadIdx.x] = z;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      sb[threadIdx.x] += sb[threadIdx.x + s];
-      sr[threadIdx.x] += sr[threadIdx.x + s];
-      sw[threadIdx.x] += sw[threadIdx.x + s];
-      ip[threadIdx.x] += ip[threadIdx.x + s];
-      in_[threadIdx.x] += in_[threadIdx.x + s];
-      iz[threadIdx.x] += iz[threadIdx.x + s];
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  int w = w0 + (int)threadIdx.x;
+  for (; w + 3 * SCHUR_BS < w1; w += 4 * SCHUR_BS) {
+    double q[4][6];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long c = (long long)(w + j * SCHUR_BS) * 4;
+      q[j][0] = part[c];
+      q[j][1] = part[c + 1];
+      q[j][2] = part[c + 2];
+      q[j][3] = inert[c];
+      q[j][4] = inert[c + 1];
+      q[j][5] = inert[c + 2];
     }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] += q[j][k];
   }
+  for (; w < w1; w += SCHUR_BS) {
+    const long long c = (long long)w * 4;
+    a[0] += part[c];
+    a[1] += part[c + 1];
+    a[2] += part[c + 2];
+    a[3] += inert[c];
+    a[4] += inert[c + 1];
+    a[5] += inert[c + 2];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] += __shfl_down(a[k], off, 64);
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) sm[k][wv] = a[k];
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    a[k] = lane < SCHUR_BS / 64 ? sm[k][lane] : 0.0;
+#pragma unroll
+    for (int off = SCHUR_BS / 128; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off, 64);
+  }
+  const double sb0 = a[0], sr0 = a[1], sw0 = a[2];
   if (threadIdx.x == 0) {
     if (mode != 2) {
-      out->sig_b = sb[0];
-      out->wdd = sw[0];
-      out->kdd = sw[0] + diagd[pb] + dwv[pb];
-      out->sd = out->kdd - sb[0];
-      long long np = ip[0], nn = in_[0], nz = iz[0];
+      out->sig_b = sb0;
+      out->wdd = sw0;
+      out->kdd = sw0 + diagd[pb] + dwv[pb];
+      out->sd = out->kdd - sb0;
+      long long np = (long long)a[3], nn = (long long)a[4], nz = (long long)a[5];
       if (out->sd > 0.0) ++np;
       else if (out->sd < 0.0) ++nn;
       else ++nz;
@@ -625,9 +645,9 @@ __global__ void k_schur(const double* __restrict__ part, const int* __restrict__
       out->nzero = nz;
     }
     if (mode != 0) {
-      out->sig_r = sr[0];
+      out->sig_r = sr0;
       out->rd = rd[pb];
-      out->dd = (rd[pb] - sr[0]) / out->sd;
+      out->dd = (rd[pb] - sr0) / out->sd;
     }
   }
 }
@@ -685,7 +705,7 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
 
 hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st) {
   const double* rd = rhs ? rhs + h.nst * NK : nullptr;
-  hipLaunchKernelGGL(k_schur, dim3(h.P), dim3(256), 0, st, h.part, h.inert, h.pchain, diagx + h.nst * NV, h.dwv, rd,
+  hipLaunchKernelGGL(k_schur, dim3(h.P), dim3(SCHUR_BS), 0, st, h.part, h.inert, h.pchain, diagx + h.nst * NV, h.dwv, rd,
                      mode, h.scal);
   if (mode != 0 && sol) {
     const long long nk = h.nst * NK;

@@ -90,16 +90,51 @@ __device__ void block_reduce(Part<K> p, const Ops<K>& ops, double* out) {
     for (int k = 0; k < K; ++k) out[blockIdx.x * K + k] = sm[k][0];
 }
 
-// per-problem reduction of segment partials (one block per problem, fixed order)
+// per-problem reduction of segment partials: one block of RS threads per
+// problem; thread i takes segments i, i + RS, ... (four at a time, their loads
+// in flight together), then a fixed shuffle tree within each wave and across
+// the waves.  The order depends only on the segment count: deterministic.
+constexpr int RS = 1024;
 template <int K>
-__global__ void k_seg_reduce(const double* __restrict__ parts, const int* __restrict__ pseg, Ops<K> ops,
-                             double* __restrict__ out) {
+__global__ __launch_bounds__(RS) void k_seg_reduce(const double* __restrict__ parts,
+                                                   const int* __restrict__ pseg, Ops<K> ops,
+                                                   double* __restrict__ out) {
+  __shared__ double sm[K][RS / 64];
   const int p = blockIdx.x;
-  Part<K> acc;
-  for (int k = 0; k < K; ++k) acc.v[k] = ops.op[k] == 0 ? 0.0 : (ops.op[k] == 1 ? -INFINITY : INFINITY);
-  for (int b = pseg[p] + threadIdx.x; b < pseg[p + 1]; b += BS)
-    for (int k = 0; k < K; ++k) acc.v[k] = red_op(ops.op[k], acc.v[k], parts[(long long)b * K + k]);
-  block_reduce<K>(acc, ops, out);
+  double acc[K];
+  for (int k = 0; k < K; ++k) acc[k] = ops.op[k] == 0 ? 0.0 : (ops.op[k] == 1 ? -INFINITY : INFINITY);
+  const int b1 = pseg[p + 1];
+  int b = pseg[p] + (int)threadIdx.x;
+  for (; b + 3 * RS < b1; b += 4 * RS) {
+    double q[4][K];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) q[j][k] = parts[(long long)(b + j * RS) * K + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[k] = red_op(ops.op[k], acc[k], q[j][k]);
+  }
+  for (; b < b1; b += RS)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = red_op(ops.op[k], acc[k], parts[(long long)b * K + k]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = red_op(ops.op[k], acc[k], __shfl_down(acc[k], off, 64));
+  if (lane == 0)
+    for (int k = 0; k < K; ++k) sm[k][wv] = acc[k];
+  __syncthreads();
+  if (wv == 0) {
+    for (int k = 0; k < K; ++k) {
+      double v = lane < RS / 64 ? sm[k][lane] : (ops.op[k] == 0 ? 0.0 : (ops.op[k] == 1 ? -INFINITY : INFINITY));
+#pragma unroll
+      for (int off = RS / 128; off > 0; off >>= 1) v = red_op(ops.op[k], v, __shfl_down(v, off, 64));
+      if (lane == 0) out[p * K + k] = v;
+    }
+  }
 }
 
 // the entries of one segment: thread tid owns primal entry NV t0 + tid (tid <
@@ -645,7 +680,7 @@ struct Prob {
 template <int K>
 static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
   double* out = h.redbuf + (long long)h.nseg * K;
-  hipLaunchKernelGGL(k_seg_reduce<K>, dim3(h.P), dim3(BS), 0, st, h.redbuf, h.pseg, ops, out);
+  hipLaunchKernelGGL(k_seg_reduce<K>, dim3(h.P), dim3(RS), 0, st, h.redbuf, h.pseg, ops, out);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * h.P * K, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -981,15 +1016,15 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       // per problem: [4] direction values, [3] the current point's theta/phi parts, then
       // [3] those of the first trial point (at alpha_max, queued without a round trip)
       double* out = h.redbuf + 7LL * nseg;
-      hipLaunchKernelGGL(k_seg_reduce<4>, dim3(P), dim3(BS), 0, st, h.redbuf, h.pseg, Ops<4>{{2, 2, 0, 0}}, out);
-      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(BS), 0, st, h.redbuf + 4LL * nseg, h.pseg,
+      hipLaunchKernelGGL(k_seg_reduce<4>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg, Ops<4>{{2, 2, 0, 0}}, out);
+      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(RS), 0, st, h.redbuf + 4LL * nseg, h.pseg,
                          Ops<3>{{0, 0, 0}}, out + 4LL * P);
       hipLaunchKernelGGL(k_trial_first, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, out, W.xt, W.dx, W.s, W.ds, nxs,
                          W.xtt, W.st);
       HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
       hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d,
                          nxs, h.redbuf);
-      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(BS), 0, st, h.redbuf, h.pseg, Ops<3>{{0, 0, 0}},
+      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg, Ops<3>{{0, 0, 0}},
                          out + 7LL * P);
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * 10 * P, hipMemcpyDeviceToHost, st));
