@@ -254,11 +254,15 @@ __device__ __forceinline__ void backward_stage(const double* __restrict__ sb, do
   const double a_l = sb[ls * SLOT + FR + 1];   // d, or e11 / e22 of a 2x2 pair
   const double b_l = sb[ls * SLOT + FR + 2];   // 1/d, or e12
   p_s = ((int)code_l) & 63;
+  // Slot s's entry at the row eliminated q-th is zero unless q > s (and is only
+  // read by lanes s < q), so only those lanes load it: the gathers touch half
+  // the cache lines of a full 43 x 43 gather.
   double reg[NK];
 #pragma unroll
   for (int q = 0; q < NK; ++q) {
     const int pq = ((int)rdl(code_l, q)) & 63;
-    reg[q] = sb[ls * SLOT + pq];
+    reg[q] = 0.0;
+    if (lane < q) reg[q] = sb[lane * SLOT + pq];
     if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
