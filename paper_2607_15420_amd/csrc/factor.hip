@@ -28,9 +28,14 @@ inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) /
 // right-hand sides.  The pivot loop uses no LDS: column entries reach every
 // lane through v_readlane (uniform operands), the pivot row is selected by a
 // uniform switch, and the diagonal is kept up to date per lane.
+constexpr int TAIL = SLOT - NK;  // rows 43-63 of a stored pivot column: coupling, r, b, code, d, 1/d
+constexpr int STG = TAIL + 1;     // LDS stride of one staged tail
 struct WaveLDS {
   double bc[WAVE];  // pivot row of the current elimination step (first: reachable by immediate offsets)
-  double src[NSRC];
+  union {
+    double src[NSRC];     // assembly sources (elimination)
+    double stg[NK * STG];  // tails of the stage's pivot columns (backward sweep)
+  };
   double xr[WAVE];
   double xb[WAVE];
 };
@@ -240,19 +245,32 @@ __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restr
 // Backward sweep of one stage for two right-hand sides.  The stage's pivot
 // columns are gathered into registers in pivot order (lane s holds slot s;
 // reg[q] = its entry at the row eliminated q-th), so that each step is a
-// static-register update.  zr/zb enter as y (forward values by slot) and the
-// solutions of the stage above (LDS, by stage-local index; read at the 16
-// coupling indices) are applied first.
+// static-register update.  The tails of the 43 columns (coupling rows, the
+// forward values of r and b, the pivot code and d) are first staged in LDS
+// with coalesced loads (three columns per load) and read back one column per
+// lane.  The solutions of the stage above (LDS, by stage-local index; read at
+// the 16 coupling indices) are applied first.
 // On return lane s holds the solution of pivot s in xr_s/xb_s and p_s its index.
-__device__ __forceinline__ void backward_stage(const double* __restrict__ sb, double zr, double zb,
-                                               const double* xcr, const double* xcb, bool two,
-                                               double& xr_s, double& xb_s, int& p_s) {
+__device__ __forceinline__ void backward_stage(const double* __restrict__ sb, double* stg, const double* xcr,
+                                               const double* xcb, bool two, double& xr_s, double& xb_s,
+                                               int& p_s) {
   int lane = lane_id();
   __asm__ volatile("" : "+v"(lane));
+  {
+    const int sj = lane / TAIL, e = lane - sj * TAIL;  // column sj of each group of three, row NK + e
+#pragma unroll
+    for (int c = 0; c < (NK + 2) / 3; ++c) {
+      const int s = 3 * c + sj;
+      if (sj < 3 && s < NK) stg[s * STG + e] = sb[s * SLOT + NK + e];
+    }
+  }
+  __syncthreads();
   const int ls = lane < NK ? lane : 0;
-  const double code_l = sb[ls * SLOT + FR];
-  const double a_l = sb[ls * SLOT + FR + 1];   // d, or e11 / e22 of a 2x2 pair
-  const double b_l = sb[ls * SLOT + FR + 2];   // 1/d, or e12
+  const double* tl = stg + ls * STG;  // this lane's column tail
+  double zr = tl[FR_R - NK], zb = tl[FR_B - NK];  // forward values of r and b by slot
+  const double code_l = tl[FR - NK];
+  const double a_l = tl[FR + 1 - NK];  // d, or e11 / e22 of a 2x2 pair
+  const double b_l = tl[FR + 2 - NK];  // 1/d, or e12
   p_s = ((int)code_l) & 63;
   // Slot s's entry at the row eliminated q-th is zero unless q > s (and is only
   // read by lanes s < q), so only those lanes load it: the gathers touch half
@@ -267,7 +285,7 @@ __device__ __forceinline__ void backward_stage(const double* __restrict__ sb, do
   }
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
-    const double c = sb[ls * SLOT + NK + a];
+    const double c = tl[a];
     zr = fma(-c, xcr[coupling_index(a)], zr);
     if (two) zb = fma(-c, xcb[coupling_index(a)], zb);
   }
@@ -449,11 +467,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
   for (int n = N - 1; n >= 0; --n) {
     const long long t = t0 + n;
     const double* sb = slots + t * NK * SLOT;
-    const int ls = lane < NK ? lane : 0;
-    const double yr = sb[ls * SLOT + FR_R], yb = sb[ls * SLOT + FR_B];
     double xr_s, xb_s;
     int p_s;
-    backward_stage(sb, yr, yb, L.xr, L.xb, true, xr_s, xb_s, p_s);
+    backward_stage(sb, L.stg, L.xr, L.xb, true, xr_s, xb_s, p_s);
     __syncthreads();
     if (lane < NK) {
       solr[t * NK + p_s] = xr_s;
