@@ -229,6 +229,13 @@ int initial_point(Handle& h, double* x_dev, hipStream_t st) {
   return ABS_OK;
 }
 
+hipError_t wait_stream(hipStream_t st) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e != hipErrorNotReady) return e;
+  }
+}
+
 static hipEvent_t prof_event(Handle& h) {
   if (!h.prof_pool.empty()) {
     hipEvent_t e = h.prof_pool.back();

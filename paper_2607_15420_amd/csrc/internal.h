@@ -187,6 +187,10 @@ struct Handle {
 };
 
 void set_error(const std::string& msg);
+// Wait for the work queued on st by polling it: the solver's per-iteration
+// reads of a few reduced scalars return as soon as the copy has landed,
+// without the wake-up latency of a blocking wait.
+hipError_t wait_stream(hipStream_t st);
 // bracket a launch of class cls with profiling events (no-ops unless the class
 // is profiled); prof_flush waits for the pending events and sums their times
 void prof_begin(Handle& h, int cls, hipStream_t st);

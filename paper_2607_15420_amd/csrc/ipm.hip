@@ -683,7 +683,7 @@ static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
   hipLaunchKernelGGL(k_seg_reduce<K>, dim3(h.P), dim3(RS), 0, st, h.redbuf, h.pseg, ops, out);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * h.P * K, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(wait_stream(st));
   return ABS_OK;
 }
 
@@ -700,7 +700,7 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     if (it > 0 || !first_residual_read) {  // else the caller has read the first residual's norms into om
       HIP_TRY(launch_residual(h, h.diagx, h.diags, sol, rhs, h.kres, h.omega_d, st));
       HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(wait_stream(st));
     }
     const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];  // ||res||_inf / ||rhs||_inf
     if (!(relr < best_rel)) {  // no further improvement: restore the best iterate
@@ -782,7 +782,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   } pact_guard{h};
   auto read_d = [&](const double* v) -> int {  // d entries of a primal vector -> W.dd_h
     HIP_TRY(hipMemcpyAsync(W.dd_h, v + nxs, sizeof(double) * P, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(wait_stream(st));
     return ABS_OK;
   };
 #define TRY(expr)            \
@@ -973,7 +973,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       HIP_TRY(launch_residual(h, h.diagx, h.diags, W.sol, W.rhs, h.kres, h.omega_d, st));
       HIP_TRY(hipMemcpyAsync(h.redbuf_h + h.red_cap - 4, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(h.scal_h, h.scal, sizeof(DevScalars) * P, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(wait_stream(st));
       bool again = false;
       for (int p = 0; p < P; ++p) {
         Prob& q = pr[(size_t)p];
@@ -1028,7 +1028,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
                          out + 7LL * P);
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(h.redbuf_h, out, sizeof(double) * 10 * P, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(wait_stream(st));
     }
     for (int p = 0; p < P; ++p) {
       Prob& q = pr[(size_t)p];
