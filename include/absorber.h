@@ -238,8 +238,9 @@ int absorber_profile_enable(absorber_t* h, int32_t mask);
  * occupancy target of the factorisation and of the stored-factor solve (waves
  * per SIMD 2, 3 or 4, which fixes each wave's register budget) and the block
  * size of the stage evaluation (64, 128 or 256), with the measured time of each
- * candidate in ms (index 0-2 in the order listed).  tuned = 0 until the first
- * factorisation of a solve with autotune on. */
+ * candidate in ms (index 0-2 in the order listed; the factorisation and the
+ * solve are timed on at most the first 12288 scenario chains).  tuned = 0 until
+ * the first factorisation of a solve with autotune on. */
 typedef struct {
   int32_t tuned;
   int32_t factor_waves_per_simd, solve_waves_per_simd, eval_block;

@@ -685,12 +685,13 @@ __global__ void k_combine(const double* __restrict__ solr, const double* __restr
 
 // ---------------------------------------------------------------- launch wrappers
 hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
-                         hipStream_t st) {
+                         hipStream_t st, int nchain) {
   const int* fm = mask ? h.fmask : nullptr;
+  const int nw = nchain < 0 || nchain > h.S ? h.S : nchain;
   prof_begin(h, 0, st);
-#define ABS_FACTOR(R, W)                                                                                     \
-  hipLaunchKernelGGL((k_factor<R, W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
-                     h.dcv, h.chain0, h.chain_p, fm, h.S, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part)
+#define ABS_FACTOR(R, W)                                                                                    \
+  hipLaunchKernelGGL((k_factor<R, W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
+                     h.dcv, h.chain0, h.chain_p, fm, nw, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part)
   const int wpe = h.tune.factor_wpe;
   if (rhs) {
     if (wpe == 2) ABS_FACTOR(1, 2);
@@ -708,11 +709,12 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
   return hipGetLastError();
 }
 
-hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st) {
+hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain) {
+  const int nw = nchain < 0 || nchain > h.S ? h.S : nchain;
   prof_begin(h, 1, st);
   const int* pa = h.pact_on ? h.pact : nullptr;
-#define ABS_SOLVE(W)                                                                                             \
-  hipLaunchKernelGGL((k_solve<W>), dim3(h.S), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, h.S, \
+#define ABS_SOLVE(W)                                                                                           \
+  hipLaunchKernelGGL((k_solve<W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, nw, \
                      h.jac_d_index, h.solr, h.part)
   if (h.tune.solve_wpe == 2) ABS_SOLVE(2);
   else if (h.tune.solve_wpe == 4) ABS_SOLVE(4);

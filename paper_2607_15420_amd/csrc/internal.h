@@ -238,11 +238,12 @@ hipError_t launch_jac_coo(Handle& h, const double* x, double* vals, hipStream_t 
 hipError_t launch_hess_coo(Handle& h, const double* x, const double* lam, double* vals, hipStream_t st);
 // factorise every scenario block from the records with the per-problem
 // regularisation h.dwv/h.dcv (chains of problems whose h.fmask entry is 0 are
-// skipped when mask is true); solve for rhs (may be null) and b
+// skipped when mask is true); solve for rhs (may be null) and b.  nchain >= 0
+// limits the launch to the first nchain chains (launch-shape timing only).
 hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
-                         hipStream_t st);
-// forward/backward with the stored factors: solr <- K_w^{-1} rhs
-hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st);
+                         hipStream_t st, int nchain = -1);
+// forward/backward with the stored factors: solr <- K_w^{-1} rhs (nchain as above)
+hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain = -1);
 // Schur complement on each problem's d.  diagx: Sigma_x (its d entries are
 // Sigma_d); rhs: the right-hand side (its d entries are r_d; may be null in
 // mode 0).  mode 0: after launch_factor without a right-hand side (S_d,

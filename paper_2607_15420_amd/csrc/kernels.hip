@@ -375,32 +375,56 @@ __global__ void k_residual_d(const double* __restrict__ part, const int* __restr
 }
 
 // out[0] = largest backward error over the segments, out[1] over the problems'
-// d rows, out[2] = largest |res_i| and out[3] = largest |rhs_i| over both
-__global__ void k_residual_max(const double* __restrict__ omb, int G, const double* __restrict__ omd, int P,
-                               double* __restrict__ out) {
-  __shared__ double sm[4][256];
-  double a = 0, b = 0, r = 0, q = 0;
-  for (int i = threadIdx.x; i < G; i += blockDim.x) {
-    a = fmax(a, omb[3 * i]);
-    r = fmax(r, omb[3 * i + 1]);
-    q = fmax(q, omb[3 * i + 2]);
+// d rows, out[2] = largest |res_i| and out[3] = largest |rhs_i| over both.  One
+// block of MAX_BS threads, four segments' loads in flight per thread, then a
+// shuffle tree in each wave and across the waves (maxima: order-free).
+constexpr int MAX_BS = 1024;
+__global__ __launch_bounds__(MAX_BS) void k_residual_max(const double* __restrict__ omb, int G,
+                                                         const double* __restrict__ omd, int P,
+                                                         double* __restrict__ out) {
+  __shared__ double sm[4][MAX_BS / 64];
+  double m[4] = {0, 0, 0, 0};  // a, b, r, q
+  int i = threadIdx.x;
+  for (; i + 3 * MAX_BS < G; i += 4 * MAX_BS) {
+    double v[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[j][k] = omb[3LL * (i + j * MAX_BS) + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      m[0] = fmax(m[0], v[j][0]);
+      m[2] = fmax(m[2], v[j][1]);
+      m[3] = fmax(m[3], v[j][2]);
+    }
   }
-  for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    b = fmax(b, omd[3 * i]);
-    r = fmax(r, omd[3 * i + 1]);
-    q = fmax(q, omd[3 * i + 2]);
+  for (; i < G; i += MAX_BS) {
+    m[0] = fmax(m[0], omb[3LL * i]);
+    m[2] = fmax(m[2], omb[3LL * i + 1]);
+    m[3] = fmax(m[3], omb[3LL * i + 2]);
   }
-  sm[0][threadIdx.x] = a;
-  sm[1][threadIdx.x] = b;
-  sm[2][threadIdx.x] = r;
-  sm[3][threadIdx.x] = q;
+  for (int p = threadIdx.x; p < P; p += MAX_BS) {
+    m[1] = fmax(m[1], omd[3 * p]);
+    m[2] = fmax(m[2], omd[3 * p + 1]);
+    m[3] = fmax(m[3], omd[3 * p + 2]);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], __shfl_down(m[k], off, 64));
+  if (lane == 0)
+    for (int k = 0; k < 4; ++k) sm[k][wv] = m[k];
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int k = 0; k < 4; ++k) sm[k][threadIdx.x] = fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + s]);
-    __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double v = lane < MAX_BS / 64 ? sm[k][lane] : 0.0;
+#pragma unroll
+      for (int off = MAX_BS / 128; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+      if (lane == 0) out[k] = v;
+    }
   }
-  if (threadIdx.x < 4) out[threadIdx.x] = sm[threadIdx.x][0];
 }
 
 inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -474,14 +498,19 @@ int autotune(Handle& h, const double* x, const double* y, double* c, const doubl
     h.tune.eval_bs = bss[i];
     h.tune.ms_eval[i] = time_launch(st, e0, e1, [&] { (void)launch_eval(h, x, 1, y, 1, c, st); });
   }
+  // The chain kernels are timed on at most TUNE_CHAINS chains (four rounds of the
+  // wave slots at 3 waves/SIMD): enough for the steady state, and the tuning of a
+  // large batch then costs a fraction of one factorisation per candidate.
+  constexpr int TUNE_CHAINS = 4 * 3 * 4 * 256;
   const int wpes[3] = {2, 3, 4};
   for (int i = 0; i < 3; ++i) {
     h.tune.factor_wpe = wpes[i];
-    h.tune.ms_factor[i] = time_launch(st, e0, e1, [&] { (void)launch_factor(h, diagx, diags, rhs, false, st); });
+    h.tune.ms_factor[i] =
+        time_launch(st, e0, e1, [&] { (void)launch_factor(h, diagx, diags, rhs, false, st, TUNE_CHAINS); });
   }
   for (int i = 0; i < 3; ++i) {
     h.tune.solve_wpe = wpes[i];
-    h.tune.ms_solve[i] = time_launch(st, e0, e1, [&] { (void)launch_solve(h, rhs, st); });
+    h.tune.ms_solve[i] = time_launch(st, e0, e1, [&] { (void)launch_solve(h, rhs, st, TUNE_CHAINS); });
   }
   auto argmin = [](const float* v) { return v[0] <= v[1] ? (v[0] <= v[2] ? 0 : 2) : (v[1] <= v[2] ? 1 : 2); };
   h.tune.eval_bs = bss[argmin(h.tune.ms_eval)];
@@ -508,7 +537,7 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
                      rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, res, part, omb);
   prof_end(h, 3, st);
   hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pseg, h.scal, sol, rhs, nks, pa, res, omd);
-  hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(256), 0, st, omb, nb, omd, h.P, omega_out);
+  hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(MAX_BS), 0, st, omb, nb, omd, h.P, omega_out);
   return hipGetLastError();
 }
 
