@@ -154,7 +154,7 @@ struct Handle {
   double* diagx = nullptr;                   // [nx] Sigma_x for the KKT (scaled)
   double* diags = nullptr;                   // [S][N] Sigma_s
   double* kres = nullptr;                    // [nkkt] refinement residual
-  double* kcor = nullptr;                    // [nkkt] refinement correction
+  double* kcor = nullptr;                    // [nkkt] second iterate buffer of the refinement
   double* kden = nullptr;                    // residual partials: 2 per stage, block maxima, per-problem d rows
   double* omega_d = nullptr;                 // [4] of the last residual: backward errors (rows, d rows), max |res|, max |rhs|
   double last_omega = 0.0;                   // componentwise backward error of the last refined solve
@@ -254,7 +254,8 @@ hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int m
 // componentwise backward error over the scenario rows, omega_out[1] over the d rows
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
                            const double* rhs, double* res, double* omega_out, hipStream_t st);
-hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st);
+// z = y + a x (z may be y)
+hipError_t launch_axpy(double* z, const double* y, const double* x, double a, long long n, hipStream_t st);
 // time the launch-shape candidates on the current data and keep the fastest (h.tune); x, y, c as for
 // launch_eval (scaled, full), diagx/diags/rhs as for launch_factor
 int autotune(Handle& h, const double* x, const double* y, double* c, const double* diagx, const double* diags,

@@ -693,29 +693,31 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     HIP_TRY(launch_solve(h, rhs, st));
     HIP_TRY(launch_schur(h, h.diagx, rhs, 2, sol, st));
   }
+  // Corrections are applied out of place, alternating between sol and h.kcor,
+  // so the best iterate is kept without copying it: xb is the best so far, xn
+  // the iterate whose residual is evaluated next.
   double best_rel = INFINITY;
-  bool have_best = false;
+  double* xb = sol;
+  double* xn = sol;
   double* om = h.redbuf_h + h.red_cap - 4;  // four pinned doubles past the partials
   for (int it = 0; it <= 10; ++it) {
     if (it > 0 || !first_residual_read) {  // else the caller has read the first residual's norms into om
-      HIP_TRY(launch_residual(h, h.diagx, h.diags, sol, rhs, h.kres, h.omega_d, st));
+      HIP_TRY(launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st));
       HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(wait_stream(st));
     }
     const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];  // ||res||_inf / ||rhs||_inf
-    if (!(relr < best_rel)) {  // no further improvement: restore the best iterate
-      if (have_best) HIP_TRY(hipMemcpyAsync(sol, h.kcor, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
-      break;
-    }
+    if (!(relr < best_rel)) break;  // no further improvement: keep the best iterate
     best_rel = relr;
+    xb = xn;
     h.last_omega = fmax(om[0], om[1]);  // componentwise backward error of the kept iterate
     if (relr <= 1e-10 || it == 10) break;  // relative residual target of the refinement
-    HIP_TRY(hipMemcpyAsync(h.kcor, sol, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
-    have_best = true;
     HIP_TRY(launch_solve(h, h.kres, st));
     HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st));  // correction in place
-    HIP_TRY(launch_axpy(sol, h.kres, 1.0, h.nkkt, st));
+    xn = xb == sol ? h.kcor : sol;
+    HIP_TRY(launch_axpy(xn, xb, h.kres, 1.0, h.nkkt, st));  // xn = xb + correction
   }
+  if (xb != sol) HIP_TRY(hipMemcpyAsync(sol, xb, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
   if (rel) *rel = best_rel;
   return ABS_OK;
 }

@@ -202,9 +202,10 @@ __global__ void k_hess_dd(const double* __restrict__ lam, ModelParams p, long lo
   if (threadIdx.x == 0) *out = sm[0];
 }
 
-__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, long long n) {
+// z = y + a x (z may be y)
+__global__ void k_axpy(double* z, const double* y, const double* __restrict__ x, double a, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] += a * x[i];
+  if (i < n) z[i] = y[i] + a * x[i];
 }
 
 // Residual of the bordered KKT system, res = rhs - K sol, and the componentwise
@@ -541,8 +542,8 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   return hipGetLastError();
 }
 
-hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n, 256)), dim3(256), 0, st, y, x, a, n);
+hipError_t launch_axpy(double* z, const double* y, const double* x, double a, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n, 256)), dim3(256), 0, st, z, y, x, a, n);
   return hipGetLastError();
 }
 
