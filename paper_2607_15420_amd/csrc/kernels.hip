@@ -84,7 +84,7 @@ __device__ __forceinline__ void load_inflow(const double* __restrict__ x, const 
 
 // One thread per stage: residuals (scaled by cs) and, if full, the scaled stage
 // record: Jacobian blocks and the Lagrangian Hessian block.
-__global__ void k_eval(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ y,
+__global__ __launch_bounds__(256) void k_eval(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ y,
                        const double* __restrict__ cs, const double* __restrict__ feeds, ModelParams p,
                        const StageInfo* __restrict__ sinfo, long long nst, const int* __restrict__ pact, int full,
                        double* __restrict__ cout, double* __restrict__ rec) {
@@ -129,7 +129,7 @@ __global__ void k_eval(const double* __restrict__ x, Scaling sc, int scaled, con
 }
 
 // maximum |d c~_r / d xt| over the whole row (for gradient-based row scaling)
-__global__ void k_rowmax(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ feeds,
+__global__ __launch_bounds__(128) void k_rowmax(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ feeds,
                          ModelParams p, const StageInfo* __restrict__ sinfo, long long nst,
                          double* __restrict__ rowmax) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,7 +153,7 @@ __global__ void k_rowmax(const double* __restrict__ x, Scaling sc, int scaled, c
 }
 
 // unscaled Jacobian values in the compact structure order of the public ABI
-__global__ void k_jac_coo(const double* __restrict__ x, const double* __restrict__ feeds, ModelParams p, int N,
+__global__ __launch_bounds__(128) void k_jac_coo(const double* __restrict__ x, const double* __restrict__ feeds, ModelParams p, int N,
                           int S, double* __restrict__ vals) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)N * S) return;
@@ -172,7 +172,7 @@ __global__ void k_jac_coo(const double* __restrict__ x, const double* __restrict
 }
 
 // unscaled Lagrangian Hessian block values (48 per stage) of the public ABI
-__global__ void k_hess_coo(const double* __restrict__ x, const double* __restrict__ lam,
+__global__ __launch_bounds__(128) void k_hess_coo(const double* __restrict__ x, const double* __restrict__ lam,
                            const double* __restrict__ feeds, ModelParams p, int N, int S, double* __restrict__ vals) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)N * S) return;
