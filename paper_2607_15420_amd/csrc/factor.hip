@@ -25,9 +25,10 @@ inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) /
 // coupling unknowns of stage n+1, 59 the right-hand side r, 60 the border b
 // (both carried as symmetric extra rows and columns).  Eliminating the 43 own
 // pivots leaves in rows/cols 43-60 the contribution to stage n+1's block and
-// right-hand sides.  The pivot loop uses no LDS: column entries reach every
-// lane through v_readlane (uniform operands), the pivot row is selected by a
-// uniform switch, and the diagonal is kept up to date per lane.
+// right-hand sides.  The candidate pivot row is selected by a uniform switch
+// over the registers (by symmetry it is the candidate column), single entries
+// reach every lane through v_readlane, and the pivot column of each rank-1
+// update is broadcast through LDS (every lane reads the same address).
 constexpr int TAIL = SLOT - NK;  // rows 43-63 of a stored pivot column: coupling, r, b, code, d, 1/d
 constexpr int STG = TAIL + 1;     // LDS stride of one staged tail
 struct WaveLDS {
