@@ -290,12 +290,13 @@ static void free_handle(Handle& h) {
   void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
-                  h.seg, h.pseg, h.ctl};
+                  h.seg, h.pseg, h.ctl, h.ipm_work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);
   if (h.redbuf_h) (void)hipHostFree(h.redbuf_h);
   if (h.ctl_h) (void)hipHostFree(h.ctl_h);
+  if (h.ipm_dd_h) (void)hipHostFree(h.ipm_dd_h);
 }
 
 // (re)allocate the scaled row-scale vector as ones

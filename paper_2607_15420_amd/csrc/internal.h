@@ -171,6 +171,12 @@ struct Handle {
   double* warm_x0 = nullptr;
   double* warm_l0 = nullptr;
   int* warm_w = nullptr;
+  // work vectors of the interior-point solve: one device allocation made on the
+  // handle's first solve and kept (cleared at the start of every solve), and a
+  // pinned [P] array for reading the d entries
+  double* ipm_work = nullptr;
+  size_t ipm_work_bytes = 0;
+  double* ipm_dd_h = nullptr;
   long long n_factor = 0, n_solve = 0;       // launch counters
   // optional per-class kernel timing: event pairs recorded on the launch stream
   // and read back only when the profile is fetched (or the pending list is full)

@@ -625,23 +625,6 @@ struct Work {
   double* dc_h = nullptr;  // pinned [P]
   int* fm_h = nullptr;     // pinned [P]
   double* dd_h = nullptr;  // pinned [P]: the d entries of a primal vector
-  std::vector<void*> all, pinned;
-  ~Work() {
-    for (void* p : all) (void)hipFree(p);
-    for (void* p : pinned) (void)hipHostFree(p);
-  }
-  template <class T>
-  hipError_t alloc(T** p, long long n) {
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)std::max<long long>(n, 1));
-    if (e == hipSuccess) all.push_back((void*)*p);
-    return e;
-  }
-  template <class T>
-  hipError_t host(T** p, long long n) {
-    hipError_t e = hipHostMalloc((void**)p, sizeof(T) * (size_t)std::max<long long>(n, 1), 0);
-    if (e == hipSuccess) pinned.push_back((void*)*p);
-    return e;
-  }
 };
 
 struct Filter {
@@ -736,14 +719,28 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     return ABS_ERR_ARG;
   }
   Work W;
-  double** bufs_nx[] = {&W.xt, &W.xtt, &W.zL, &W.zU, &W.g, &W.dx, &W.dzL, &W.dzU};
-  for (double** p : bufs_nx) HIP_TRY(W.alloc(p, nx));
-  double** bufs_nc[] = {&W.y, &W.c, &W.ct, &W.dy, &W.rowmax};
-  for (double** p : bufs_nc) HIP_TRY(W.alloc(p, nc));
-  double** bufs_ns[] = {&W.s, &W.st, &W.vU, &W.ds, &W.dvU, &W.dpart};
-  for (double** p : bufs_ns) HIP_TRY(W.alloc(p, nst));
-  HIP_TRY(W.alloc(&W.rhs, nkkt));
-  HIP_TRY(W.alloc(&W.sol, nkkt));
+  {
+    // the work vectors, carved from one device allocation kept by the handle
+    double** bufs[] = {&W.xt, &W.xtt, &W.zL, &W.zU, &W.g, &W.dx, &W.dzL, &W.dzU,  // nx
+                       &W.y, &W.c, &W.ct, &W.dy, &W.rowmax,                       // nc
+                       &W.s, &W.st, &W.vU, &W.ds, &W.dvU, &W.dpart,               // nst
+                       &W.rhs, &W.sol};                                           // nkkt
+    const long long len[] = {nx, nx, nx, nx, nx, nx, nx, nx, nc, nc, nc, nc, nc,
+                             nst, nst, nst, nst, nst, nst, nkkt, nkkt};
+    static_assert(sizeof(bufs) / sizeof(bufs[0]) == sizeof(len) / sizeof(len[0]), "one length per buffer");
+    size_t off[sizeof(len) / sizeof(len[0])], total = 0;
+    for (size_t i = 0; i < sizeof(len) / sizeof(len[0]); ++i) {
+      off[i] = total;
+      total += ((size_t)std::max<long long>(len[i], 1) + 31) / 32 * 32;  // 256-byte aligned pieces
+    }
+    if (!h.ipm_work) {
+      HIP_TRY(hipMalloc((void**)&h.ipm_work, total * sizeof(double)));
+      h.ipm_work_bytes = total * sizeof(double);
+    }
+    if (!h.ipm_dd_h) HIP_TRY(hipHostMalloc((void**)&h.ipm_dd_h, sizeof(double) * (size_t)P, 0));
+    HIP_TRY(hipMemsetAsync(h.ipm_work, 0, h.ipm_work_bytes, st));
+    for (size_t i = 0; i < sizeof(len) / sizeof(len[0]); ++i) *bufs[i] = h.ipm_work + off[i];
+  }
   // per-problem scalars live in the handle's control block (one transfer for all of them)
   static_assert(sizeof(PS) <= CTL_SLOT, "solver scalars exceed the control block slot");
   W.ps = reinterpret_cast<PS*>(h.slot_area);
@@ -752,7 +749,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   W.dc_h = W.dw_h + P;
   W.fm_h = reinterpret_cast<int*>(h.ctl_h + ctl_off_fmask(P));
   int* pa_h = reinterpret_cast<int*>(h.ctl_h + ctl_off_pact(P));
-  HIP_TRY(W.host(&W.dd_h, P));
+  W.dd_h = h.ipm_dd_h;
   std::vector<Prob> pr((size_t)P);
   // scalars, activity, regularisation and the refactorisation mask of every
   // problem -> device, in one transfer
