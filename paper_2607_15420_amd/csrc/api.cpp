@@ -220,12 +220,7 @@ static int build_tables(Handle& h) {
 }
 
 int initial_point(Handle& h, double* x_dev, hipStream_t st) {
-  std::vector<double> x0((size_t)h.nx);
-  for (long long t = 0; t < h.nst; ++t)
-    for (int k = 0; k < NV; ++k) x0[t * NV + k] = h.x0[k];
-  for (int p = 0; p < h.P; ++p) x0[h.nst * NV + p] = h.x0[NV];
-  HIP_TRY(hipMemcpyAsync(x_dev, x0.data(), sizeof(double) * h.nx, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(launch_tile_x0(h, x_dev, st));
   return ABS_OK;
 }
 

@@ -260,6 +260,8 @@ hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int m
 // componentwise backward error over the scenario rows, omega_out[1] over the d rows
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
                            const double* rhs, double* res, double* omega_out, hipStream_t st);
+// x <- the cold-start point (h.x0 in every stage, its diameter for every problem)
+hipError_t launch_tile_x0(Handle& h, double* x, hipStream_t st);
 // z = y + a x (z may be y)
 hipError_t launch_axpy(double* z, const double* y, const double* x, double a, long long n, hipStream_t st);
 // time the launch-shape candidates on the current data and keep the fastest (h.tune); x, y, c as for

@@ -202,6 +202,16 @@ __global__ void k_hess_dd(const double* __restrict__ lam, ModelParams p, long lo
   if (threadIdx.x == 0) *out = sm[0];
 }
 
+// the cold-start point: x0's stage vector in every stage, its diameter for every problem
+struct TileX0 {
+  double v[NV + 1];
+};
+__global__ void k_tile_x0(TileX0 x0, long long nst, int P, double* __restrict__ x) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nst * NV) x[i] = x0.v[i % NV];
+  else if (i < nst * NV + P) x[i] = x0.v[NV];
+}
+
 // z = y + a x (z may be y)
 __global__ void k_axpy(double* z, const double* y, const double* __restrict__ x, double a, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -539,6 +549,13 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   prof_end(h, 3, st);
   hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pseg, h.scal, sol, rhs, nks, pa, res, omd);
   hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(MAX_BS), 0, st, omb, nb, omd, h.P, omega_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_x0(Handle& h, double* x, hipStream_t st) {
+  TileX0 a;
+  for (int k = 0; k <= NV; ++k) a.v[k] = h.x0[k];
+  hipLaunchKernelGGL(k_tile_x0, dim3(grid_for(h.nx, 256)), dim3(256), 0, st, a, h.nst, h.P, x);
   return hipGetLastError();
 }
 
