@@ -37,11 +37,14 @@ def _random_states(S, N, seed):
     return Z, float(rng.uniform(0.3, 2.0))
 
 
-@pytest.fixture(scope="module")
-def small(params):
+# (stages, scenarios, feed table): 4 x 3 (two segments of 11 stages, the second
+# ragged), and 10 x 23 (23 chains, 21 segments with a ragged last one, several
+# evaluation blocks with a ragged tail)
+@pytest.fixture(scope="module", params=[(4, 3, "C1"), (10, 23, "C2")], ids=["4x3", "10x23"])
+def small(params, request):
     from paper_2607_15420_amd import Absorber
-    N, S = 4, 3
-    feeds = CONFIGS["C1"].feeds(params)[:S]
+    N, S, cfg = request.param
+    feeds = CONFIGS[cfg].feeds(params)[:S]
     h = Absorber(params, N, feeds)
     Z, d = _random_states(S, N, 11)
     x = np.concatenate([Z.reshape(-1), [d]])
