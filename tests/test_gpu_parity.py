@@ -215,3 +215,50 @@ def test_profile_counts_timed_launches(small):
     p = h.profile()
     assert p["factor"]["calls"] == 1 and p["solve"]["calls"] == 0
     h.profile_enable(False)
+
+
+def test_kkt_full_size_inertia_and_sampled_rows(params):
+    """The benchmarked size (10 stages x 5000 scenarios, random states, variables
+    scaled by magnitude).  With zero multipliers the Lagrangian Hessian vanishes,
+    so the (1,1) block is Sigma_x + delta_w > 0 and the dual block is negative
+    definite (-delta_c, slack terms): by Sylvester's law the inertia is exactly
+    (nx, nc, 0).  The rows of sampled scenarios, rebuilt by the oracle from its
+    own Jacobian, hold at the returned solution to the relative residual the
+    device reports (its maximum over all rows bounds theirs).  Random states are
+    not an interior-point iterate, so the refinement may stop above its 1e-10
+    target; it must still stay well below 1e-6."""
+    from paper_2607_15420_amd import Absorber
+    w = CONFIGS["C3"]
+    N, feeds = w.n_stages, w.feeds(params)
+    S = feeds.shape[0]
+    h = Absorber(params, N, feeds)
+    Z, d = _random_states(S, N, 23)
+    x = np.concatenate([Z.reshape(-1), [d]])
+    D = np.r_[np.abs(Z[0, 0]) + 0.1, 1.0]
+    h.set_scaling(D, None)
+    rng = np.random.default_rng(29)
+    lam = np.zeros(S * N * M.NR)
+    sig_x = rng.uniform(0.1, 10.0, h.nx)
+    sig_s = rng.uniform(0.5, 5.0, S * N)
+    dw, dc = 1e-4, 1e-8
+    inert = h.kkt_factor(_t(x), _t(lam), _t(sig_x), _t(sig_s), dw, dc)
+    assert inert == (h.nx, h.nc, 0)
+    rhs = rng.normal(size=h.nkkt)
+    sol = torch.empty(h.nkkt, dtype=torch.float64, device=DEV)
+    rel = h.kkt_solve(_t(rhs), sol)
+    assert rel < 1e-6
+    gs, gd = _to_oracle_order(sol.cpu().numpy(), S, N)
+    rs, rd = _to_oracle_order(rhs, S, N)
+    P = M.OracleParams(params)
+    bs = np.r_[np.tile(D[:M.NV], N), D[M.NV]]
+    eps = np.finfo(float).eps
+    for s in sorted(rng.choice(S, 5, replace=False).tolist()):
+        J = M.jacobian(Z[s], d, feeds[s], P) * bs[None, :]
+        H = np.zeros((N * M.NV + 1, N * M.NV + 1))
+        K, b, _ = scenario_kkt(J, H, sig_x[s * N * M.NV:(s + 1) * N * M.NV], sig_s[s * N:(s + 1) * N], dw, dc, N)
+        res = rs[s] - K @ gs[s] - b * gd
+        mag = np.abs(K) @ np.abs(gs[s]) + np.abs(b) * abs(gd)
+        bound = 1.01 * rel * np.abs(rhs).max() + 64 * eps * mag.max()
+        assert np.abs(res).max() <= bound, (s, np.abs(res).max(), bound)
+    h.set_scaling(None, None)
+    h.close()
