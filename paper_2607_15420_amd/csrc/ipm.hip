@@ -75,19 +75,25 @@ __device__ __forceinline__ double red_op(int op, double a, double b) {
   return op == 0 ? a + b : (op == 1 ? fmax(a, b) : fmin(a, b));
 }
 
-// block reduction of K values; per-block partials out[blockIdx.x * K + k]
+// block reduction of K values in a fixed order (a shuffle tree inside each
+// wave, then across the BS / 64 waves); per-block partials out[blockIdx.x * K + k]
 template <int K>
 __device__ void block_reduce(Part<K> p, const Ops<K>& ops, double* out) {
-  __shared__ double sm[K][BS];
-  for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = p.v[k];
+  __shared__ double sm[K][BS / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) p.v[k] = red_op(ops.op[k], p.v[k], __shfl_down(p.v[k], off, 64));
+  if (lane == 0)
+    for (int k = 0; k < K; ++k) sm[k][wv] = p.v[k];
   __syncthreads();
-  for (int s = BS / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int k = 0; k < K; ++k) sm[k][threadIdx.x] = red_op(ops.op[k], sm[k][threadIdx.x], sm[k][threadIdx.x + s]);
-    __syncthreads();
-  }
   if (threadIdx.x == 0)
-    for (int k = 0; k < K; ++k) out[blockIdx.x * K + k] = sm[k][0];
+    for (int k = 0; k < K; ++k) {
+      double a = sm[k][0];
+      for (int i = 1; i < BS / 64; ++i) a = red_op(ops.op[k], a, sm[k][i]);
+      out[blockIdx.x * K + k] = a;
+    }
 }
 
 // per-problem reduction of segment partials: one block of RS threads per
