@@ -285,13 +285,15 @@ static void free_handle(Handle& h) {
   void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
-                  h.seg, h.pseg, h.ctl, h.ipm_work};
+                  h.seg, h.pseg, h.ctl, h.ipm_work, h.pres, h.rmask};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);
   if (h.redbuf_h) (void)hipHostFree(h.redbuf_h);
   if (h.ctl_h) (void)hipHostFree(h.ctl_h);
   if (h.ipm_dd_h) (void)hipHostFree(h.ipm_dd_h);
+  if (h.pres_h) (void)hipHostFree(h.pres_h);
+  if (h.rmask_h) (void)hipHostFree(h.rmask_h);
 }
 
 // (re)allocate the scaled row-scale vector as ones
@@ -461,6 +463,8 @@ int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const 
   h.pact = reinterpret_cast<int*>(h.ctl + ctl_off_pact(h.P));
   h.slot_area = h.ctl + ctl_off_slot(h.P);
   ALLOC(h.omega_d, 8);
+  ALLOC(h.pres, 2LL * h.P);
+  ALLOC(h.rmask, h.P);
   ALLOC(h.diagx, h.nx);
   ALLOC(h.diags, nst);
   ALLOC(h.kres, h.nkkt);
@@ -473,7 +477,9 @@ int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const 
 #undef ALLOC
   if (hipHostMalloc((void**)&h.scal_h, sizeof(DevScalars) * h.P, 0) != hipSuccess ||
       hipHostMalloc((void**)&h.redbuf_h, sizeof(double) * h.red_cap, 0) != hipSuccess ||
-      hipHostMalloc((void**)&h.ctl_h, h.ctl_bytes, 0) != hipSuccess) {
+      hipHostMalloc((void**)&h.ctl_h, h.ctl_bytes, 0) != hipSuccess ||
+      hipHostMalloc((void**)&h.pres_h, sizeof(double) * 2 * h.P, 0) != hipSuccess ||
+      hipHostMalloc((void**)&h.rmask_h, sizeof(int) * h.P, 0) != hipSuccess) {
     set_error("absorber_create: pinned host allocation failed");
     return fail(ABS_ERR_OOM);
   }

@@ -126,6 +126,12 @@ struct Handle {
   int* pact = nullptr;                       // device [P] problems the per-stage kernels work on
   char* slot_area = nullptr;                 // device [P][CTL_SLOT] the solver's per-problem scalars
   bool pact_on = false;                      // false: every problem
+  // batched refinement: per-problem max |res| and max |rhs| of the last residual,
+  // and the problems a correction is computed for (the others are converged)
+  double* pres = nullptr;                    // device [2P]
+  double* pres_h = nullptr;                  // pinned [2P]
+  int* rmask = nullptr;                      // device [P]
+  int* rmask_h = nullptr;                    // pinned [P]
   ModelParams mp{};
   double xL[NV], xU[NV], dL = 0, dU = 0;     // unscaled bounds per local variable
   std::vector<double> feeds_h;
@@ -260,6 +266,11 @@ hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int m
 // componentwise backward error over the scenario rows, omega_out[1] over the d rows
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
                            const double* rhs, double* res, double* omega_out, hipStream_t st);
+// per problem p: pres[2p] = max |res_i|, pres[2p + 1] = max |rhs_i| over its
+// rows (stage rows and its d row) from the partials of the last launch_residual
+hipError_t launch_residual_pmax(Handle& h, hipStream_t st);
+// res_i = 0 on the rows of the problems whose mask entry is 0
+hipError_t launch_mask_rows(Handle& h, const int* mask, double* res, hipStream_t st);
 // x <- the cold-start point (h.x0 in every stage, its diameter for every problem)
 hipError_t launch_tile_x0(Handle& h, double* x, hipStream_t st);
 // z = y + a x (z may be y)

@@ -685,6 +685,11 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
   // Corrections are applied out of place, alternating between sol and h.kcor,
   // so the best iterate is kept without copying it: xb is the best so far, xn
   // the iterate whose residual is evaluated next.
+  // With several problems, a correction is computed only for the problems whose
+  // own relative residual is above the target (the others keep their iterate:
+  // their rows of the residual are cleared and their chains skipped).
+  constexpr double target = 1e-10;  // relative residual target of the refinement
+  const bool per_problem = h.P > 1;
   double best_rel = INFINITY;
   double* xb = sol;
   double* xn = sol;
@@ -693,6 +698,11 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     if (it > 0 || !first_residual_read) {  // else the caller has read the first residual's norms into om
       HIP_TRY(launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st));
       HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+      if (!per_problem) HIP_TRY(wait_stream(st));
+    }
+    if (per_problem) {  // per-problem maxima of the same residual
+      HIP_TRY(launch_residual_pmax(h, st));
+      HIP_TRY(hipMemcpyAsync(h.pres_h, h.pres, sizeof(double) * 2 * h.P, hipMemcpyDeviceToHost, st));
       HIP_TRY(wait_stream(st));
     }
     const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];  // ||res||_inf / ||rhs||_inf
@@ -700,8 +710,25 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     best_rel = relr;
     xb = xn;
     h.last_omega = fmax(om[0], om[1]);  // componentwise backward error of the kept iterate
-    if (relr <= 1e-10 || it == 10) break;  // relative residual target of the refinement
-    HIP_TRY(launch_solve(h, h.kres, st));
+    if (relr <= target || it == 10) break;
+    if (per_problem) {
+      for (int p = 0; p < h.P; ++p) {
+        const double r = h.pres_h[2 * p], b = h.pres_h[2 * p + 1];
+        h.rmask_h[p] = (b > 0.0 ? r / b : r) > target || !std::isfinite(r) ? 1 : 0;
+      }
+      HIP_TRY(hipMemcpyAsync(h.rmask, h.rmask_h, sizeof(int) * h.P, hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_mask_rows(h, h.rmask, h.kres, st));
+      int* const pact = h.pact;
+      const bool pact_on = h.pact_on;
+      h.pact = h.rmask;
+      h.pact_on = true;
+      const hipError_t e = launch_solve(h, h.kres, st);
+      h.pact = pact;
+      h.pact_on = pact_on;
+      HIP_TRY(e);
+    } else {
+      HIP_TRY(launch_solve(h, h.kres, st));
+    }
     HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st));  // correction in place
     xn = xb == sol ? h.kcor : sol;
     HIP_TRY(launch_axpy(xn, xb, h.kres, 1.0, h.nkkt, st));  // xn = xb + correction

@@ -438,6 +438,46 @@ __global__ __launch_bounds__(MAX_BS) void k_residual_max(const double* __restric
   }
 }
 
+// per problem (one block each): the largest |res_i| and |rhs_i| over its
+// segments' partials and its d row
+__global__ __launch_bounds__(256) void k_residual_pmax(const double* __restrict__ omb, const int* __restrict__ pseg,
+                                                       const double* __restrict__ omd, double* __restrict__ out) {
+  __shared__ double sm[2][4];
+  const int p = blockIdx.x;
+  double r = 0.0, q = 0.0;
+  for (int g = pseg[p] + (int)threadIdx.x; g < pseg[p + 1]; g += 256) {
+    r = fmax(r, omb[3LL * g + 1]);
+    q = fmax(q, omb[3LL * g + 2]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    r = fmax(r, __shfl_down(r, off, 64));
+    q = fmax(q, __shfl_down(q, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sm[0][threadIdx.x >> 6] = r;
+    sm[1][threadIdx.x >> 6] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    r = fmax(omd[3 * p + 1], fmax(fmax(sm[0][0], sm[0][1]), fmax(sm[0][2], sm[0][3])));
+    q = fmax(omd[3 * p + 2], fmax(fmax(sm[1][0], sm[1][1]), fmax(sm[1][2], sm[1][3])));
+    out[2 * p] = r;
+    out[2 * p + 1] = q;
+  }
+}
+
+// res_i = 0 on the stage rows and the d row of the problems with mask 0
+__global__ void k_mask_rows(const int* __restrict__ mask, const StageInfo* __restrict__ sinfo, long long nks, int P,
+                            double* __restrict__ res) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nks) {
+    if (!mask[sinfo[i / NK].p]) res[i] = 0.0;
+  } else if (i < nks + P) {
+    if (!mask[i - nks]) res[i] = 0.0;
+  }
+}
+
 inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -549,6 +589,20 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   prof_end(h, 3, st);
   hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pseg, h.scal, sol, rhs, nks, pa, res, omd);
   hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(MAX_BS), 0, st, omb, nb, omd, h.P, omega_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_pmax(Handle& h, hipStream_t st) {
+  const int nb = h.nseg;
+  const double* omb = h.kden + 2LL * nb;
+  const double* omd = omb + 3LL * nb;
+  hipLaunchKernelGGL(k_residual_pmax, dim3(h.P), dim3(256), 0, st, omb, h.pseg, omd, h.pres);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_rows(Handle& h, const int* mask, double* res, hipStream_t st) {
+  const long long nks = h.nst * NK;
+  hipLaunchKernelGGL(k_mask_rows, dim3(grid_for(nks + h.P, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, res);
   return hipGetLastError();
 }
 
