@@ -260,8 +260,12 @@ void prof_end(Handle& h, int cls, hipStream_t st) {
 }
 
 int prof_flush(Handle& h) {
-  for (const auto& q : h.prof_pending) {
-    HIP_TRY(hipEventSynchronize(q.e1));  // returns at once for an event already reached
+  size_t done = 0;
+  hipError_t err = hipSuccess;
+  for (; done < h.prof_pending.size(); ++done) {
+    const auto& q = h.prof_pending[done];
+    err = hipEventSynchronize(q.e1);  // returns at once for an event already reached
+    if (err != hipSuccess) break;
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, q.e0, q.e1) == hipSuccess) {
       h.prof_ms[q.cls] += ms;
@@ -270,7 +274,9 @@ int prof_flush(Handle& h) {
     h.prof_pool.push_back(q.e0);
     h.prof_pool.push_back(q.e1);
   }
-  h.prof_pending.clear();
+  // each event is either still pending or back in the pool, never both
+  h.prof_pending.erase(h.prof_pending.begin(), h.prof_pending.begin() + (long)done);
+  HIP_TRY(err);
   return ABS_OK;
 }
 
