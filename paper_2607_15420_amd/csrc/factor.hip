@@ -290,8 +290,14 @@ __device__ __forceinline__ void backward_stage(const double* __restrict__ sb, do
     zr = fma(-c, xcr[coupling_index(a)], zr);
     if (two) zb = fma(-c, xcb[coupling_index(a)], zb);
   }
-  xr_s = 0.0;
-  xb_s = 0.0;
+  // Slot s's entries at its own row and at the rows eliminated before it were
+  // not loaded (reg = 0), so a lane's z stops changing once its own slot has been
+  // solved: a 1x1 slot's solution is its final z times 1/d, formed for every lane
+  // after the loop.  Pivot types are wave masks, tested on the scalar unit.
+  const int type_l = lane < NK ? (((int)code_l) >> 6) : 1;  // 0 zero pivot, 1 1x1, 2/3 first/second of 2x2
+  const uint64_t m_second = __ballot(lane < NK && type_l == 3);
+  const uint64_t m_zero = __ballot(lane < NK && type_l == 0);
+  double pr = 0.0, pb = 0.0;  // solutions of the 2x2 pairs
   bool skip = false;
 #pragma unroll
   for (int s = NK - 1; s >= 0; --s) {
@@ -299,39 +305,36 @@ __device__ __forceinline__ void backward_stage(const double* __restrict__ sb, do
       skip = false;
       continue;
     }
-    const int code = (int)rdl(code_l, s);
-    const int type = code >> 6;
-    if (s > 0 && type == 3) {
-      constexpr int dummy = 0;
-      (void)dummy;
+    if (s > 0 && ((m_second >> s) & 1ull)) {
       const int s0 = s > 0 ? s - 1 : 0;
       const double e11 = rdl(a_l, s0), e12 = rdl(b_l, s0), e22 = rdl(a_l, s);
       const double idet = 1.0 / (e11 * e22 - e12 * e12);
       const double zk = rdl(zr, s0), zq = rdl(zr, s);
       const double xk = (e22 * zk - e12 * zq) * idet, xq = (e11 * zq - e12 * zk) * idet;
       zr = fma(-reg[s0], xk, fma(-reg[s], xq, zr));
-      if (lane == s0) xr_s = xk;
-      if (lane == s) xr_s = xq;
+      if (lane == s0) pr = xk;
+      if (lane == s) pr = xq;
       if (two) {
         const double wk = rdl(zb, s0), wq = rdl(zb, s);
         const double yk = (e22 * wk - e12 * wq) * idet, yq = (e11 * wq - e12 * wk) * idet;
         zb = fma(-reg[s0], yk, fma(-reg[s], yq, zb));
-        if (lane == s0) xb_s = yk;
-        if (lane == s) xb_s = yq;
+        if (lane == s0) pb = yk;
+        if (lane == s) pb = yq;
       }
       skip = true;
     } else {
-      const double dinv = rdl(b_l, s);
-      const double x = type ? rdl(zr, s) * dinv : 0.0;
+      const bool zero = (m_zero >> s) & 1ull;
+      const double x = zero ? 0.0 : rdl(zr * b_l, s);  // lane s: z_s / d_s
       zr = fma(-reg[s], x, zr);
-      if (lane == s) xr_s = x;
       if (two) {
-        const double y = type ? rdl(zb, s) * dinv : 0.0;
+        const double y = zero ? 0.0 : rdl(zb * b_l, s);
         zb = fma(-reg[s], y, zb);
-        if (lane == s) xb_s = y;
       }
     }
   }
+  const bool pair = type_l >= 2;
+  xr_s = pair ? pr : (type_l == 0 ? 0.0 : zr * b_l);
+  xb_s = pair ? pb : (type_l == 0 ? 0.0 : zb * b_l);
 }
 
 // Sum over the wave of a double, fixed order (DPP row shifts and row
