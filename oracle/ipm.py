@@ -163,10 +163,13 @@ class Problem:
 
 
 class OracleIPM:
-    def __init__(self, prob: Problem, opts: IpmOptions | None = None, verbose: bool = False):
+    def __init__(self, prob: Problem, opts: IpmOptions | None = None, verbose: bool = False, on_factor=None):
         self.pr = prob
         self.o = opts or IpmOptions()
         self.verbose = verbose
+        # optional observer called as on_factor(F, dw, dc) after every factorisation
+        # of the inertia-correction loop (A-4), for tests that check each trial
+        self.on_factor = on_factor
         pr = prob
         self.hasL = np.isfinite(pr.xL)
         self.hasU = np.isfinite(pr.xU)
@@ -440,8 +443,12 @@ class OracleIPM:
             rdd = dI - s
             dw, dc = 0.0, 0.0
             ncorr = 0
+            dw_trials = []
             while True:
                 F = self.factor(x, yc, yd, sig_x, sig_s, dw, dc, Jb)
+                dw_trials.append(dw)
+                if self.on_factor is not None:
+                    self.on_factor(F, dw, dc)
                 want = (pr.n, pr.mE + pr.mI, 0)
                 if F.inertia == want:
                     if dw > 0:
@@ -534,7 +541,7 @@ class OracleIPM:
             Jb = self.jac_scaled(x)
             it += 1
             rec = dict(it=it, mu=mu, theta=th, phi=phi, alpha=alpha, alpha_z=alpha_z, ls=nls,
-                       dw=dw, d=float(self.D[-1] * x[-1]), E0=E0)
+                       dw=dw, dc=dc, dw_trials=dw_trials, d=float(self.D[-1] * x[-1]), E0=E0)
             log.append(rec)
             if self.verbose:
                 print(f"it {it:4d} mu {mu:9.2e} th {th:9.2e} a {alpha:9.2e} az {alpha_z:9.2e} "
@@ -547,7 +554,7 @@ class OracleIPM:
                          time.perf_counter() - t0, log, self.n_inertia_corr, self.max_lin_resid)
 
 
-def solve(params, feeds, n_stages, opts=None, verbose=False, x0=None, yc0=None, yd0=None):
+def solve(params, feeds, n_stages, opts=None, verbose=False, x0=None, yc0=None, yd0=None, on_factor=None):
     torch.set_num_threads(1)
     prob = Problem(params, feeds, n_stages)
-    return OracleIPM(prob, opts, verbose).solve(x0, yc0, yd0)
+    return OracleIPM(prob, opts, verbose, on_factor).solve(x0, yc0, yd0)
