@@ -152,6 +152,7 @@ def warm_leg(params, steps: int, epochs: int):
                     f"{TRAIN_SET.n_scen} single-scenario solutions (seed {TRAIN_SET.seed}) from one batched solve",
         "cold_s": cold_s, "warm_s": warm_s, "speedup": cold_s / warm_s,
         "cold_iterations": rc.iterations, "warm_iterations": rw.iterations, "warm_used": used,
+        "warm_feasibility_restarts": rw.feasibility_restarts,
         "cold_converged": rc.status == 0 and rc.E0 <= 1e-8, "warm_converged": rw.status == 0 and rw.E0 <= 1e-8,
         "warm_E0": rw.E0, "d_cold": rc.d, "d_warm": rw.d,
         "datagen_s": t_data, "datagen_converged": int(n_ok), "datagen_max_iterations": int(max(r.iterations for r in res_tr)),
@@ -187,6 +188,9 @@ def batch_leg(params, n_problems: int, sequential: bool):
         "batched_restarted": int(sum(r.feasibility_restarts for r in res)),
         "batched_solves_per_s": len(probs) / t_batch,
         "max_iterations": int(max(r.iterations for r in res)),
+        "max_lin_resid": float(max(r.max_lin_resid for r in res)),
+        "lin_resid_le_1e-10": int(sum(r.max_lin_resid <= 1e-10 for r in res)),
+        "lin_resid_per_problem": [float(r.max_lin_resid) for r in res],
     }
     print(f"bench: batch of {len(probs)} solved in {t_batch:.2f} s", file=sys.stderr, flush=True)
     if sequential:

@@ -123,7 +123,10 @@ int absorber_hess_structure(const absorber_t* h, int64_t* rows_host, int64_t* co
 int absorber_eval_hess(absorber_t* h, const double* x_dev, const double* lambda_dev, double obj_factor,
                        double* vals_dev, void* stream);
 
-/* Factorise the slack-reduced primal-dual KKT matrix in the scaled variables
+/* Factorise the slack-reduced primal-dual KKT matrix (the Newton system of
+ * the interior-point solver of the numerical results, assembled and
+ * factorised on the GPU; its scenario blocks are coupled only through d, the
+ * structure the conclusion proposes to exploit) in the scaled variables
  *   [[W~ + diag(sigma_x) + dw I,  J~^T                                  ],
  *    [J~,                         -diag(dc (MESH rows), 1/(sigma_s+dw)+dc)]]
  * where J~ = diag(cs) J D and W~ = D (sum_j lambda_j cs_j grad^2 c_j) D at x
@@ -138,10 +141,17 @@ int absorber_kkt_factor(absorber_t* h, const double* x_dev, const double* lambda
                         const double* sigma_x_dev, const double* sigma_s_dev, double delta_w,
                         double delta_c, int64_t* inertia_host, void* stream);
 
-/* Solve with the last factorisation: sol_dev[nkkt] = K^{-1} rhs_dev[nkkt],
- * iteratively refined on the whole bordered system until the componentwise
- * backward error stops improving (at most 10 rounds).  rel_resid_host gets
- * ||K sol - rhs||_inf / ||rhs||_inf.  Blocking. */
+/* Solve with the last factorisation: sol_dev[nkkt] = K^{-1} rhs_dev[nkkt]
+ * (the block LDL^T solves of every scenario, then the Schur complement step on
+ * d: Delta d = (r_d - sum_w b_w^T K_w^{-1} r_w) / S_d and
+ * Delta_w = K_w^{-1} (r_w - b_w Delta d)), iteratively refined on the whole
+ * bordered system until the relative residual ||rhs - K sol||_inf /
+ * ||rhs||_inf is <= 1e-10 or stops decreasing (at most 10 corrections; the
+ * best iterate is kept).  rel_resid_host gets that relative residual.  This is
+ * the GPU-resident solve of the interior-point Newton system the paper's
+ * numerical results time, in the scenario-block form its conclusion names as
+ * the structure to exploit.  ABS_ERR_STATE before any absorber_kkt_factor.
+ * Blocking. */
 int absorber_kkt_solve(absorber_t* h, const double* rhs_dev, double* sol_dev, double* rel_resid_host,
                        void* stream);
 
@@ -156,13 +166,15 @@ typedef struct {
   double warm_bound_push;   /* 1e-8 */
   double nlp_scaling_max_gradient; /* 100 */
   int32_t print_level;      /* 0 silent, 1 one line per iteration to stderr */
-  int32_t use_graph;        /* reserved */
+  int32_t use_graph;        /* reserved (0) */
   int32_t feasibility_restart; /* 1: a problem that stops without converging (line search, inertia,
                                   iteration limit) is solved again from its simulated states
                                   (absorber_simulate, d at 1.001 x its hydraulic minimum) with the
                                   warm-start options; 0: report the failure (default 1) */
   int32_t autotune;         /* 1: on the handle's first factorisation, time the launch-shape candidates
                                (absorber_tuning) on its own data and keep the fastest (default 1) */
+  double delta_w_max;       /* inertia correction: a problem whose delta_w would exceed this value stops
+                               with ABS_ERR_INERTIA (default 1e40) */
 } absorber_ipm_options;
 
 typedef struct {
@@ -174,11 +186,36 @@ typedef struct {
   double seconds;           /* wall time of the solve */
   int32_t n_inertia_corrections;
   int32_t n_factorizations;
-  double max_lin_resid;     /* largest relative linear residual of the KKT solves */
+  double max_lin_resid;     /* largest relative linear residual ||r - K x||_inf / ||r||_inf of this
+                               problem's own rows over its KKT solves */
   int32_t feasibility_restarts; /* 1 if the result comes from the feasibility restart */
 } absorber_ipm_result;
 
 void absorber_ipm_default_options(absorber_ipm_options* opts);
+
+/* One accepted interior-point iteration of one problem, as recorded by the
+ * last absorber_ipm_solve / absorber_batch_solve. */
+typedef struct {
+  int32_t iteration;        /* 1, 2, ... */
+  int32_t n_factorizations; /* factorisations of the inertia-correction loop in this iteration */
+  int32_t n_trials;         /* line-search trial points */
+  int32_t pad;
+  double mu;                /* barrier parameter of the iteration */
+  double theta;             /* constraint violation ||c||_1 (scaled rows) at the start of the iteration */
+  double alpha;             /* accepted primal step */
+  double alpha_z;           /* bound-multiplier step */
+  double delta_w;           /* primal regularisation of the accepted factorisation */
+  double delta_c;           /* dual regularisation of the accepted factorisation */
+  double d;                 /* diameter after the step */
+  double E0;                /* scaled optimality error at the start of the iteration */
+} absorber_ipm_log_entry;
+
+/* Copy the iteration log of problem `problem` from the last solve on the
+ * handle into out[0..max_entries) and the number of entries it holds into
+ * *n_out (which may exceed max_entries).  For a problem that went through the
+ * feasibility restart the log is that of the restarted run.  Blocking. */
+int absorber_ipm_log_get(const absorber_t* h, int32_t problem, int32_t max_entries, absorber_ipm_log_entry* out,
+                         int32_t* n_out);
 
 /* A batch of P independent problems in one handle (the batched form): problem
  * p has n_stages[p] stages and n_scen[p] scenarios; feeds_host holds the

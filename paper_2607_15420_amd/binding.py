@@ -62,7 +62,7 @@ class IpmOptions(ctypes.Structure):
         ("mu_init", ctypes.c_double), ("warm_mu_init", ctypes.c_double), ("bound_push", ctypes.c_double),
         ("warm_bound_push", ctypes.c_double), ("nlp_scaling_max_gradient", ctypes.c_double),
         ("print_level", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("feasibility_restart", ctypes.c_int32),
-        ("autotune", ctypes.c_int32),
+        ("autotune", ctypes.c_int32), ("delta_w_max", ctypes.c_double),
     ]
 
 
@@ -77,6 +77,18 @@ class IpmResult(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IpmLogEntry(ctypes.Structure):
+    _fields_ = [
+        ("iteration", ctypes.c_int32), ("n_factorizations", ctypes.c_int32), ("n_trials", ctypes.c_int32),
+        ("pad", ctypes.c_int32), ("mu", ctypes.c_double), ("theta", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("alpha_z", ctypes.c_double), ("delta_w", ctypes.c_double), ("delta_c", ctypes.c_double),
+        ("d", ctypes.c_double), ("E0", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
 class Profile(ctypes.Structure):
@@ -140,6 +152,8 @@ def lib():
             "absorber_ipm_default_options": (None, [ctypes.POINTER(IpmOptions)]),
             "absorber_ipm_solve": (ctypes.c_int, [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp,
                                                   ctypes.POINTER(IpmResult)]),
+            "absorber_ipm_log_get": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(IpmLogEntry),
+                                                    ctypes.POINTER(i32)]),
             "absorber_profile_enable": (ctypes.c_int, [vp, i32]),
             "absorber_profile_get": (ctypes.c_int, [vp, ctypes.POINTER(Profile)]),
             "absorber_tuning_get": (ctypes.c_int, [vp, ctypes.POINTER(Tuning)]),
@@ -344,6 +358,14 @@ class Absorber:
     def profile_enable(self, on=True, mask=0xF):
         """Time the kernel classes in mask (bit 0 factor, 1 solve, 2 eval, 3 residual)."""
         _check(lib().absorber_profile_enable(self.h, int(mask) if on else 0))
+
+    def ipm_log(self, problem: int = 0) -> list:
+        """Accepted iterations of problem `problem` in the last solve (list of dicts)."""
+        n = ctypes.c_int32()
+        _check(lib().absorber_ipm_log_get(self.h, int(problem), 0, None, ctypes.byref(n)))
+        buf = (IpmLogEntry * max(n.value, 1))()
+        _check(lib().absorber_ipm_log_get(self.h, int(problem), n.value, buf, ctypes.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
 
     def tuning(self) -> dict:
         t = Tuning()

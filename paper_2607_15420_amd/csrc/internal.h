@@ -184,6 +184,7 @@ struct Handle {
   size_t ipm_work_bytes = 0;
   double* ipm_dd_h = nullptr;
   long long n_factor = 0, n_solve = 0;       // launch counters
+  std::vector<std::vector<absorber_ipm_log_entry>> ipm_log;  // per problem: accepted iterations of the last solve
   // optional per-class kernel timing: event pairs recorded on the launch stream
   // and read back only when the profile is fetched (or the pending list is full)
   int prof = 0;  // bit mask of the profiled kernel classes
@@ -232,8 +233,10 @@ hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling
 // ||r - K x||_inf <= 1e-10 ||r||_inf (at most 10 corrections, keeping the best).
 // first_residual_read: the residual of the fused solution has been computed and
 // its norms copied to the last four doubles of redbuf_h.
+// rel: the largest of the problems' kept relative residuals; rel_p (host [P],
+// may be null): each problem's own.
 int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st,
-                      bool first_residual_read = false);
+                      bool first_residual_read = false, double* rel_p = nullptr);
 // res[P]; active0 (host [P], may be null): only these problems iterate and
 // are written to xout/yout/res
 int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0, const double* y0, double* xout,
@@ -271,6 +274,8 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
 hipError_t launch_residual_pmax(Handle& h, hipStream_t st);
 // res_i = 0 on the rows of the problems whose mask entry is 0
 hipError_t launch_mask_rows(Handle& h, const int* mask, double* res, hipStream_t st);
+// dst_i = src_i on the KKT rows of the problems whose mask entry is not 0
+hipError_t launch_copy_rows(Handle& h, const int* mask, double* dst, const double* src, hipStream_t st);
 // x <- the cold-start point (h.x0 in every stage, its diameter for every problem)
 hipError_t launch_tile_x0(Handle& h, double* x, hipStream_t st);
 // z = y + a x (z may be y)

@@ -658,7 +658,8 @@ struct Prob {
   double E0 = INFINITY, inf_pr = 0, inf_du = 0, compl0 = 0, xd = 0, dxd = 0;
   double alpha = 0, alpha_max = 0, alpha_z = 0, gdx = 0, th = 0, phi = 0, amin = 0;
   double n_all = 0, n_b = 0, nx_p = 0, nc_p = 0;
-  int status = ABS_ERR_MAXITER, it = 0, ncorr = 0, nls = 0;
+  double max_lin = 0;  // largest relative residual of this problem's Newton-system solves
+  int status = ABS_ERR_MAXITER, it = 0, ncorr = 0, nls = 0, nfac = 0;
   bool active = true, need = false, searching = false, accepted = false, ftype = false;
   Filter filt;
 };
@@ -677,20 +678,23 @@ static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
 }
 
 int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st,
-                      bool first_residual_read) {
+                      bool first_residual_read, double* rel_p) {
   if (!fused_first) {
     HIP_TRY(launch_solve(h, rhs, st));
     HIP_TRY(launch_schur(h, h.diagx, rhs, 2, sol, st));
   }
-  // Corrections are applied out of place, alternating between sol and h.kcor,
-  // so the best iterate is kept without copying it: xb is the best so far, xn
-  // the iterate whose residual is evaluated next.
-  // With several problems, a correction is computed only for the problems whose
-  // own relative residual is above the target (the others keep their iterate:
-  // their rows of the residual are cleared and their chains skipped).
+  // Each problem refines until its own relative residual ||r_p - K_p x_p||_inf /
+  // ||r_p||_inf (its stage rows and its d row) is at most the target, or until
+  // a correction no longer decreases it; then it keeps its best iterate and
+  // later corrections skip it (its rows of the residual are cleared and its
+  // chains solve nothing).  Corrections are applied out of place: xn = xb +
+  // correction, where xb holds every problem's best iterate so far; a problem
+  // whose residual grew takes its entries of xb back into xn.
   constexpr double target = 1e-10;  // relative residual target of the refinement
-  const bool per_problem = h.P > 1;
-  double best_rel = INFINITY;
+  const int P = h.P;
+  const bool per_problem = P > 1;
+  std::vector<double> best((size_t)P, INFINITY);
+  std::vector<char> refining((size_t)P, 1);
   double* xb = sol;
   double* xn = sol;
   double* om = h.redbuf_h + h.red_cap - 4;  // four pinned doubles past the partials
@@ -702,21 +706,41 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     }
     if (per_problem) {  // per-problem maxima of the same residual
       HIP_TRY(launch_residual_pmax(h, st));
-      HIP_TRY(hipMemcpyAsync(h.pres_h, h.pres, sizeof(double) * 2 * h.P, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(h.pres_h, h.pres, sizeof(double) * 2 * P, hipMemcpyDeviceToHost, st));
       HIP_TRY(wait_stream(st));
     }
-    const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];  // ||res||_inf / ||rhs||_inf
-    if (!(relr < best_rel)) break;  // no further improvement: keep the best iterate
-    best_rel = relr;
-    xb = xn;
-    h.last_omega = fmax(om[0], om[1]);  // componentwise backward error of the kept iterate
-    if (relr <= target || it == 10) break;
-    if (per_problem) {
-      for (int p = 0; p < h.P; ++p) {
-        const double r = h.pres_h[2 * p], b = h.pres_h[2 * p + 1];
-        h.rmask_h[p] = (b > 0.0 ? r / b : r) > target || !std::isfinite(r) ? 1 : 0;
+    bool any_revert = false, any_left = false;
+    for (int p = 0; p < P; ++p) {
+      h.rmask_h[p] = 0;
+      if (!refining[(size_t)p]) continue;
+      const double r = per_problem ? h.pres_h[2 * p] : om[2];
+      const double b = per_problem ? h.pres_h[2 * p + 1] : om[3];
+      const double relr = b > 0.0 ? r / b : r;
+      if (relr < best[(size_t)p]) {
+        best[(size_t)p] = relr;
+        if (!per_problem) h.last_omega = fmax(om[0], om[1]);  // backward error of the kept iterate
+        if (relr <= target) refining[(size_t)p] = 0;
+      } else {  // no decrease (or not finite): this problem keeps its previous iterate
+        refining[(size_t)p] = 0;
+        if (xn != xb) {
+          h.rmask_h[p] = 1;
+          any_revert = true;
+        }
       }
-      HIP_TRY(hipMemcpyAsync(h.rmask, h.rmask_h, sizeof(int) * h.P, hipMemcpyHostToDevice, st));
+      any_left = any_left || refining[(size_t)p];
+    }
+    if (any_revert) {
+      if (per_problem) {
+        HIP_TRY(hipMemcpyAsync(h.rmask, h.rmask_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_copy_rows(h, h.rmask, xn, xb, st));
+      } else {
+        xn = xb;  // the single problem's best iterate is the whole of xb
+      }
+    }
+    if (!any_left || it == 10) break;
+    if (per_problem) {
+      for (int p = 0; p < P; ++p) h.rmask_h[p] = refining[(size_t)p] ? 1 : 0;
+      HIP_TRY(hipMemcpyAsync(h.rmask, h.rmask_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
       HIP_TRY(launch_mask_rows(h, h.rmask, h.kres, st));
       int* const pact = h.pact;
       const bool pact_on = h.pact_on;
@@ -730,11 +754,18 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
       HIP_TRY(launch_solve(h, h.kres, st));
     }
     HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st));  // correction in place
-    xn = xb == sol ? h.kcor : sol;
-    HIP_TRY(launch_axpy(xn, xb, h.kres, 1.0, h.nkkt, st));  // xn = xb + correction
+    double* xnew = xn == sol ? h.kcor : sol;
+    HIP_TRY(launch_axpy(xnew, xn, h.kres, 1.0, h.nkkt, st));  // xnew = xn + correction
+    xb = xn;
+    xn = xnew;
   }
-  if (xb != sol) HIP_TRY(hipMemcpyAsync(sol, xb, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
-  if (rel) *rel = best_rel;
+  if (xn != sol) HIP_TRY(hipMemcpyAsync(sol, xn, sizeof(double) * h.nkkt, hipMemcpyDeviceToDevice, st));
+  double worst = 0.0;
+  for (int p = 0; p < P; ++p) {
+    worst = std::max(worst, best[(size_t)p]);
+    if (rel_p) rel_p[p] = best[(size_t)p];
+  }
+  if (rel) *rel = worst;
   return ABS_OK;
 }
 
@@ -784,6 +815,10 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   int* pa_h = reinterpret_cast<int*>(h.ctl_h + ctl_off_pact(P));
   W.dd_h = h.ipm_dd_h;
   std::vector<Prob> pr((size_t)P);
+  h.ipm_log.resize((size_t)P);
+  for (int p = 0; p < P; ++p)
+    if (!active0 || active0[p]) h.ipm_log[(size_t)p].clear();
+  std::vector<double> rel_p((size_t)P, 0.0);
   // scalars, activity, regularisation and the refactorisation mask of every
   // problem -> device, in one transfer
   auto upload = [&]() -> int {
@@ -860,7 +895,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   hipLaunchKernelGGL(k_init_slack, dim3(gst), dim3(BS), 0, st, W.c, W.s, W.vU, warm ? o.warm_bound_push : o.bound_push,
                      warm ? 1 : 0, mu0, C.zinit, nst);
   hipLaunchKernelGGL(k_fill, dim3(gc), dim3(BS), 0, st, W.y, 0.0, nc);
-  double rel = 0.0, max_rel = 0.0;
+  double rel = 0.0;
   int nfact = 0;
   TRY(upload());
   if (warm && y0_dev) {
@@ -989,6 +1024,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       q.dw = 0.0;
       q.dc = 0.0;
       q.need = q.active;
+      q.nfac = 0;
     }
     TRY(upload());
     for (bool first = true;; first = false) {
@@ -1010,6 +1046,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       for (int p = 0; p < P; ++p) {
         Prob& q = pr[(size_t)p];
         if (!q.need) continue;
+        ++q.nfac;
         const DevScalars& D = h.scal_h[p];
         if ((double)D.npos == q.nx_p && (double)D.nneg == q.nc_p && D.nzero == 0) {
           if (q.dw > 0.0) q.dw_last = q.dw;
@@ -1020,7 +1057,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
         if (D.nzero > 0) q.dc = C.dc_bar * pow(q.mu, C.kappa_c);
         if (q.dw == 0.0) q.dw = q.dw_last == 0.0 ? C.dw_init : std::max(C.dw_min, C.kw_minus * q.dw_last);
         else q.dw = (q.dw_last == 0.0 ? C.kw_plus_bar : C.kw_plus) * q.dw;
-        if (q.dw > C.dw_max) {
+        if (q.dw > o.delta_w_max) {
           q.status = ABS_ERR_INERTIA;
           q.active = false;
           q.need = false;
@@ -1034,8 +1071,9 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     if (n_active == 0) break;
     const auto ph2 = now();
     TRY(upload());
-    TRY(kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st, true));
-    max_rel = std::max(max_rel, rel);
+    TRY(kkt_solve_refined(h, W.rhs, W.sol, true, &rel, st, true, rel_p.data()));
+    for (int p = 0; p < P; ++p)
+      if (pr[(size_t)p].active) pr[(size_t)p].max_lin = std::max(pr[(size_t)p].max_lin, rel_p[(size_t)p]);
     const auto ph3 = now();
     // ---- step pieces and fraction to the boundary
     // and, reduced together, theta and the barrier function at the current point
@@ -1150,6 +1188,19 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       if (!q.ftype) q.filt.pts.push_back({(1 - C.gamma_theta) * q.th, q.phi - C.gamma_phi * q.th});
       q.xd = q.xd + q.alpha * q.dxd;
       ++q.it;
+      absorber_ipm_log_entry e{};
+      e.iteration = q.it;
+      e.n_factorizations = q.nfac;
+      e.n_trials = q.nls;
+      e.mu = q.mu;
+      e.theta = q.th;
+      e.alpha = q.alpha;
+      e.alpha_z = q.alpha_z;
+      e.delta_w = q.dw;
+      e.delta_c = q.dc;
+      e.d = q.xd * h.sc.Dd;
+      e.E0 = q.E0;
+      h.ipm_log[(size_t)p].push_back(e);
     }
     TRY(upload());
     hipLaunchKernelGGL(k_accept, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.xtt, W.s, W.st, W.y, W.dy, W.zL,
@@ -1201,7 +1252,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     r.seconds = secs;
     r.n_inertia_corrections = q.ncorr;
     r.n_factorizations = nfact;
-    r.max_lin_resid = max_rel;
+    r.max_lin_resid = q.max_lin;
     r.feasibility_restarts = 0;
   }
   return first_err;
@@ -1237,8 +1288,9 @@ int solve_with_restart(Handle& h, const absorber_ipm_options& o, const double* x
       absorber_ipm_options ow = o;
       ow.warm_start = 1;
       std::vector<absorber_ipm_result> r2 = r1;
-      ipm_solve(h, ow, xs, nullptr, xout, yout, r2.data(), redo.data());
-      for (int p = 0; p < P; ++p)
+      const int rc2 = ipm_solve(h, ow, xs, nullptr, xout, yout, r2.data(), redo.data());
+      if (rc2 < 0 && rc2 > ABS_ERR_INERTIA) rs = rc2;  // argument, device or allocation error of the restart
+      for (int p = 0; p < P && !rs; ++p)
         if (redo[(size_t)p]) {
           r2[(size_t)p].iterations += r1[(size_t)p].iterations;
           r2[(size_t)p].n_inertia_corrections += r1[(size_t)p].n_inertia_corrections;
@@ -1278,12 +1330,13 @@ void absorber_ipm_default_options(absorber_ipm_options* o) {
   o->use_graph = 0;
   o->feasibility_restart = 1;
   o->autotune = 1;
+  o->delta_w_max = 1e40;
 }
 
 static int check_options(const absorber_ipm_options* opts, absorber_ipm_options* o, const char* who) {
   if (opts) *o = *opts;
   else absorber_ipm_default_options(o);
-  if (!(o->tol > 0) || o->max_iter < 0) {
+  if (!(o->tol > 0) || o->max_iter < 0 || !(o->delta_w_max > 0)) {
     set_error(std::string(who) + ": bad options");
     return ABS_ERR_ARG;
   }
@@ -1335,6 +1388,21 @@ int absorber_tuning_get(const absorber_t* H, absorber_tuning* out) {
     out->solve_ms[i] = t.ms_solve[i];
     out->eval_ms[i] = t.ms_eval[i];
   }
+  return ABS_OK;
+}
+
+int absorber_ipm_log_get(const absorber_t* H, int32_t problem, int32_t max_entries, absorber_ipm_log_entry* out,
+                         int32_t* n_out) {
+  if (!H || problem < 0 || problem >= H->h.P || max_entries < 0 || (max_entries > 0 && !out)) {
+    set_error("absorber_ipm_log_get: bad argument");
+    return ABS_ERR_ARG;
+  }
+  const Handle& h = H->h;
+  const std::vector<absorber_ipm_log_entry>* log =
+      (size_t)problem < h.ipm_log.size() ? &h.ipm_log[(size_t)problem] : nullptr;
+  const int n = log ? (int)log->size() : 0;
+  for (int i = 0; i < n && i < max_entries; ++i) out[i] = (*log)[(size_t)i];
+  if (n_out) *n_out = n;
   return ABS_OK;
 }
 

@@ -478,6 +478,16 @@ __global__ void k_mask_rows(const int* __restrict__ mask, const StageInfo* __res
   }
 }
 
+__global__ void k_copy_rows(const int* __restrict__ mask, const StageInfo* __restrict__ sinfo, long long nks, int P,
+                            double* __restrict__ dst, const double* __restrict__ src) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nks) {
+    if (mask[sinfo[i / NK].p]) dst[i] = src[i];
+  } else if (i < nks + P) {
+    if (mask[i - nks]) dst[i] = src[i];
+  }
+}
+
 inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -603,6 +613,13 @@ hipError_t launch_residual_pmax(Handle& h, hipStream_t st) {
 hipError_t launch_mask_rows(Handle& h, const int* mask, double* res, hipStream_t st) {
   const long long nks = h.nst * NK;
   hipLaunchKernelGGL(k_mask_rows, dim3(grid_for(nks + h.P, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(Handle& h, const int* mask, double* dst, const double* src, hipStream_t st) {
+  const long long nks = h.nst * NK;
+  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for(nks + h.P, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, dst,
+                     src);
   return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ struct Epi {
   float* y = nullptr;           // float result [M][ldy] (OUT: outputs, WGRAD: weight gradient)
   int ldy = 0;
   int m_real = 0, n_real = 0;   // OUT / WGRAD store rows < m_real and cols < n_real only
+  int n_par = 0;                // OUT: entries of the bias and standardisation arrays
   const float* omean = nullptr; // OUT: optional un-standardisation y * ostd + omean
   const float* ostd = nullptr;
 };
@@ -106,9 +107,14 @@ __global__ __launch_bounds__(64) void k_gemm(const __bf16* __restrict__ A, int l
             e.h[(long long)m * e.ldh + n] = (__bf16)hv;
           }
         } else if (EPI == EPI_OUT) {
-          float yv = acc + e.bias[n];
-          if (e.ostd) yv = yv * e.ostd[n] + e.omean[n];
-          if (m < M && m < e.m_real && n < e.n_real) e.y[(long long)m * e.ldy + n] = yv;
+          // the output bias and the standardisation arrays hold n_par entries: a
+          // padded column (n >= n_par, zero weights) takes bias 0 and is never
+          // un-standardised, so no read leaves those arrays
+          if (m < M && m < e.m_real && n < e.n_real) {
+            float yv = acc + (n < e.n_par ? e.bias[n] : 0.0f);
+            if (e.ostd && n < e.n_par) yv = yv * e.ostd[n] + e.omean[n];
+            e.y[(long long)m * e.ldy + n] = yv;
+          }
         } else if (EPI == EPI_BWD) {
           const float g = m < M ? acc * gelu_d(e.zf[(long long)m * e.ldz + n]) : 0.0f;
           o[r] = g;
@@ -317,6 +323,7 @@ struct MlpImpl {
         e.ldy = ldy;
         e.m_real = m_real;
         e.n_real = train ? nout[l] : dout[l];
+        e.n_par = dout[l];
         e.omean = om;
         e.ostd = os;
         hipLaunchKernelGGL(k_gemm<EPI_OUT>, grid, dim3(64), 0, st, H[l], kin[l], Wq[l], kin[l], B, nout[l], kin[l], e);

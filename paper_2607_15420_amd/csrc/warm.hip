@@ -237,9 +237,12 @@ int absorber_warm_solve(absorber_t* ah, absorber_mlp* net, const absorber_ipm_op
   absorber_ipm_options ow = *opts;
   ow.warm_start = 1;
   rc = absorber_ipm_solve(ah, &ow, h.warm_x0, pd ? h.warm_l0 : nullptr, x_out_dev, lambda_out_dev, result);
-  const bool ok = rc == ABS_OK && result->status == ABS_OK;
-  if (used_warm) *used_warm = ok ? 1 : 0;
-  if (!ok) {  // cold-start fallback
+  if (rc < 0 && rc > ABS_ERR_INERTIA) return rc;  // argument, device or allocation error
+  const bool converged = rc == ABS_OK && result->status == ABS_OK;
+  // the network's start counts only when that run converged by itself, not
+  // through the feasibility restart (which starts from simulated states)
+  if (used_warm) *used_warm = converged && result->feasibility_restarts == 0 ? 1 : 0;
+  if (!converged) {  // cold-start fallback
     absorber_ipm_options oc = *opts;
     oc.warm_start = 0;
     const int it_warm = result->iterations;

@@ -46,6 +46,8 @@ def test_uneven_batch_matches_closed_form_and_single_solves(params):
     Zb = _states_of(xh[:nxs], problems)
     for p, ((N, F), r) in enumerate(zip(problems, res)):
         assert r.status == 0 and r.E0 <= 1e-8, (p, r.as_dict())
+        # every Newton-system solve of this problem refined to its own rows' target
+        assert r.max_lin_resid <= 1e-10, (p, r.max_lin_resid)
         assert xh[nxs + p] == pytest.approx(r.d, rel=1e-14)
         dstar, _, Zs, ok = simulate.closed_form_diameter(F, N, params)
         assert ok.all()
