@@ -180,6 +180,13 @@ def batch_leg(params, n_problems: int, sequential: bool):
     rc, res = h.batch_solve(opts)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    tuning = h.tuning()
+    # the same batch with the per-problem decisions on the device and the
+    # iterations replayed as captured graphs (same handle: tuned shapes kept)
+    t0 = time.perf_counter()
+    rc_g, res_g = h.batch_solve(Absorber.default_options(use_graph=1))
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
     h.close()
     out = {
         "workload": f"C5: {len(probs)} problems, stages uniform 8-60, scenarios log-uniform 50-2000, feeds +-15%, "
@@ -187,6 +194,12 @@ def batch_leg(params, n_problems: int, sequential: bool):
         "batched_s": t_batch, "batched_converged": int(sum(r.status == 0 for r in res)),
         "batched_restarted": int(sum(r.feasibility_restarts for r in res)),
         "batched_solves_per_s": len(probs) / t_batch,
+        "tuning": tuning,
+        "graph_s": t_graph, "graph_converged": int(sum(r.status == 0 for r in res_g)),
+        "graph_solves_per_s": len(probs) / t_graph,
+        "graph_replays": int(max(r.graph_replays for r in res_g)),
+        "graph_d_agree_1e-8": int(sum(a.status == 0 and b.status == 0 and abs(a.d - b.d) <= 1e-8 * a.d
+                                      for a, b in zip(res, res_g))),
         "max_iterations": int(max(r.iterations for r in res)),
         "max_lin_resid": float(max(r.max_lin_resid for r in res)),
         "lin_resid_le_1e-10": int(sum(r.max_lin_resid <= 1e-10 for r in res)),

@@ -166,7 +166,12 @@ typedef struct {
   double warm_bound_push;   /* 1e-8 */
   double nlp_scaling_max_gradient; /* 100 */
   int32_t print_level;      /* 0 silent, 1 one line per iteration to stderr */
-  int32_t use_graph;        /* reserved (0) */
+  int32_t use_graph;        /* 1: the per-problem decisions of each iteration (convergence test, barrier
+                               update, inertia correction, refinement stop, filter line search, step
+                               acceptance) are taken on the device, and the iteration's launches replay
+                               as captured HIP graphs, one per phase, with one status read per replay
+                               pass (the usual iteration is one pass); 0: the host takes the decisions
+                               between launches (default 0).  Both take the same decisions. */
   int32_t feasibility_restart; /* 1: a problem that stops without converging (line search, inertia,
                                   iteration limit) is solved again from its simulated states
                                   (absorber_simulate, d at 1.001 x its hydraulic minimum) with the
@@ -189,6 +194,7 @@ typedef struct {
   double max_lin_resid;     /* largest relative linear residual ||r - K x||_inf / ||r||_inf of this
                                problem's own rows over its KKT solves */
   int32_t feasibility_restarts; /* 1 if the result comes from the feasibility restart */
+  int32_t graph_replays;    /* graph launches of the solve (use_graph = 1), 0 otherwise */
 } absorber_ipm_result;
 
 void absorber_ipm_default_options(absorber_ipm_options* opts);

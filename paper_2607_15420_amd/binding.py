@@ -72,7 +72,7 @@ class IpmResult(ctypes.Structure):
         ("inf_pr", ctypes.c_double), ("inf_du", ctypes.c_double), ("compl_", ctypes.c_double),
         ("d", ctypes.c_double), ("seconds", ctypes.c_double), ("n_inertia_corrections", ctypes.c_int32),
         ("n_factorizations", ctypes.c_int32), ("max_lin_resid", ctypes.c_double),
-        ("feasibility_restarts", ctypes.c_int32),
+        ("feasibility_restarts", ctypes.c_int32), ("graph_replays", ctypes.c_int32),
     ]
 
     def as_dict(self):

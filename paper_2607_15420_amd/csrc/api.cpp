@@ -281,6 +281,7 @@ int prof_flush(Handle& h) {
 }
 
 static void free_handle(Handle& h) {
+  free_ipm_graph(h);
   if (!h.prof_pending.empty()) (void)hipEventSynchronize(h.prof_pending.back().e1);
   for (const auto& q : h.prof_pending) {
     (void)hipEventDestroy(q.e0);

@@ -601,13 +601,15 @@ constexpr int SCHUR_BS = 1024;
 __global__ __launch_bounds__(SCHUR_BS) void k_schur(const double* __restrict__ part, const int* __restrict__ inert,
                                                     const int* __restrict__ pchain, const double* __restrict__ diagd,
                                                     const double* __restrict__ dwv, const double* __restrict__ rd,
-                                                    int mode, DevScalars* __restrict__ outv) {
+                                                    int mode, const int* __restrict__ pmask,
+                                                    DevScalars* __restrict__ outv) {
   // mode 0: factor only; 1: factor with a right-hand side; 2: right-hand side only
   // The six sums (three of them integer counts, exact in double) run in a fixed
   // order: thread i takes chains i, i + SCHUR_BS, ... four at a time, then a
   // shuffle tree inside each wave and across the waves.
   __shared__ double sm[6][SCHUR_BS / 64];
   const int pb = blockIdx.x;
+  if (pmask && !pmask[pb]) return;  // this problem keeps its scalars
   const int w0 = pchain[pb], w1 = pchain[pb + 1];
   DevScalars* out = outv + pb;
   double a[6] = {0, 0, 0, 0, 0, 0};
@@ -679,10 +681,14 @@ __global__ __launch_bounds__(SCHUR_BS) void k_schur(const double* __restrict__ p
 // sol = solr - solb * dd_p on the stage entries, sol[d_p] = dd_p
 __global__ void k_combine(const double* __restrict__ solr, const double* __restrict__ solb,
                           const DevScalars* __restrict__ sc, const StageInfo* __restrict__ sinfo, long long nk,
-                          int P, double* __restrict__ sol) {
+                          int P, const int* __restrict__ pmask, double* __restrict__ sol) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nk) sol[i] = solr[i] - solb[i] * sc[sinfo[i / NK].p].dd;
-  else if (i < nk + P) sol[i] = sc[i - nk].dd;
+  if (i < nk) {
+    const int p = sinfo[i / NK].p;
+    if (!pmask || pmask[p]) sol[i] = solr[i] - solb[i] * sc[p].dd;
+  } else if (i < nk + P) {
+    if (!pmask || pmask[i - nk]) sol[i] = sc[i - nk].dd;
+  }
 }
 
 }  // namespace
@@ -729,14 +735,15 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
   return hipGetLastError();
 }
 
-hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st) {
+hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st,
+                        const int* pmask) {
   const double* rd = rhs ? rhs + h.nst * NK : nullptr;
   hipLaunchKernelGGL(k_schur, dim3(h.P), dim3(SCHUR_BS), 0, st, h.part, h.inert, h.pchain, diagx + h.nst * NV, h.dwv, rd,
-                     mode, h.scal);
+                     mode, pmask, h.scal);
   if (mode != 0 && sol) {
     const long long nk = h.nst * NK;
     hipLaunchKernelGGL(k_combine, dim3(grid_for(nk + h.P, 256)), dim3(256), 0, st, h.solr, h.solb, h.scal, h.sinfo,
-                       nk, h.P, sol);
+                       nk, h.P, pmask, sol);
   }
   return hipGetLastError();
 }

@@ -185,6 +185,7 @@ struct Handle {
   double* ipm_dd_h = nullptr;
   long long n_factor = 0, n_solve = 0;       // launch counters
   std::vector<std::vector<absorber_ipm_log_entry>> ipm_log;  // per problem: accepted iterations of the last solve
+  void* ipm_graph = nullptr;  // captured iteration graphs and their device control state (ipm.hip)
   // optional per-class kernel timing: event pairs recorded on the launch stream
   // and read back only when the profile is fetched (or the pending list is full)
   int prof = 0;  // bit mask of the profiled kernel classes
@@ -243,6 +244,9 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0, const 
               double* yout, absorber_ipm_result* res, const unsigned char* active0 = nullptr);
 int solve_with_restart(Handle& h, const absorber_ipm_options& o, const double* x0, const double* y0, double* xout,
                        double* yout, absorber_ipm_result* res);
+// stream of the graph-replayed iterations (created on first use; null if that fails)
+hipStream_t ipm_graph_stream(Handle& h);
+void free_ipm_graph(Handle& h);
 // process simulation (damped Newton on every scenario's MESH block) of the
 // problems in pmask (host [P], null: all) from x (unscaled, in/out)
 int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, int max_iter, int* conv, int* iters);
@@ -264,7 +268,9 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
 // mode 0).  mode 0: after launch_factor without a right-hand side (S_d,
 // inertia); 1: after launch_factor with one; 2: after launch_solve.  For modes
 // 1 and 2, sol (if not null) receives the combined solution of the bordered system.
-hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st);
+// pmask (device [P], may be null): only the problems whose entry is not 0 are updated.
+hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st,
+                        const int* pmask = nullptr);
 // residual res = rhs - K sol of the bordered systems; omega_out[0] = max
 // componentwise backward error over the scenario rows, omega_out[1] over the d rows
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,

@@ -666,6 +666,676 @@ struct Prob {
 
 }  // namespace
 
+// ------------------------------------------------------------------ device-resident control
+// With use_graph, the per-problem decisions of an iteration (convergence test
+// and barrier update, inertia correction, refinement stop, step bounds, filter
+// acceptance, step acceptance) are taken on the device by one thread per
+// problem, with the same arithmetic and in the same order as the host
+// decisions of the host-driven loop.  Each problem moves through the phases
+// of an iteration; every launch of the iteration acts on the problems in its
+// phase, so the launches of one iteration can be replayed as fixed HIP graphs
+// and the host only reads a compact status once per replay pass.
+namespace {
+
+constexpr int PH_IDLE = 0;    // between iterations (or finished)
+constexpr int PH_FACTOR = 1;  // a factorisation trial of the inertia correction is due
+constexpr int PH_RES0 = 2;    // factorised with the right inertia: first residual due
+constexpr int PH_REFINE = 3;  // refinement corrections due
+constexpr int PH_DIR = 4;     // solution final: step pieces and bounds due
+constexpr int PH_SEARCH = 5;  // line search: the trial point at alpha is due
+constexpr int PH_ACCEPT = 6;  // trial accepted: the step is due
+
+struct DevProb {
+  double mu, tau, dw, dc, dw_last, theta_max, theta_min;
+  double E0, inf_pr, inf_du, compl0, xd, dxd;
+  double alpha, alpha_z, gdx, th, phi, amin;
+  double n_all, n_b, nx_p, nc_p, max_lin, best;
+  int status, it, ncorr, nls, nfac, nfilt, nref, phase, active, ftype;
+};
+
+// device pointers of the control state (passed by value)
+struct GCtl {
+  DevProb* dp;
+  PS* ps;
+  int* pact;
+  double* dwv;
+  double* dcv;
+  int* fmask;
+  int* rmask;  // problems whose refinement correction is due
+  int* cmask;  // problems whose corrected iterate is kept
+  double* filt;  // [P][fcap][2]
+  int fcap;
+  int2* stat;  // [P] (phase, active) for the host
+  absorber_ipm_log_entry* log;  // [log_np][log_cap]
+  int log_np, log_cap;
+  int P;
+};
+
+__device__ __forceinline__ void ctl_store(const GCtl& g, int p, const DevProb& q) {
+  g.dp[p] = q;
+  g.stat[p] = make_int2(q.phase, q.active);
+}
+
+__device__ __forceinline__ void ctl_stop(const GCtl& g, int p, DevProb& q, int status) {
+  q.status = status;
+  q.active = 0;
+  q.phase = PH_IDLE;
+  g.pact[p] = 0;
+  g.fmask[p] = 0;
+  g.rmask[p] = 0;
+  g.ps[p].active = 0;
+  g.ps[p].search = 0;
+  g.ps[p].accept = 0;
+}
+
+// convergence test on the reduced optimality-error parts and the monotone
+// barrier update; starts the inertia correction with delta_w = delta_c = 0
+__global__ void k_ctl_opt(GCtl g, const double* __restrict__ ov, Consts C, double tol, int max_iter) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  DevProb q = g.dp[p];
+  if (!q.active || q.phase != PH_IDLE) return;
+  const double* o = ov + 9LL * p;
+  const double dual = fmax(o[0], o[1]);
+  const double primal = fmax(o[2], o[3]);
+  const double sd = fmax(C.s_max, (o[6] + o[7]) / q.n_all) / C.s_max;
+  const double sc = fmax(C.s_max, o[7] / q.n_b) / C.s_max;
+  auto Emu = [&](double m) {
+    const double comp = fmax(fabs(o[5] - m), fabs(o[4] - m));
+    return fmax(fmax(dual / sd, primal), comp / sc);
+  };
+  q.E0 = Emu(0.0);
+  q.inf_pr = primal;
+  q.inf_du = dual;
+  q.compl0 = fmax(fabs(o[4]), fabs(o[5]));
+  int stop = 1;
+  if (o[8] > 0 || !isfinite(q.E0)) q.status = ABS_ERR_NAN;
+  else if (q.E0 <= tol) q.status = ABS_OK;
+  else if (q.it >= max_iter) q.status = ABS_ERR_MAXITER;
+  else stop = 0;
+  if (stop) {
+    ctl_stop(g, p, q, q.status);
+    ctl_store(g, p, q);
+    return;
+  }
+  while (Emu(q.mu) <= C.kappa_eps * q.mu) {
+    const double mu_new = fmax(tol / 10.0, fmin(C.kappa_mu * q.mu, pow(q.mu, C.theta_mu)));
+    if (mu_new >= q.mu) break;  // already at its floor tol / 10
+    q.mu = mu_new;
+    q.tau = fmax(C.tau_min, 1.0 - q.mu);
+    q.nfilt = 0;
+  }
+  q.dw = 0.0;
+  q.dc = 0.0;
+  q.nfac = 0;
+  q.phase = PH_FACTOR;
+  g.ps[p].mu = q.mu;
+  g.ps[p].tau = q.tau;
+  g.dwv[p] = 0.0;
+  g.dcv[p] = 0.0;
+  g.fmask[p] = 1;
+  ctl_store(g, p, q);
+}
+
+// inertia of the last factorisation: accept it or raise delta_w (and set delta_c)
+__global__ void k_ctl_inertia(GCtl g, const DevScalars* __restrict__ scal, Consts C, double dw_max) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  DevProb q = g.dp[p];
+  if (!q.active || q.phase != PH_FACTOR) return;
+  ++q.nfac;
+  const DevScalars D = scal[p];
+  if ((double)D.npos == q.nx_p && (double)D.nneg == q.nc_p && D.nzero == 0) {
+    if (q.dw > 0.0) q.dw_last = q.dw;
+    q.phase = PH_RES0;
+    g.fmask[p] = 0;
+    ctl_store(g, p, q);
+    return;
+  }
+  ++q.ncorr;
+  if (D.nzero > 0) q.dc = C.dc_bar * pow(q.mu, C.kappa_c);
+  if (q.dw == 0.0) q.dw = q.dw_last == 0.0 ? C.dw_init : fmax(C.dw_min, C.kw_minus * q.dw_last);
+  else q.dw = (q.dw_last == 0.0 ? C.kw_plus_bar : C.kw_plus) * q.dw;
+  if (q.dw > dw_max) {
+    ctl_stop(g, p, q, ABS_ERR_INERTIA);
+  } else {
+    g.dwv[p] = q.dw;
+    g.dcv[p] = q.dc;
+    g.fmask[p] = 1;
+  }
+  ctl_store(g, p, q);
+}
+
+// relative residual of each problem's own rows from the per-problem maxima
+__device__ __forceinline__ double rel_of(const double* pres, int p) {
+  const double r = pres[2 * p], b = pres[2 * p + 1];
+  return b > 0.0 ? r / b : r;
+}
+
+// first residual of the fused solution: done at the target, else refine
+__global__ void k_ctl_res0(GCtl g, const double* __restrict__ pres, double target) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  DevProb q = g.dp[p];
+  if (!q.active || q.phase != PH_RES0) return;
+  const double rel = rel_of(pres, p);
+  q.best = INFINITY;
+  q.nref = 0;
+  bool done = true;
+  if (rel < q.best) {  // false for a residual that is not finite
+    q.best = rel;
+    done = rel <= target;
+  }
+  if (done) {
+    q.max_lin = fmax(q.max_lin, q.best);
+    q.phase = PH_DIR;
+    g.rmask[p] = 0;
+  } else {
+    q.phase = PH_REFINE;
+    g.rmask[p] = 1;
+  }
+  g.cmask[p] = 0;
+  ctl_store(g, p, q);
+}
+
+// residual of the corrected iterate: keep it if it decreased; stop at the
+// target, at no decrease, or after 10 corrections
+__global__ void k_ctl_refine(GCtl g, const double* __restrict__ pres, double target) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  DevProb q = g.dp[p];
+  g.cmask[p] = 0;
+  if (!q.active || q.phase != PH_REFINE) return;
+  const double rel = rel_of(pres, p);
+  ++q.nref;
+  bool done;
+  if (rel < q.best) {
+    q.best = rel;
+    g.cmask[p] = 1;
+    done = rel <= target || q.nref >= 10;
+  } else {
+    done = true;
+  }
+  if (done) {
+    q.max_lin = fmax(q.max_lin, q.best);
+    q.phase = PH_DIR;
+    g.rmask[p] = 0;
+  }
+  ctl_store(g, p, q);
+}
+
+// step bounds from the direction reduction; the line search starts at alpha_max
+__global__ void k_ctl_dir(GCtl g, const double* __restrict__ dv4, const double* __restrict__ lv3, Consts C,
+                          double phi_d) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  DevProb q = g.dp[p];
+  if (!q.active || q.phase != PH_DIR) return;
+  const double* dv = dv4 + 4LL * p;
+  const double* lv = lv3 + 3LL * p;
+  q.alpha = dv[0];
+  q.alpha_z = dv[1];
+  q.gdx = dv[2];
+  q.dxd = dv[3];
+  q.th = lv[0];
+  q.phi = phi_d * q.xd + lv[1];
+  const double th = q.th, gdx = q.gdx;
+  if (gdx < 0 && th <= q.theta_min)
+    q.amin = C.gamma_alpha * fmin(fmin(C.gamma_theta, C.gamma_phi * th / (-gdx)),
+                                  C.delta * pow(th, C.s_theta) / pow(-gdx, C.s_phi));
+  else if (gdx < 0)
+    q.amin = C.gamma_alpha * fmin(C.gamma_theta, C.gamma_phi * th / (-gdx));
+  else
+    q.amin = C.gamma_alpha * C.gamma_theta;
+  q.nls = 0;
+  q.phase = PH_SEARCH;
+  g.ps[p].alpha = q.alpha;
+  g.ps[p].alpha_z = q.alpha_z;
+  g.ps[p].search = 1;
+  g.ps[p].accept = 0;
+  ctl_store(g, p, q);
+}
+
+// filter acceptance of the trial point (its reduced theta, barrier sum and
+// infeasibility count in tv3); backtrack by one half otherwise
+__global__ void k_ctl_ls(GCtl g, const double* __restrict__ tv3, Consts C, double phi_d) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  DevProb q = g.dp[p];
+  if (!q.active || q.phase != PH_SEARCH) return;
+  const double* tv = tv3 + 3LL * p;
+  ++q.nls;
+  const double tht = tv[0];
+  const double phit = tv[2] > 0 ? INFINITY : phi_d * (q.xd + q.alpha * q.dxd) + tv[1];
+  const double th = q.th, phi = q.phi;
+  bool okt = isfinite(phit) && isfinite(tht) && tht < q.theta_max;
+  if (okt) {
+    const double* f = g.filt + 2LL * g.fcap * p;
+    for (int i = 0; i < q.nfilt; ++i)
+      if (tht >= f[2 * i] && phit >= f[2 * i + 1]) {
+        okt = false;
+        break;
+      }
+  }
+  bool acc = false, ftype = false;
+  if (okt) {
+    const double ma = q.alpha * q.gdx;
+    const bool switching = ma < 0 && pow(-ma, C.s_phi) * pow(q.alpha, 1 - C.s_phi) > C.delta * pow(th, C.s_theta);
+    if (th <= q.theta_min && switching) {
+      if (phit <= phi + C.eta_phi * ma) {
+        acc = true;
+        ftype = true;
+      }
+    } else if (tht <= (1 - C.gamma_theta) * th || phit <= phi - C.gamma_phi * th) {
+      acc = true;
+    }
+  }
+  if (acc) {
+    q.ftype = ftype;
+    q.phase = PH_ACCEPT;
+    g.ps[p].search = 0;
+    g.ps[p].accept = 1;
+  } else {
+    q.alpha *= 0.5;
+    if (q.alpha < fmax(q.amin, C.alpha_floor)) {
+      ctl_stop(g, p, q, ABS_ERR_LS);
+    } else {
+      g.ps[p].alpha = q.alpha;
+    }
+  }
+  ctl_store(g, p, q);
+}
+
+// after the accepted step: filter augmentation, the diameter, the log entry
+__global__ void k_ctl_accept(GCtl g, Consts C, double Dd) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  DevProb q = g.dp[p];
+  if (!q.active || q.phase != PH_ACCEPT) return;
+  if (!q.ftype && q.nfilt < g.fcap) {
+    double* f = g.filt + 2LL * g.fcap * p + 2LL * q.nfilt;
+    f[0] = (1 - C.gamma_theta) * q.th;
+    f[1] = q.phi - C.gamma_phi * q.th;
+    ++q.nfilt;
+  }
+  q.xd = q.xd + q.alpha * q.dxd;
+  ++q.it;
+  if (p < g.log_np && q.it - 1 < g.log_cap) {
+    absorber_ipm_log_entry e;
+    e.iteration = q.it;
+    e.n_factorizations = q.nfac;
+    e.n_trials = q.nls;
+    e.pad = 0;
+    e.mu = q.mu;
+    e.theta = q.th;
+    e.alpha = q.alpha;
+    e.alpha_z = q.alpha_z;
+    e.delta_w = q.dw;
+    e.delta_c = q.dc;
+    e.d = q.xd * Dd;
+    e.E0 = q.E0;
+    g.log[(long long)p * g.log_cap + q.it - 1] = e;
+  }
+  g.ps[p].accept = 0;
+  q.phase = PH_IDLE;
+  if (fabs(q.xd) > 1e20) ctl_stop(g, p, q, ABS_ERR_DIVERGE);
+  ctl_store(g, p, q);
+}
+
+}  // namespace
+#define GTRY(expr)           \
+  do {                       \
+    const int rc_ = (expr);  \
+    if (rc_) return rc_;     \
+  } while (0)
+// ------------------------------------------------------------------ graph-replayed iterations
+namespace {
+
+// G_FAC_A and G_FAC_B are G_FAC without its factorisation, which is launched
+// between them (with the per-launch timing events) when the factorisation is timed
+enum { G_OPT = 0, G_FAC, G_FAC_A, G_FAC_B, G_REF, G_DIR, G_LS, G_ACC, G_COUNT };
+
+// graphs of one iteration's launches and the device control state they act on
+struct GraphState {
+  hipStream_t st = nullptr;  // capture and replay stream (default priority)
+  hipGraphExec_t ex[G_COUNT] = {};
+  bool captured = false;
+  // what the captured launches depend on besides the handle's fixed buffers
+  double tol = 0, dw_max = 0;
+  int max_iter = -1, timed = -1, fwpe = -1, swpe = -1, ebs = -1;
+  char* dev = nullptr;
+  size_t dev_bytes = 0;
+  DevProb* dp = nullptr;
+  double* filt = nullptr;
+  int2* stat = nullptr;
+  int* cmask = nullptr;
+  absorber_ipm_log_entry* log = nullptr;
+  int fcap = 0, log_np = 0, log_cap = 0;
+  int2* stat_h = nullptr;  // pinned [P]
+  ~GraphState() {
+    for (auto& e : ex)
+      if (e) (void)hipGraphExecDestroy(e);
+    if (dev) (void)hipFree(dev);
+    if (stat_h) (void)hipHostFree(stat_h);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+}  // namespace
+
+void free_ipm_graph(Handle& h) {
+  delete static_cast<GraphState*>(h.ipm_graph);
+  h.ipm_graph = nullptr;
+}
+
+hipStream_t ipm_graph_stream(Handle& h) {
+  if (!h.ipm_graph) h.ipm_graph = new GraphState();
+  GraphState& gs = *static_cast<GraphState*>(h.ipm_graph);
+  if (!gs.st && hipStreamCreateWithFlags(&gs.st, hipStreamNonBlocking) != hipSuccess) gs.st = nullptr;
+  return gs.st;
+}
+
+namespace {
+
+// record the launches of body() on st into an executable graph
+template <class F>
+int capture_graph(hipStream_t st, hipGraphExec_t* out, F body) {
+  if (*out) {
+    (void)hipGraphExecDestroy(*out);
+    *out = nullptr;
+  }
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+  const int rc = body();
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HIP_TRY(e);
+  const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIP_TRY(ei);
+  return ABS_OK;
+}
+
+// The interior-point iterations with the per-problem decisions on the device:
+// each iteration replays the graphs of its phases (evaluation and convergence
+// test, factorisation trial with the first residual, direction with the first
+// trial point, step) and reads the problems' phases once; a problem that needs
+// another factorisation trial, refinement corrections or further trial points
+// is finished by replaying the graphs of those phases.  Same arithmetic and
+// order of decisions as the host-driven loop.
+int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, const Bnd& b, double gf,
+                     Work& W, std::vector<Prob>& pr, hipStream_t st, int& nfact, int& replays) {
+  GraphState& gs = *static_cast<GraphState*>(h.ipm_graph);
+  const int P = h.P;
+  const long long nx = h.nx, nst = h.nst, nkkt = h.nkkt;
+  const long long nxs = nst * NV, nks = nst * NK;
+  const int nseg = h.nseg;
+  const unsigned gm = grid_for(std::max(nx, h.nc), BS);
+  const unsigned gp = grid_for(P, 64);
+  // ---- device control state
+  const int fcap = o.max_iter + 1, log_np = std::min(P, 64), log_cap = std::max(o.max_iter, 1);
+  auto al = [](size_t n) { return (n + 255) / 256 * 256; };
+  const size_t b_dp = al(sizeof(DevProb) * P), b_filt = al(sizeof(double) * 2 * (size_t)fcap * P),
+               b_stat = al(sizeof(int2) * P), b_cm = al(sizeof(int) * P),
+               b_log = al(sizeof(absorber_ipm_log_entry) * (size_t)log_np * log_cap);
+  const size_t need = b_dp + b_filt + b_stat + b_cm + b_log;
+  if (need > gs.dev_bytes) {
+    if (gs.dev) HIP_TRY(hipFree(gs.dev));
+    gs.dev = nullptr;
+    gs.dev_bytes = 0;
+    HIP_TRY(hipMalloc((void**)&gs.dev, need));
+    gs.dev_bytes = need;
+    if (gs.stat_h) HIP_TRY(hipHostFree(gs.stat_h));
+    gs.stat_h = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&gs.stat_h, sizeof(int2) * P, 0));
+    gs.captured = false;
+  }
+  if (!gs.stat_h) HIP_TRY(hipHostMalloc((void**)&gs.stat_h, sizeof(int2) * P, 0));
+  gs.dp = reinterpret_cast<DevProb*>(gs.dev);
+  gs.filt = reinterpret_cast<double*>(gs.dev + b_dp);
+  gs.stat = reinterpret_cast<int2*>(gs.dev + b_dp + b_filt);
+  gs.cmask = reinterpret_cast<int*>(gs.dev + b_dp + b_filt + b_stat);
+  gs.log = reinterpret_cast<absorber_ipm_log_entry*>(gs.dev + b_dp + b_filt + b_stat + b_cm);
+  gs.fcap = fcap;
+  gs.log_np = log_np;
+  gs.log_cap = log_cap;
+  {
+    std::vector<DevProb> dp((size_t)P);
+    for (int p = 0; p < P; ++p) {
+      const Prob& q = pr[(size_t)p];
+      DevProb d{};
+      d.mu = q.mu;
+      d.tau = q.tau;
+      d.theta_max = q.theta_max;
+      d.theta_min = q.theta_min;
+      d.E0 = q.E0;
+      d.xd = q.xd;
+      d.n_all = q.n_all;
+      d.n_b = q.n_b;
+      d.nx_p = q.nx_p;
+      d.nc_p = q.nc_p;
+      d.status = q.status;
+      d.active = q.active ? 1 : 0;
+      d.phase = PH_IDLE;
+      dp[(size_t)p] = d;
+    }
+    HIP_TRY(hipMemcpyAsync(gs.dp, dp.data(), sizeof(DevProb) * P, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  GCtl g{gs.dp, W.ps, h.pact, h.dwv, h.dcv, h.fmask, h.rmask, gs.cmask, gs.filt, fcap, gs.stat, gs.log,
+         log_np, log_cap, P};
+  const double phi_d = h.sf * h.sc.Dd;
+  const int timed = (h.prof & 1) ? 1 : 0;
+  // ---- capture (again when the options, the launch shapes or the timing changed)
+  if (o.autotune && !h.tune.done) GTRY(autotune(h, W.xt, W.y, W.c, h.diagx, h.diags, W.rhs, st));
+  if (!gs.captured || gs.tol != o.tol || gs.dw_max != o.delta_w_max || gs.max_iter != o.max_iter ||
+      gs.timed != timed || gs.fwpe != h.tune.factor_wpe || gs.swpe != h.tune.solve_wpe ||
+      gs.ebs != h.tune.eval_bs) {
+    gs.captured = false;
+    const int prof = h.prof;
+    h.prof = 0;  // per-launch event pairs are not recorded into graphs
+    struct Restore {
+      Handle& h;
+      int prof;
+      ~Restore() { h.prof = prof; }
+    } restore{h, prof};
+    double* out = h.redbuf + 7LL * nseg;  // direction [4P], current point [3P], trial point [3P]
+    GTRY(capture_graph(st, &gs.ex[G_OPT], [&]() -> int {
+      HIP_TRY(launch_eval(h, W.xt, 1, W.y, 1, W.c, st));
+      hipLaunchKernelGGL(k_lag_grad, dim3(nseg), dim3(GBS), 0, st, h.rec, h.gtab, h.gtab_n, W.y, h.seg, h.sinfo,
+                         nst, h.jac_d_index, W.g, W.dpart);
+      hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, gf, nxs, W.g);
+      hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s,
+                         W.vU, b, nxs, h.redbuf);
+      hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nxs, nst, h.diagx,
+                         h.diags);
+      hipLaunchKernelGGL(k_seg_reduce<9>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg,
+                         Ops<9>{{1, 1, 1, 1, 2, 1, 0, 0, 0}}, h.redbuf + 9LL * nseg);
+      hipLaunchKernelGGL(k_ctl_opt, dim3(gp), dim3(64), 0, st, g, h.redbuf + 9LL * nseg, C, o.tol, o.max_iter);
+      HIP_TRY(hipGetLastError());
+      return ABS_OK;
+    }));
+    auto fac_a = [&]() -> int {
+      hipLaunchKernelGGL(k_rhs, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.g, W.y, W.c, W.s, h.diags,
+                         b, C.kappa_d, gf, nxs, nks, W.rhs);
+      HIP_TRY(hipGetLastError());
+      return ABS_OK;
+    };
+    auto fac_b = [&]() -> int {
+      HIP_TRY(launch_schur(h, h.diagx, W.rhs, 1, W.sol, st, h.fmask));
+      hipLaunchKernelGGL(k_ctl_inertia, dim3(gp), dim3(64), 0, st, g, h.scal, C, o.delta_w_max);
+      HIP_TRY(launch_residual(h, h.diagx, h.diags, W.sol, W.rhs, h.kres, h.omega_d, st));
+      HIP_TRY(launch_residual_pmax(h, st));
+      hipLaunchKernelGGL(k_ctl_res0, dim3(gp), dim3(64), 0, st, g, h.pres, 1e-10);
+      HIP_TRY(hipGetLastError());
+      return ABS_OK;
+    };
+    GTRY(capture_graph(st, &gs.ex[G_FAC], [&]() -> int {
+      GTRY(fac_a());
+      HIP_TRY(launch_factor(h, h.diagx, h.diags, W.rhs, true, st));
+      return fac_b();
+    }));
+    GTRY(capture_graph(st, &gs.ex[G_FAC_A], fac_a));
+    GTRY(capture_graph(st, &gs.ex[G_FAC_B], fac_b));
+    GTRY(capture_graph(st, &gs.ex[G_REF], [&]() -> int {
+      HIP_TRY(launch_mask_rows(h, h.rmask, h.kres, st));
+      int* const pact = h.pact;
+      h.pact = h.rmask;
+      const hipError_t e = launch_solve(h, h.kres, st);
+      h.pact = pact;
+      HIP_TRY(e);
+      HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st, h.rmask));
+      HIP_TRY(launch_axpy(h.kcor, W.sol, h.kres, 1.0, nkkt, st));
+      HIP_TRY(launch_residual(h, h.diagx, h.diags, h.kcor, W.rhs, h.kres, h.omega_d, st));
+      HIP_TRY(launch_residual_pmax(h, st));
+      hipLaunchKernelGGL(k_ctl_refine, dim3(gp), dim3(64), 0, st, g, h.pres, 1e-10);
+      HIP_TRY(launch_copy_rows(h, gs.cmask, W.sol, h.kcor, st));
+      HIP_TRY(hipGetLastError());
+      return ABS_OK;
+    }));
+    auto trial = [&]() -> int {
+      hipLaunchKernelGGL(k_trial, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.dx, W.s, W.ds, nxs, W.xtt,
+                         W.st);
+      HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
+      hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d,
+                         nxs, h.redbuf);
+      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg, Ops<3>{{0, 0, 0}},
+                         out + 7LL * P);
+      hipLaunchKernelGGL(k_ctl_ls, dim3(gp), dim3(64), 0, st, g, out + 7LL * P, C, phi_d);
+      HIP_TRY(hipGetLastError());
+      return ABS_OK;
+    };
+    GTRY(capture_graph(st, &gs.ex[G_DIR], [&]() -> int {
+      hipLaunchKernelGGL(k_direction, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.zL, W.zU, W.y, W.s,
+                         W.vU, h.diags, W.sol, b, C.kappa_d, gf, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
+                         h.redbuf);
+      hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
+                         h.redbuf + 4LL * nseg);
+      hipLaunchKernelGGL(k_seg_reduce<4>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg, Ops<4>{{2, 2, 0, 0}}, out);
+      hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(RS), 0, st, h.redbuf + 4LL * nseg, h.pseg,
+                         Ops<3>{{0, 0, 0}}, out + 4LL * P);
+      hipLaunchKernelGGL(k_ctl_dir, dim3(gp), dim3(64), 0, st, g, out, out + 4LL * P, C, phi_d);
+      return trial();
+    }));
+    GTRY(capture_graph(st, &gs.ex[G_LS], trial));
+    GTRY(capture_graph(st, &gs.ex[G_ACC], [&]() -> int {
+      hipLaunchKernelGGL(k_accept, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.xtt, W.s, W.st, W.y, W.dy,
+                         W.zL, W.dzL, W.zU, W.dzU, W.vU, W.dvU, b, C.kappa_sigma, nxs);
+      hipLaunchKernelGGL(k_ctl_accept, dim3(gp), dim3(64), 0, st, g, C, h.sc.Dd);
+      HIP_TRY(hipGetLastError());
+      return ABS_OK;
+    }));
+    gs.captured = true;
+    gs.tol = o.tol;
+    gs.dw_max = o.delta_w_max;
+    gs.max_iter = o.max_iter;
+    gs.timed = timed;
+    gs.fwpe = h.tune.factor_wpe;
+    gs.swpe = h.tune.solve_wpe;
+    gs.ebs = h.tune.eval_bs;
+  }
+  // ---- replay passes
+  auto read_status = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(gs.stat_h, gs.stat, sizeof(int2) * P, hipMemcpyDeviceToHost, st));
+    HIP_TRY(wait_stream(st));
+    return ABS_OK;
+  };
+  // a factorisation trial; timed: the factorisation is launched between the two
+  // halves of the graph, bracketed by the profiling events on the same stream
+  auto replay = [&](int k) -> hipError_t {
+    ++replays;
+    return hipGraphLaunch(gs.ex[k], st);
+  };
+  auto factor_trial = [&]() -> int {
+    ++nfact;
+    if (!timed) {
+      HIP_TRY(replay(G_FAC));
+      return ABS_OK;
+    }
+    HIP_TRY(replay(G_FAC_A));
+    HIP_TRY(launch_factor(h, h.diagx, h.diags, W.rhs, true, st));
+    HIP_TRY(replay(G_FAC_B));
+    return ABS_OK;
+  };
+  auto count_phase = [&](int lo, int hi) {
+    int n = 0;
+    for (int p = 0; p < P; ++p) n += gs.stat_h[p].y && gs.stat_h[p].x >= lo && gs.stat_h[p].x <= hi;
+    return n;
+  };
+  for (int p = 0; p < P; ++p) gs.stat_h[p] = make_int2(PH_IDLE, pr[(size_t)p].active ? 1 : 0);
+  HIP_TRY(hipMemcpyAsync(gs.stat, gs.stat_h, sizeof(int2) * P, hipMemcpyHostToDevice, st));
+  for (int iter = 0;; ++iter) {
+    // the usual iteration: one factorisation with the right inertia, no
+    // refinement correction, the first trial point accepted
+    HIP_TRY(replay(G_OPT));
+    GTRY(factor_trial());
+    HIP_TRY(replay(G_DIR));
+    HIP_TRY(replay(G_ACC));
+    GTRY(read_status());
+    // the problems that need more finish the iteration phase by phase; each
+    // replay advances every problem in that phase (a bounded number of times:
+    // delta_w grows to its bound, at most 10 corrections, alpha halves to its floor)
+    for (int pass = 0; count_phase(PH_FACTOR, PH_ACCEPT) > 0; ++pass) {
+      if (pass > 100000) {
+        set_error("ipm_solve: the iteration of a problem does not advance");
+        return ABS_ERR_STATE;
+      }
+      bool accept = count_phase(PH_ACCEPT, PH_ACCEPT) > 0;
+      if (count_phase(PH_FACTOR, PH_FACTOR)) {
+        GTRY(factor_trial());
+      } else if (count_phase(PH_REFINE, PH_REFINE)) {
+        HIP_TRY(replay(G_REF));
+      } else if (count_phase(PH_DIR, PH_DIR)) {
+        HIP_TRY(replay(G_DIR));
+        accept = true;
+      } else if (count_phase(PH_SEARCH, PH_SEARCH)) {
+        HIP_TRY(replay(G_LS));
+        accept = true;
+      }
+      if (accept) HIP_TRY(replay(G_ACC));
+      GTRY(read_status());
+    }
+    int n_active = 0;
+    for (int p = 0; p < P; ++p) n_active += gs.stat_h[p].y;
+    if (o.print_level > 0 && P > 1) fprintf(stderr, "batch iteration %4d: %d of %d problems active\n", iter, n_active, P);
+    if (n_active == 0) break;
+  }
+  // ---- final state of every problem, and the iteration logs
+  std::vector<DevProb> dp((size_t)P);
+  HIP_TRY(hipMemcpyAsync(dp.data(), gs.dp, sizeof(DevProb) * P, hipMemcpyDeviceToHost, st));
+  std::vector<absorber_ipm_log_entry> lg((size_t)log_np * log_cap);
+  HIP_TRY(hipMemcpyAsync(lg.data(), gs.log, sizeof(absorber_ipm_log_entry) * lg.size(), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int p = 0; p < P; ++p) {
+    Prob& q = pr[(size_t)p];
+    if (!q.active) continue;  // not part of this solve
+    const DevProb& d = dp[(size_t)p];
+    q.status = d.status;
+    q.it = d.it;
+    q.ncorr = d.ncorr;
+    q.E0 = d.E0;
+    q.inf_pr = d.inf_pr;
+    q.inf_du = d.inf_du;
+    q.compl0 = d.compl0;
+    q.xd = d.xd;
+    q.max_lin = d.max_lin;
+    q.active = false;
+    if (p < log_np) {
+      auto& L = h.ipm_log[(size_t)p];
+      L.clear();
+      for (int i = 0; i < std::min(d.it, log_cap); ++i) L.push_back(lg[(size_t)p * log_cap + i]);
+    }
+  }
+  return ABS_OK;
+}
+
+}  // namespace
+
+#undef GTRY
+
 // per-problem results of the segment partials in h.redbuf -> h.redbuf_h[p * K + k]
 template <int K>
 static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
@@ -774,6 +1444,16 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   const auto t_start = std::chrono::steady_clock::now();
   const Consts C;
   hipStream_t st = h.stream;
+  if (o.use_graph) {
+    // graphs are captured on a stream of their own; the caller's work on the
+    // default stream (its start point, multipliers) is complete first
+    st = ipm_graph_stream(h);
+    if (!st) {
+      set_error("ipm_solve: could not create the graph stream");
+      return ABS_ERR_HIP;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+  }
   const int P = h.P;
   const long long nx = h.nx, nc = h.nc, nst = h.nst, nkkt = h.nkkt;
   const long long nxs = nst * NV, nks = nst * NK;
@@ -964,11 +1644,13 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   }
   TRY(upload());
   h.pact_on = true;
+  int replays = 0;
+  if (o.use_graph) TRY(graph_iterations(h, o, C, b, gf, W, pr, st, nfact, replays));
   auto now = [] { return std::chrono::steady_clock::now(); };
   auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
   };
-  while (true) {
+  while (!o.use_graph) {
     const auto ph0 = now();
     int n_fac_it = 0, n_ls_it = 0;
     // ---- evaluation at (x_k, y_k): residuals, Jacobian, Hessian, Lagrangian gradient
@@ -1254,6 +1936,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     r.n_factorizations = nfact;
     r.max_lin_resid = q.max_lin;
     r.feasibility_restarts = 0;
+    r.graph_replays = replays;
   }
   return first_err;
 }
@@ -1294,6 +1977,7 @@ int solve_with_restart(Handle& h, const absorber_ipm_options& o, const double* x
         if (redo[(size_t)p]) {
           r2[(size_t)p].iterations += r1[(size_t)p].iterations;
           r2[(size_t)p].n_inertia_corrections += r1[(size_t)p].n_inertia_corrections;
+          r2[(size_t)p].graph_replays += r1[(size_t)p].graph_replays;
           r2[(size_t)p].feasibility_restarts = 1;
           r1[(size_t)p] = r2[(size_t)p];
         }
