@@ -400,6 +400,19 @@ int absorber_warm_point(absorber_t* h, const float* Y_dev, int32_t n_out, double
                         double* lambda0_dev, void* stream);
 int absorber_warm_start(absorber_t* h, absorber_mlp* net, float* X_work_dev, float* Y_work_dev, double d_margin,
                         double* x0_dev, double* lambda0_dev, void* stream);
+/* absorber_warm_start for callers that cannot allocate device memory (code
+ * being captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result, with the network inputs, its outputs and the
+ * per-problem worst-scenario index in a static device workspace of the
+ * library (32 MiB on each GPU it runs on, held until the process ends)
+ * instead of caller workspaces; it calls no allocating routine.  Requires
+ * 256-aligned S*3*4 + S*n_out*4 + P*4 bytes <= 32 MiB (5000 scenarios of a
+ * 430-output network take 8.7 MB); larger sizes return ABS_ERR_ARG with the
+ * byte counts.  Every call on one GPU shares that workspace: calls that
+ * overlap on one GPU (other threads, other streams) race.  Asynchronous on
+ * stream. */
+int absorber_warm_start_noalloc(absorber_t* h, absorber_mlp* net, double d_margin, double* x0_dev,
+                                double* lambda0_dev, void* stream);
 /* Warm-started solve with cold-start fallback: warm_start (workspaces owned by
  * the handle, allocated on the first call), then absorber_ipm_solve with
  * opts->warm_start = 1 and the predicted multipliers (primal-dual network) or

@@ -179,6 +179,7 @@ def lib():
             "absorber_warm_targets": (ctypes.c_int, [vp, vp, vp, vp, vp]),
             "absorber_warm_point": (ctypes.c_int, [vp, vp, i32, dbl, vp, vp, vp]),
             "absorber_warm_start": (ctypes.c_int, [vp, vp, vp, vp, dbl, vp, vp, vp]),
+            "absorber_warm_start_noalloc": (ctypes.c_int, [vp, vp, dbl, vp, vp, vp]),
             "absorber_warm_solve": (ctypes.c_int, [vp, vp, ctypes.POINTER(IpmOptions), dbl, vp, vp,
                                                    ctypes.POINTER(IpmResult), ctypes.POINTER(ctypes.c_int32)]),
         }
@@ -417,6 +418,11 @@ class Absorber:
     def warm_start(self, net: "Mlp", X_work, Y_work, x0, lam0=None, d_margin=1e-3, stream=None):
         _check(lib().absorber_warm_start(self.h, net.h, _ptr(X_work), _ptr(Y_work), float(d_margin), _ptr(x0),
                                          _ptr(lam0), _stream(stream)))
+
+    def warm_start_noalloc(self, net: "Mlp", x0, lam0=None, d_margin=1e-3, stream=None):
+        """absorber_warm_start with the library's static workspace (no device allocation)."""
+        _check(lib().absorber_warm_start_noalloc(self.h, net.h, float(d_margin), _ptr(x0), _ptr(lam0),
+                                                 _stream(stream)))
 
     def warm_solve(self, net: "Mlp", opts: IpmOptions | None = None, d_margin=1e-3, x_out=None, lam_out=None):
         """Warm-started solve with cold fallback; returns (result, used_warm)."""

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <chrono>
+#include <mutex>
 
 #include "internal.h"
 
@@ -120,7 +121,55 @@ __global__ void k_decode_duals(const float* __restrict__ Y, int ld, const StageI
 
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Workspace of absorber_warm_start_noalloc: the network inputs [S][3], its
+// outputs [S][n_out] and the worst scenario of each problem [P], in one
+// static device array that every GPU the library runs on holds until the
+// process ends.  Host code never passes the array's name to a kernel: it
+// keeps the array's device address, looked up once per device.
+constexpr size_t NOALLOC_BYTES = (size_t)32 << 20;
+__device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+char* scratch_ptr[MAX_DEVICES] = {};
+
+// device address of the scratch array on the current device
+int scratch_address(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("absorber_warm_start_noalloc: device index out of range");
+    return ABS_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = scratch_ptr[dev];
+  return ABS_OK;
+}
+
+inline size_t al256(size_t n) { return (n + 255) / 256 * 256; }
+
 }  // namespace
+
+// decode Y into x0 (and lambda0) with the per-problem index buffer wmax [P]
+static int warm_point(Handle& h, const float* Y_dev, int32_t n_out, double d_margin, double* x0_dev,
+                      double* lambda0_dev, int* wmax, hipStream_t st) {
+  const long long nst = h.nst;
+  double* dh = h.kden;  // per-stage scratch
+  hipLaunchKernelGGL(k_decode, dim3(nblk(nst, WB)), dim3(WB), 0, st, Y_dev, n_out, h.feeds, h.mp, h.sinfo, nst, x0_dev,
+                     dh);
+  hipLaunchKernelGGL(k_decode_d, dim3(h.P), dim3(WB), 0, st, dh, h.pstage, h.sinfo, d_margin, x0_dev + nst * NV, wmax);
+  if (lambda0_dev)
+    hipLaunchKernelGGL(k_decode_duals, dim3(nblk(nst, WB)), dim3(WB), 0, st, Y_dev, n_out, h.sinfo, nst, wmax,
+                       lambda0_dev);
+  HIP_TRY(hipGetLastError());
+  return ABS_OK;
+}
+
 }  // namespace absorber
 
 using absorber::Handle;
@@ -177,18 +226,7 @@ int absorber_warm_point(absorber_t* ah, const float* Y_dev, int32_t n_out, doubl
     return ABS_ERR_ARG;
   }
   if (!h.warm_w) HIP_TRY(hipMalloc((void**)&h.warm_w, sizeof(int) * (size_t)h.P));
-  const long long nst = h.nst;
-  hipStream_t st = (hipStream_t)stream;
-  double* dh = h.kden;  // per-stage scratch
-  hipLaunchKernelGGL(absorber::k_decode, dim3(absorber::nblk(nst, absorber::WB)), dim3(absorber::WB), 0, st, Y_dev,
-                     n_out, h.feeds, h.mp, h.sinfo, nst, x0_dev, dh);
-  hipLaunchKernelGGL(absorber::k_decode_d, dim3(h.P), dim3(absorber::WB), 0, st, dh, h.pstage, h.sinfo, d_margin,
-                     x0_dev + nst * NV, h.warm_w);
-  if (lambda0_dev)
-    hipLaunchKernelGGL(absorber::k_decode_duals, dim3(absorber::nblk(nst, absorber::WB)), dim3(absorber::WB), 0, st,
-                       Y_dev, n_out, h.sinfo, nst, h.warm_w, lambda0_dev);
-  HIP_TRY(hipGetLastError());
-  return ABS_OK;
+  return absorber::warm_point(h, Y_dev, n_out, d_margin, x0_dev, lambda0_dev, h.warm_w, (hipStream_t)stream);
 }
 
 int absorber_warm_start(absorber_t* ah, absorber_mlp* net, float* X_work_dev, float* Y_work_dev, double d_margin,
@@ -207,6 +245,45 @@ int absorber_warm_start(absorber_t* ah, absorber_mlp* net, float* X_work_dev, fl
   rc = absorber_warm_features(ah, X_work_dev, stream);
   if (!rc) rc = absorber_mlp_forward(net, X_work_dev, ah->h.S, Y_work_dev, stream);
   if (!rc) rc = absorber_warm_point(ah, Y_work_dev, cfg.n_out, d_margin, x0_dev, lambda0_dev, stream);
+  return rc;
+}
+
+int absorber_warm_start_noalloc(absorber_t* ah, absorber_mlp* net, double d_margin, double* x0_dev,
+                                double* lambda0_dev, void* stream) {
+  if (!ah || !net || !x0_dev || !(d_margin >= 0.0)) {
+    set_error("absorber_warm_start_noalloc: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Handle& h = ah->h;
+  absorber_mlp_config cfg;
+  int rc = absorber_mlp_get_config(net, &cfg);
+  if (rc) return rc;
+  bool same = true;
+  for (int n : h.pN) same = same && n == h.N;
+  const bool pd = cfg.n_out == (NV + NR) * h.N;
+  if (cfg.n_in != 3 || !same || !(cfg.n_out == NV * h.N || pd) || (lambda0_dev && !pd)) {
+    set_error("absorber_warm_start_noalloc: the network needs 3 inputs and 21 N (primal) or 43 N (primal-dual, "
+              "needed for lambda0) outputs, every problem N stages");
+    return ABS_ERR_ARG;
+  }
+  const size_t bx = absorber::al256(sizeof(float) * 3 * (size_t)h.S);
+  const size_t by = absorber::al256(sizeof(float) * (size_t)cfg.n_out * (size_t)h.S);
+  const size_t bw = absorber::al256(sizeof(int) * (size_t)h.P);
+  if (bx + by + bw > absorber::NOALLOC_BYTES) {
+    set_error("absorber_warm_start_noalloc: " + std::to_string(h.S) + " scenarios x " + std::to_string(cfg.n_out) +
+              " network outputs need " + std::to_string(bx + by + bw) + " bytes of workspace, more than its " +
+              std::to_string(absorber::NOALLOC_BYTES) + "-byte maximum (use absorber_warm_start)");
+    return ABS_ERR_ARG;
+  }
+  char* ws = nullptr;
+  rc = absorber::scratch_address(&ws);
+  if (rc) return rc;
+  float* X = reinterpret_cast<float*>(ws);
+  float* Y = reinterpret_cast<float*>(ws + bx);
+  int* wmax = reinterpret_cast<int*>(ws + bx + by);
+  rc = absorber_warm_features(ah, X, stream);
+  if (!rc) rc = absorber_mlp_forward(net, X, h.S, Y, stream);
+  if (!rc) rc = absorber::warm_point(h, Y, cfg.n_out, d_margin, x0_dev, lambda0_dev, wmax, (hipStream_t)stream);
   return rc;
 }
 
