@@ -277,19 +277,28 @@ typedef struct {
 } absorber_profile;
 int absorber_profile_enable(absorber_t* h, int32_t mask);
 
-/* Launch shapes chosen by the autotuner (absorber_ipm_options.autotune): the
- * occupancy target of the factorisation and of the stored-factor solve (waves
- * per SIMD 2, 3 or 4, which fixes each wave's register budget) and the block
- * size of the stage evaluation (64, 128 or 256), with the measured time of each
- * candidate in ms (index 0-2 in the order listed; the factorisation and the
- * solve are timed on at most the first 12288 scenario chains).  tuned = 0 until
- * the first factorisation of a solve with autotune on. */
+/* Launch shapes chosen by the autotuner (absorber_ipm_options.autotune): for
+ * the block LDL^T factorisation the occupancy target (waves per SIMD 2 or 3,
+ * which fixes each wave's register budget) and the row split of its trailing
+ * update (0: updates from rows 0/16/32 of the frontal tile, 1: from rows 0/24,
+ * 2: from rows 0/8/16/24/32/40; rows whose pivots are all eliminated are never
+ * updated again); the occupancy target of the stored-factor solve (waves per
+ * SIMD 2, 3 or 4); the block size of the stage evaluation (64, 128 or 256).
+ * The measured time of each candidate is in ms (factor_ms[waves 2, 3][split];
+ * the other arrays in the order listed; the factorisation and the solve are
+ * timed on at most the first 12288 scenario chains).  tuned = 0 until the first
+ * factorisation of a solve with autotune on. */
 typedef struct {
   int32_t tuned;
-  int32_t factor_waves_per_simd, solve_waves_per_simd, eval_block;
-  float factor_ms[3], solve_ms[3], eval_ms[3];
+  int32_t factor_waves_per_simd, factor_row_split, solve_waves_per_simd, eval_block;
+  float factor_ms[2][3], solve_ms[3], eval_ms[3];
 } absorber_tuning;
 int absorber_tuning_get(const absorber_t* h, absorber_tuning* out);
+/* Pin the launch shapes (factor_waves_per_simd 2 or 3, factor_row_split 0-2,
+ * solve_waves_per_simd 2-4, eval_block 64/128/256; the timing arrays are
+ * ignored) and mark them tuned, so the autotuner does not run; ABS_ERR_ARG for
+ * a shape outside those sets.  The shapes change the speed, not the results. */
+int absorber_tuning_set(absorber_t* h, const absorber_tuning* in);
 int absorber_profile_get(const absorber_t* h, absorber_profile* out);
 
 /* ------------------------------------------------------------------------

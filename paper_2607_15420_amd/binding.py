@@ -113,8 +113,10 @@ class MlpTrainResult(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tuned", ctypes.c_int32), ("factor_waves_per_simd", ctypes.c_int32),
+                ("factor_row_split", ctypes.c_int32),
                 ("solve_waves_per_simd", ctypes.c_int32), ("eval_block", ctypes.c_int32),
-                ("factor_ms", ctypes.c_float * 3), ("solve_ms", ctypes.c_float * 3), ("eval_ms", ctypes.c_float * 3)]
+                ("factor_ms", ctypes.c_float * 3 * 2), ("solve_ms", ctypes.c_float * 3),
+                ("eval_ms", ctypes.c_float * 3)]
 
 
 PROFILE_CLASSES = ("factor", "solve", "eval", "residual")
@@ -157,6 +159,7 @@ def lib():
             "absorber_profile_enable": (ctypes.c_int, [vp, i32]),
             "absorber_profile_get": (ctypes.c_int, [vp, ctypes.POINTER(Profile)]),
             "absorber_tuning_get": (ctypes.c_int, [vp, ctypes.POINTER(Tuning)]),
+            "absorber_tuning_set": (ctypes.c_int, [vp, ctypes.POINTER(Tuning)]),
             "absorber_last_error": (ctypes.c_char_p, []),
             "absorber_mlp_default_config": (None, [ctypes.POINTER(MlpConfig)]),
             "absorber_mlp_default_train_options": (None, [ctypes.POINTER(MlpTrainOptions)]),
@@ -372,8 +375,17 @@ class Absorber:
         t = Tuning()
         _check(lib().absorber_tuning_get(self.h, ctypes.byref(t)))
         return {"tuned": bool(t.tuned), "factor_waves_per_simd": t.factor_waves_per_simd,
+                "factor_row_split": t.factor_row_split,
                 "solve_waves_per_simd": t.solve_waves_per_simd, "eval_block": t.eval_block,
-                "factor_ms": list(t.factor_ms), "solve_ms": list(t.solve_ms), "eval_ms": list(t.eval_ms)}
+                "factor_ms": [list(r) for r in t.factor_ms], "solve_ms": list(t.solve_ms),
+                "eval_ms": list(t.eval_ms)}
+
+    def set_tuning(self, factor_waves_per_simd=3, factor_row_split=0, solve_waves_per_simd=3, eval_block=128):
+        """Pin the launch shapes (the autotuner then does not run)."""
+        t = Tuning()
+        t.factor_waves_per_simd, t.factor_row_split = factor_waves_per_simd, factor_row_split
+        t.solve_waves_per_simd, t.eval_block = solve_waves_per_simd, eval_block
+        _check(lib().absorber_tuning_set(self.h, ctypes.byref(t)))
 
     def profile(self) -> dict:
         p = Profile()

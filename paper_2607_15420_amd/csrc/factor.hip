@@ -231,16 +231,32 @@ __device__ __forceinline__ void eliminate_phase(double (&v)[FR], double* __restr
 
 
 // Eliminate the 43 own pivots of one stage.  The lowest remaining pivot only
-// grows, so the stage runs in three phases whose rank-1 updates skip the rows
-// 0-15 (then 0-31) once all their pivots are gone: those rows are never read
-// again.
+// grows, so the stage runs in phases whose rank-1 updates skip the leading rows
+// once all their pivots are gone (those rows are never read again).  The row
+// split is the tile shape of the trailing update, chosen by the autotuner:
+//   SPLIT 0: three phases, updates from rows 0, 16, 32;
+//   SPLIT 1: two phases, updates from rows 0, 24;
+//   SPLIT 2: six phases, updates from rows 0, 8, 16, 24, 32, 40.
+template <int SPLIT>
 __device__ __forceinline__ void eliminate_stage(double (&v)[FR], double* __restrict__ sb, double* bc,
                                                 int& npos, int& nneg, int& nzero) {
   uint64_t act = (1ull << NK) - 1ull;
   int slot = 0;
-  eliminate_phase<0, 16>(v, sb, bc, act, slot, npos, nneg, nzero);
-  eliminate_phase<2, 32>(v, sb, bc, act, slot, npos, nneg, nzero);
-  eliminate_phase<4, 64>(v, sb, bc, act, slot, npos, nneg, nzero);
+  if (SPLIT == 0) {
+    eliminate_phase<0, 16>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<2, 32>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<4, 64>(v, sb, bc, act, slot, npos, nneg, nzero);
+  } else if (SPLIT == 1) {
+    eliminate_phase<0, 24>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<3, 64>(v, sb, bc, act, slot, npos, nneg, nzero);
+  } else {
+    eliminate_phase<0, 8>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<1, 16>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<2, 24>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<3, 32>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<4, 40>(v, sb, bc, act, slot, npos, nneg, nzero);
+    eliminate_phase<5, 64>(v, sb, bc, act, slot, npos, nneg, nzero);
+  }
 }
 
 // Backward sweep of one stage for two right-hand sides.  The stage's pivot
@@ -411,7 +427,7 @@ __device__ __forceinline__ void backward_rows(const double* __restrict__ sb, con
   }
 }
 
-template <int WITH_RHS, int WPE>
+template <int SPLIT, int WPE>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_factor(
     const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
     const double* __restrict__ diagx, const double* __restrict__ diags, const double* __restrict__ dwv,
@@ -436,7 +452,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     double v[FR];
     for (int i = lane; i < REC; i += WAVE) L.src[SRC_REC + i] = R[i];
     if (lane < NJD) L.src[SRC_DOWN1 + lane] = (n < N - 1) ? rec[(t + 1) * REC + REC_DOWN + lane] : 0.0;
-    if (lane < NK) L.src[SRC_RHS + lane] = WITH_RHS ? rhs[t * NK + lane] : 0.0;
+    if (lane < NK) L.src[SRC_RHS + lane] = rhs ? rhs[t * NK + lane] : 0.0;
     if (lane < NV) L.src[SRC_DIAGX + lane] = diagx[t * NV + lane] + dw;
     if (lane == 0) {
       L.src[SRC_BRD] = R[jd];
@@ -454,7 +470,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    eliminate_stage(v, slots + t * NK * SLOT, L.bc, npos, nneg, nzero);
+    eliminate_stage<SPLIT>(v, slots + t * NK * SLOT, L.bc, npos, nneg, nzero);
     // contribution block to stage n+1 (rows/cols 43..60 of the coupling lanes)
     if (lane >= NK && lane < NK + NC) {
       const int a = lane - NK;
@@ -699,17 +715,18 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
   const int* fm = mask ? h.fmask : nullptr;
   const int nw = nchain < 0 || nchain > h.S ? h.S : nchain;
   prof_begin(h, 0, st);
-#define ABS_FACTOR(R, W)                                                                                    \
-  hipLaunchKernelGGL((k_factor<R, W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
+#define ABS_FACTOR(S, W)                                                                                    \
+  hipLaunchKernelGGL((k_factor<S, W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
                      h.dcv, h.chain0, h.chain_p, fm, nw, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part)
-  const int wpe = h.tune.factor_wpe;
-  if (rhs) {
-    if (wpe == 2) ABS_FACTOR(1, 2);
-    else if (wpe == 4) ABS_FACTOR(1, 4);
-    else ABS_FACTOR(1, 3);
+  // launch shape: occupancy target (waves per SIMD 2 or 3) and row split of the update
+  const int wpe = h.tune.factor_wpe, split = h.tune.factor_split;
+  if (wpe == 2) {
+    if (split == 1) ABS_FACTOR(1, 2);
+    else if (split == 2) ABS_FACTOR(2, 2);
+    else ABS_FACTOR(0, 2);
   } else {
-    if (wpe == 2) ABS_FACTOR(0, 2);
-    else if (wpe == 4) ABS_FACTOR(0, 4);
+    if (split == 1) ABS_FACTOR(1, 3);
+    else if (split == 2) ABS_FACTOR(2, 3);
     else ABS_FACTOR(0, 3);
   }
 #undef ABS_FACTOR

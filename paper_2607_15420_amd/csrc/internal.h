@@ -91,9 +91,10 @@ struct Scaling {
 
 // launch shapes picked by measurement (autotune)
 struct Tune {
-  int factor_wpe = 3, solve_wpe = 3, eval_bs = 128;
+  int factor_wpe = 3, factor_split = 0, solve_wpe = 3, eval_bs = 128;
   bool done = false;
-  float ms_factor[3] = {0, 0, 0}, ms_solve[3] = {0, 0, 0}, ms_eval[3] = {0, 0, 0};
+  float ms_factor[2][3] = {{0, 0, 0}, {0, 0, 0}};  // [waves per SIMD 2, 3][row split 0-2]
+  float ms_solve[3] = {0, 0, 0}, ms_eval[3] = {0, 0, 0};
 };
 
 // all per-handle device and host state

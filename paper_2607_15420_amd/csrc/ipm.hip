@@ -1002,7 +1002,7 @@ struct GraphState {
   bool captured = false;
   // what the captured launches depend on besides the handle's fixed buffers
   double tol = 0, dw_max = 0;
-  int max_iter = -1, timed = -1, fwpe = -1, swpe = -1, ebs = -1;
+  int max_iter = -1, timed = -1, fwpe = -1, fsplit = -1, swpe = -1, ebs = -1;
   char* dev = nullptr;
   size_t dev_bytes = 0;
   DevProb* dp = nullptr;
@@ -1132,7 +1132,8 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
   // ---- capture (again when the options, the launch shapes or the timing changed)
   if (o.autotune && !h.tune.done) GTRY(autotune(h, W.xt, W.y, W.c, h.diagx, h.diags, W.rhs, st));
   if (!gs.captured || gs.tol != o.tol || gs.dw_max != o.delta_w_max || gs.max_iter != o.max_iter ||
-      gs.timed != timed || gs.fwpe != h.tune.factor_wpe || gs.swpe != h.tune.solve_wpe ||
+      gs.timed != timed || gs.fwpe != h.tune.factor_wpe || gs.fsplit != h.tune.factor_split ||
+      gs.swpe != h.tune.solve_wpe ||
       gs.ebs != h.tune.eval_bs) {
     gs.captured = false;
     const int prof = h.prof;
@@ -1234,6 +1235,7 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
     gs.max_iter = o.max_iter;
     gs.timed = timed;
     gs.fwpe = h.tune.factor_wpe;
+    gs.fsplit = h.tune.factor_split;
     gs.swpe = h.tune.solve_wpe;
     gs.ebs = h.tune.eval_bs;
   }
@@ -2065,13 +2067,31 @@ int absorber_tuning_get(const absorber_t* H, absorber_tuning* out) {
   const Tune& t = H->h.tune;
   out->tuned = t.done;
   out->factor_waves_per_simd = t.factor_wpe;
+  out->factor_row_split = t.factor_split;
   out->solve_waves_per_simd = t.solve_wpe;
   out->eval_block = t.eval_bs;
   for (int i = 0; i < 3; ++i) {
-    out->factor_ms[i] = t.ms_factor[i];
+    out->factor_ms[0][i] = t.ms_factor[0][i];
+    out->factor_ms[1][i] = t.ms_factor[1][i];
     out->solve_ms[i] = t.ms_solve[i];
     out->eval_ms[i] = t.ms_eval[i];
   }
+  return ABS_OK;
+}
+
+int absorber_tuning_set(absorber_t* H, const absorber_tuning* in) {
+  if (!H || !in || (in->factor_waves_per_simd != 2 && in->factor_waves_per_simd != 3) || in->factor_row_split < 0 ||
+      in->factor_row_split > 2 || in->solve_waves_per_simd < 2 || in->solve_waves_per_simd > 4 ||
+      (in->eval_block != 64 && in->eval_block != 128 && in->eval_block != 256)) {
+    set_error("absorber_tuning_set: bad argument");
+    return ABS_ERR_ARG;
+  }
+  Tune& t = H->h.tune;
+  t.factor_wpe = in->factor_waves_per_simd;
+  t.factor_split = in->factor_row_split;
+  t.solve_wpe = in->solve_waves_per_simd;
+  t.eval_bs = in->eval_block;
+  t.done = true;
   return ABS_OK;
 }
 

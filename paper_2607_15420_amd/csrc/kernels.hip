@@ -563,19 +563,28 @@ int autotune(Handle& h, const double* x, const double* y, double* c, const doubl
   // wave slots at 3 waves/SIMD): enough for the steady state, and the tuning of a
   // large batch then costs a fraction of one factorisation per candidate.
   constexpr int TUNE_CHAINS = 4 * 3 * 4 * 256;
+  // block LDL^T launch shapes: occupancy target x row split of the trailing update
   const int wpes[3] = {2, 3, 4};
-  for (int i = 0; i < 3; ++i) {
-    h.tune.factor_wpe = wpes[i];
-    h.tune.ms_factor[i] =
-        time_launch(st, e0, e1, [&] { (void)launch_factor(h, diagx, diags, rhs, false, st, TUNE_CHAINS); });
-  }
+  int best_w = 1, best_s = 0;
+  for (int i = 0; i < 2; ++i)
+    for (int k = 0; k < 3; ++k) {
+      h.tune.factor_wpe = wpes[i];
+      h.tune.factor_split = k;
+      h.tune.ms_factor[i][k] =
+          time_launch(st, e0, e1, [&] { (void)launch_factor(h, diagx, diags, rhs, false, st, TUNE_CHAINS); });
+      if (h.tune.ms_factor[i][k] < h.tune.ms_factor[best_w][best_s]) {
+        best_w = i;
+        best_s = k;
+      }
+    }
   for (int i = 0; i < 3; ++i) {
     h.tune.solve_wpe = wpes[i];
     h.tune.ms_solve[i] = time_launch(st, e0, e1, [&] { (void)launch_solve(h, rhs, st, TUNE_CHAINS); });
   }
   auto argmin = [](const float* v) { return v[0] <= v[1] ? (v[0] <= v[2] ? 0 : 2) : (v[1] <= v[2] ? 1 : 2); };
   h.tune.eval_bs = bss[argmin(h.tune.ms_eval)];
-  h.tune.factor_wpe = wpes[argmin(h.tune.ms_factor)];
+  h.tune.factor_wpe = wpes[best_w];
+  h.tune.factor_split = best_s;
   h.tune.solve_wpe = wpes[argmin(h.tune.ms_solve)];
   h.tune.done = true;
   h.prof = prof;

@@ -274,3 +274,47 @@ def test_primal_dual_network_from_batched_single_scenario_solves(params):
     print(f"primal-dual warm {rw.iterations} iterations, cold {rc_.iterations}; train loss {tr.final_loss:.2e}")
     h.close()
     net.close()
+
+
+# ---------------------------------------------------------------- the deployed shape
+# the benchmarked warm-start network: 3 inputs, 3 hidden layers of 256, 430 outputs
+# (43 per stage at 10 stages, padded to 448 columns on the device), 512-row chunks
+DEPLOYED = dict(n_in=3, n_hidden=256, n_layers=3, n_out=430)
+
+
+def test_forward_matches_oracle_at_the_deployed_shape():
+    net, ps = _net(**DEPLOYED, seed=31, max_batch=512)
+    rng = np.random.default_rng(32)
+    im, isd = np.array([10.0, 0.12, 313.0]), np.array([1.2, 0.014, 36.0])
+    om, osd = rng.standard_normal(430) * 2, rng.uniform(0.1, 3.0, 430)
+    net.set_normalization(im, isd, om, osd)
+    B = 1100  # three chunks of 512, the last one ragged
+    X = im + isd * rng.standard_normal((B, 3))
+    Y = torch.empty((B, 430), dtype=torch.float32, device=DEV)
+    net.forward(_f32(X), Y)
+    torch.cuda.synchronize()
+    Xs = ((X - im.astype(np.float32)) / isd.astype(np.float32)).astype(np.float32).astype(np.float64)
+    Yo, _ = O.forward(ps, Xs, quantize=True)
+    Yo = Yo * osd.astype(np.float32) + om.astype(np.float32)
+    Yd = Y.cpu().numpy()
+    assert np.isfinite(Yd).all()
+    assert np.abs(Yd - Yo).max() <= 5e-3 * np.abs(Yo).max()
+    net.close()
+
+
+def test_loss_grad_matches_oracle_at_the_deployed_shape():
+    net, ps = _net(**DEPLOYED, seed=33, max_batch=512)
+    rng = np.random.default_rng(34)
+    B = 512
+    X = rng.standard_normal((B, 3)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((B, 430)).astype(np.float32).astype(np.float64)
+    g = torch.empty(net.n_params, dtype=torch.float32, device=DEV)
+    loss = net.loss_grad(_f32(X), _f32(T), g)
+    lo, go = O.loss_and_grads(ps, X, T, quantize=True)
+    assert loss == pytest.approx(lo, rel=2e-3)
+    gg = _unflat(g.cpu().numpy(), ps)
+    for l, ((gW, gb), (oW, ob)) in enumerate(zip(gg, go)):
+        for a, b_ in ((gW, oW), (gb, ob)):
+            assert np.linalg.norm(a - b_) <= 2e-2 * np.linalg.norm(b_), l
+            assert np.abs(a - b_).max() <= 2e-2 * np.abs(b_).max(), l
+    net.close()
