@@ -432,13 +432,24 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
     const double* __restrict__ diagx, const double* __restrict__ diags, const double* __restrict__ dwv,
     const double* __restrict__ dcv, const int* __restrict__ chain0, const int* __restrict__ chain_p,
-    const int* __restrict__ fmask, int W, int jd, double* __restrict__ slots, double* __restrict__ solr,
-    double* __restrict__ solb, int* __restrict__ inert, double* __restrict__ part) {
+    const int* __restrict__ fmask, const int* __restrict__ chmask, int W, int jd, double* __restrict__ slots,
+    double* __restrict__ solr, double* __restrict__ solb, int* __restrict__ inert, double* __restrict__ part) {
   __shared__ WaveLDS L;
   const int w = blockIdx.x;
   if (w >= W) return;
   const int pw = chain_p[w];
   if (fmask && !fmask[pw]) return;  // this problem keeps its factorisation
+  if (chmask && !chmask[w]) {       // chain left out: zero solutions and partial sums
+    for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE) {
+      solr[i] = 0.0;
+      solb[i] = 0.0;
+    }
+    if (threadIdx.x < 4) {
+      part[(long long)w * 4 + threadIdx.x] = 0.0;
+      inert[w * 4 + threadIdx.x] = 0;
+    }
+    return;
+  }
   const long long t0 = chain0[w];
   const int N = chain0[w + 1] - (int)t0;
   const double dw = dwv[pw], dc = dcv[pw];
@@ -460,14 +471,21 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       L.src[SRC_DHYD] = -(1.0 / (diags[t] + dw) + dc);
     }
     __syncthreads();
-    // keep the table loads inside the stage loop (hoisting them would pin ~120 registers)
-    const int* gt = gather;
+    // keep the table loads inside the stage loop (hoisting them would pin ~120
+    // registers); the pointer keeps its global address space, so the loads are
+    // global loads issued eight at a time before their LDS gathers
+    typedef const __attribute__((address_space(1))) int gint;
+    gint* gt = (gint*)gather;
     __asm__ volatile("" : "+s"(gt));
 #pragma unroll
-    for (int i = 0; i < FR; ++i) {
-      const int g = gt[i * WAVE + lane];
-      v[i] = L.src[g & 1023] + L.src[(g >> 10) & 1023] + L.src[(g >> 20) & 1023];
-      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    for (int i0 = 0; i0 < FR; i0 += 8) {
+      int g[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g[j] = i0 + j < FR ? gt[(i0 + j) * WAVE + lane] : 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (i0 + j < FR) v[i0 + j] = L.src[g[j] & 1023] + L.src[(g[j] >> 10) & 1023] + L.src[(g[j] >> 20) & 1023];
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     eliminate_stage<SPLIT>(v, slots + t * NK * SLOT, L.bc, npos, nneg, nzero);
@@ -524,12 +542,12 @@ template <int WPE>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
                                                 const double* __restrict__ rhs, const int* __restrict__ chain0,
                                                 const int* __restrict__ chain_p, const int* __restrict__ pact,
-                                                int W, int jd, double* __restrict__ solr,
-                                                double* __restrict__ part) {
+                                                const int* __restrict__ chmask, int W, int jd,
+                                                double* __restrict__ solr, double* __restrict__ part) {
   __shared__ double sh[WAVE];
   const int w = blockIdx.x;
   if (w >= W) return;
-  if (pact && !pact[chain_p[w]]) {  // problem not being worked on: zero solution
+  if ((pact && !pact[chain_p[w]]) || (chmask && !chmask[w])) {  // not worked on: zero solution
     if (threadIdx.x == 0) part[(long long)w * 4 + 1] = 0.0;
     for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE)
       solr[i] = 0.0;
@@ -717,7 +735,8 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
   prof_begin(h, 0, st);
 #define ABS_FACTOR(S, W)                                                                                    \
   hipLaunchKernelGGL((k_factor<S, W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
-                     h.dcv, h.chain0, h.chain_p, fm, nw, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, h.part)
+                     h.dcv, h.chain0, h.chain_p, fm, h.chmask, nw, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, \
+                     h.part)
   // launch shape: occupancy target (waves per SIMD 2 or 3) and row split of the update
   const int wpe = h.tune.factor_wpe, split = h.tune.factor_split;
   if (wpe == 2) {
@@ -741,8 +760,8 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
   prof_begin(h, 1, st);
   const int* pa = h.pact_on ? h.pact : nullptr;
 #define ABS_SOLVE(W)                                                                                           \
-  hipLaunchKernelGGL((k_solve<W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, nw, \
-                     h.jac_d_index, h.solr, h.part)
+  hipLaunchKernelGGL((k_solve<W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, \
+                     h.chmask, nw, h.jac_d_index, h.solr, h.part)
   if (h.tune.solve_wpe == 2) ABS_SOLVE(2);
   else if (h.tune.solve_wpe == 4) ABS_SOLVE(4);
   else ABS_SOLVE(3);

@@ -127,6 +127,8 @@ struct Handle {
   int* pact = nullptr;                       // device [P] problems the per-stage kernels work on
   char* slot_area = nullptr;                 // device [P][CTL_SLOT] the solver's per-problem scalars
   bool pact_on = false;                      // false: every problem
+  int* chmask = nullptr;                     // device [chains] or null: chains the factorisation and the
+                                             // stored-factor solve work on (the others get zero solutions)
   // batched refinement: per-problem max |res| and max |rhs| of the last residual,
   // and the problems a correction is computed for (the others are converged)
   double* pres = nullptr;                    // device [2P]

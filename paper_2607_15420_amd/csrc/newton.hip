@@ -37,14 +37,17 @@ inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs)
 
 // Newton right-hand side in KKT layout: 0 for primals, hydraulic duals and the
 // d's, -c~ for the MESH rows
-__global__ void k_newton_rhs(const double* __restrict__ c, long long nks, long long nkkt, double* __restrict__ rhs) {
+// Newton right-hand side -F on the MESH rows; zero on the chains whose mask entry is 0
+__global__ void k_newton_rhs(const double* __restrict__ c, const int* __restrict__ chmask,
+                             const StageInfo* __restrict__ sinfo, long long nks, long long nkkt,
+                             double* __restrict__ rhs) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nkkt) return;
   double v = 0.0;
   if (i < nks) {
     const long long t = i / NK;
     const int k = (int)(i % NK);
-    if (k >= NV && k < NV + NE) v = -c[t * NR + (k - NV)];
+    if (k >= NV && k < NV + NE && chmask[sinfo[t].w]) v = -c[t * NR + (k - NV)];
   }
   rhs[i] = v;
 }
@@ -190,9 +193,11 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
   double *aw_h, *st_h;
   HIP_TRY(B.h(&aw_h, W));
   HIP_TRY(B.h(&st_h, 2LL * W));
-  int *src, *src_h;
+  int *src, *src_h, *cm, *cm_h;
   HIP_TRY(B.d(&src, W));
   HIP_TRY(B.h(&src_h, W));
+  HIP_TRY(B.d(&cm, W));
+  HIP_TRY(B.h(&cm_h, W));
   std::vector<int> wp((size_t)W);  // problem of each chain
   for (int p = 0; p < P; ++p)
     for (long long w = h.pchain_h[(size_t)p]; w < h.pchain_h[(size_t)p + 1]; ++w) wp[(size_t)w] = p;
@@ -204,7 +209,10 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
   HIP_TRY(hipMemcpyAsync(h.fmask, pm_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
   struct PactGuard {
     Handle& h;
-    ~PactGuard() { h.pact_on = false; }
+    ~PactGuard() {
+      h.pact_on = false;
+      h.chmask = nullptr;
+    }
   } pact_guard{h};
   h.pact_on = true;
   // scaling as in the interior-point method: variables by the cold point,
@@ -233,12 +241,18 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
       bool any = false;
       for (int w = 0; w < W; ++w) any = any || (wanted(w) && !(nr[(size_t)w] <= tol));
       if (!any) break;
-      hipLaunchKernelGGL(k_newton_rhs, dim3(nblk(nkkt, BS)), dim3(BS), 0, st, c, nks, nkkt, rhs);
+      // only the chains still iterating are factorised and solved: the others
+      // take a zero step
+      for (int w = 0; w < W; ++w) cm_h[w] = wanted(w) && !(nr[(size_t)w] <= tol) ? 1 : 0;
+      HIP_TRY(hipMemcpyAsync(cm, cm_h, sizeof(int) * W, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_newton_rhs, dim3(nblk(nkkt, BS)), dim3(BS), 0, st, c, cm, h.sinfo, nks, nkkt, rhs);
+      h.chmask = cm;
       HIP_TRY(launch_factor(h, h.diagx, h.diags, rhs, true, st));
       HIP_TRY(launch_schur(h, h.diagx, rhs, 1, sol, st));
       double rel = 0.0;
       {
         const int rc = kkt_solve_refined(h, rhs, sol, true, &rel, st);
+        h.chmask = nullptr;
         if (rc) return rc;
       }
       hipLaunchKernelGGL(k_primal_of, dim3(nblk(nx, BS)), dim3(BS), 0, st, sol, nxs, nx, nks, dx);
