@@ -24,7 +24,11 @@ no second-order correction, no restoration phase (a failed line search returns
 status LS_FAIL), no watchdog.
 
 Problem form.  Variables w = (z_1..z_S, d) with bounds; the hydraulic rows
-g(w) <= 0 become g(w) - s = 0 with a slack s <= 0 (upper bound 0).
+g(w) <= 0 become g(w) - s = 0 with a slack s <= 0 (upper bound 0).  With
+n_sections = p > 1 the shared design variables are the diameters theta_1..p of
+p contiguous column sections (the general design vector of the scenario NLP,
+eq. 8): each stage's hydraulic row uses its section's diameter and the design
+cost is sum_k (N_k / N) theta_k, N_k the stages of section k.
 """
 
 from __future__ import annotations
@@ -105,18 +109,21 @@ class IpmResult:
     log: list = field(default_factory=list)
     n_inertia_corrections: int = 0
     max_lin_resid: float = 0.0
+    theta: np.ndarray | None = None  # the p design variables (theta = [d] for one diameter)
 
 
 class Problem:
     """Problem (10) for S scenarios and N stages, with the oracle's model."""
 
-    def __init__(self, params: dict, feeds: np.ndarray, n_stages: int):
+    def __init__(self, params: dict, feeds: np.ndarray, n_stages: int, n_sections: int = 1):
         self.P = M.OracleParams(params)
         self.p = params
         self.feeds = np.ascontiguousarray(feeds, dtype=np.float64)
         self.S, self.N = self.feeds.shape[0], int(n_stages)
+        self.npar = int(n_sections)
+        self.c = M.section_weights(self.N, self.npar)  # design-cost weight of each diameter
         self.nz = self.S * self.N * M.NV
-        self.n = self.nz + 1
+        self.n = self.nz + self.npar
         self.mI = self.S * self.N
         self.mE = self.S * self.N * (M.NR - 1)
         self._bounds()
@@ -130,8 +137,8 @@ class Problem:
         lo[M.IL], hi[M.IL] = b["L"]
         lo[M.IV], hi[M.IV] = b["V"]
         lo[M.IT], hi[M.IT] = b["T"]
-        self.xL = np.concatenate([np.tile(lo, self.S * self.N), [b["d"][0]]])
-        self.xU = np.concatenate([np.tile(hi, self.S * self.N), [b["d"][1]]])
+        self.xL = np.concatenate([np.tile(lo, self.S * self.N), np.full(self.npar, b["d"][0])])
+        self.xU = np.concatenate([np.tile(hi, self.S * self.N), np.full(self.npar, b["d"][1])])
 
     def initial_point(self) -> np.ndarray:
         """The cold-start point: every stage starts from the lean-solvent liquid,
@@ -142,11 +149,13 @@ class Problem:
         z[9:13] = ip["y"]
         z[M.IL], z[M.IV], z[M.IT] = ip["L"], ip["V"], ip["T"]
         z[M.IE:M.IE + 5] = ip["eps"]
-        return np.concatenate([np.tile(z, self.S * self.N), [ip["d"]]])
+        return np.concatenate([np.tile(z, self.S * self.N), np.full(self.npar, ip["d"])])
 
     # --- model evaluations on the full vector -------------------------------------------
     def split(self, x):
-        return x[:self.nz].reshape(self.S, self.N, M.NV), float(x[self.nz])
+        """States (S, N, 21) and the design: the diameter, or the (p,) section diameters."""
+        Z = x[:self.nz].reshape(self.S, self.N, M.NV)
+        return Z, (float(x[self.nz]) if self.npar == 1 else np.array(x[self.nz:]))
 
     def cons(self, x):
         Z, d = self.split(x)
@@ -192,7 +201,10 @@ class OracleIPM:
             g = np.abs(J).max(axis=1).reshape(pr.N, M.NR)
             cs[w] = np.minimum(1.0, o.nlp_scaling_max_gradient / np.maximum(g, 1e-300))
         self.cs = cs
-        self.sf = min(1.0, o.nlp_scaling_max_gradient / self.D[-1])  # grad f = e_d
+        if pr.npar == 1:
+            self.sf = min(1.0, o.nlp_scaling_max_gradient / self.D[-1])  # grad f = e_d
+        else:  # grad f = the section weights c in the original variables
+            self.sf = min(1.0, o.nlp_scaling_max_gradient / float(np.max(pr.c * self.D[-pr.npar:])))
 
     def push_into_bounds(self, x, push, frac):
         """A-1 bound push: move x strictly inside [xL, xU] (Ipopt's kappa_1, kappa_2 rule)."""
@@ -215,12 +227,15 @@ class OracleIPM:
 
     def grad_f(self):
         g = np.zeros(self.pr.n)
-        g[-1] = self.sf * self.D[-1]
+        if self.pr.npar == 1:
+            g[-1] = self.sf * self.D[-1]
+        else:
+            g[-self.pr.npar:] = self.sf * self.D[-self.pr.npar:] * self.pr.c
         return g
 
     def block_scale(self, w):
         nzs = self.pr.N * M.NV
-        return np.concatenate([self.D[w * nzs:(w + 1) * nzs], self.D[-1:]])
+        return np.concatenate([self.D[w * nzs:(w + 1) * nzs], self.D[-self.pr.npar:]])
 
     def jac_scaled(self, x):
         out = []
@@ -231,12 +246,13 @@ class OracleIPM:
     def JT_times(self, Jb, yc, yd):
         """J^T y for the full vector, from per-scenario blocks."""
         pr = self.pr
+        q = pr.npar
         r = np.zeros(pr.n)
         for w, J in enumerate(Jb):
             lam = np.concatenate([yc[w], yd[w][:, None]], axis=1).reshape(-1)
             v = J.T @ lam
-            r[w * pr.N * M.NV:(w + 1) * pr.N * M.NV] += v[:-1]
-            r[-1] += v[-1]
+            r[w * pr.N * M.NV:(w + 1) * pr.N * M.NV] += v[:-q]
+            r[-q:] += v[-q:]
         return r
 
     def J_times(self, Jb, dx):
@@ -244,7 +260,7 @@ class OracleIPM:
         cE = np.empty((pr.S, pr.N, M.NR - 1))
         dI = np.empty((pr.S, pr.N))
         for w, J in enumerate(Jb):
-            v = J @ np.concatenate([dx[w * pr.N * M.NV:(w + 1) * pr.N * M.NV], [dx[-1]]])
+            v = J @ np.concatenate([dx[w * pr.N * M.NV:(w + 1) * pr.N * M.NV], dx[-pr.npar:]])
             v = v.reshape(pr.N, M.NR)
             cE[w], dI[w] = v[:, :M.NR - 1], v[:, M.NR - 1]
         return cE, dI
@@ -259,7 +275,8 @@ class OracleIPM:
         sL, sU = self.slacks(x)
         if np.any(sL[self.hasL] <= 0) or np.any(sU[self.hasU] <= 0) or np.any(s >= 0):
             return np.inf
-        phi = self.sf * x[-1]
+        q = self.pr.npar
+        phi = self.sf * x[-1] if q == 1 else self.sf * float((self.pr.c * self.D[-q:]) @ x[-q:])
         phi -= mu * (np.log(sL[self.hasL]).sum() + np.log(sU[self.hasU]).sum() + np.log(-s).sum())
         phi += self.o.kappa_d * mu * (sL[self.onlyL].sum() + sU[self.onlyU].sum() + (-s).sum())
         return phi
@@ -299,27 +316,33 @@ class OracleIPM:
         pr = self.pr
         lam = np.concatenate([yc, yd[:, :, None]], axis=2) * self.cs  # unscaled-row weights
         Hb = pr.hess_blocks(self.D * x, lam)
-        blocks, borders, kdd = [], [], 0.0
+        q = pr.npar
+        blocks, borders, kdd = [], [], 0.0 if q == 1 else np.zeros((q, q))
         for w in range(pr.S):
             bs = self.block_scale(w)
             Hb[w] = Hb[w] * bs[:, None] * bs[None, :]
             sl = slice(w * pr.N * M.NV, (w + 1) * pr.N * M.NV)
-            K, b, hdd = scenario_kkt(Jb[w], Hb[w], sig_x[sl], sig_s[w], dw, dc, pr.N)
+            K, b, hdd = scenario_kkt(Jb[w], Hb[w], sig_x[sl], sig_s[w], dw, dc, pr.N, q)
             blocks.append(K)
             borders.append(b)
-            kdd += hdd
-        kdd += sig_x[-1] + dw
+            kdd = kdd + hdd
+        if q == 1:
+            kdd += sig_x[-1] + dw
+        else:
+            kdd = kdd + np.diag(sig_x[-q:] + dw)
         return BorderedKKT(blocks, borders, kdd)
 
     def kkt_solve(self, F, rx, rc, rd):
         """Solve K [dx; dyc; dyd] = [rx; rc; rd] (reduced system), returns full vectors."""
         pr = self.pr
         nzs = pr.N * M.NV
+        q = pr.npar
         rs = []
         for w in range(pr.S):
             rs.append(np.concatenate([rx[w * nzs:(w + 1) * nzs], rc[w].reshape(-1), rd[w]]))
-        sol, dd = F.solve(rs, rx[-1])
-        self.max_lin_resid = max(self.max_lin_resid, F.rel_residual(sol, dd, rs, rx[-1]))
+        rth = rx[-1] if q == 1 else rx[-q:]
+        sol, dd = F.solve(rs, rth)
+        self.max_lin_resid = max(self.max_lin_resid, F.rel_residual(sol, dd, rs, rth))
         dx = np.empty(pr.n)
         dyc = np.empty((pr.S, pr.N, M.NR - 1))
         dyd = np.empty((pr.S, pr.N))
@@ -329,7 +352,10 @@ class OracleIPM:
             dx[w * nzs:(w + 1) * nzs] = u[:nzs]
             dyc[w] = u[nzs:nzs + nE].reshape(pr.N, M.NR - 1)
             dyd[w] = u[nzs + nE:]
-        dx[-1] = dd
+        if q == 1:
+            dx[-1] = dd
+        else:
+            dx[-q:] = dd
         return dx, dyc, dyd
 
     # ---- fraction to boundary ----
@@ -449,7 +475,7 @@ class OracleIPM:
                 dw_trials.append(dw)
                 if self.on_factor is not None:
                     self.on_factor(F, dw, dc)
-                want = (pr.n, pr.mE + pr.mI, 0)
+                want = (pr.n, pr.mE + pr.mI, 0)  # n counts the p design variables
                 if F.inertia == want:
                     if dw > 0:
                         dw_last = dw
@@ -551,10 +577,12 @@ class OracleIPM:
                 break
         x = self.D * x
         return IpmResult(status, it, float(E0), float(x[-1]), x, yc, yd, zL / self.D, zU / self.D, s, vU,
-                         time.perf_counter() - t0, log, self.n_inertia_corr, self.max_lin_resid)
+                         time.perf_counter() - t0, log, self.n_inertia_corr, self.max_lin_resid,
+                         np.array(x[-pr.npar:]))
 
 
-def solve(params, feeds, n_stages, opts=None, verbose=False, x0=None, yc0=None, yd0=None, on_factor=None):
+def solve(params, feeds, n_stages, opts=None, verbose=False, x0=None, yc0=None, yd0=None, on_factor=None,
+          n_sections=1):
     torch.set_num_threads(1)
-    prob = Problem(params, feeds, n_stages)
+    prob = Problem(params, feeds, n_stages, n_sections)
     return OracleIPM(prob, opts, verbose, on_factor).solve(x0, yc0, yd0)

@@ -73,17 +73,32 @@ class OracleParams:
         self.raw = p
 
 
+def sections(n_stages: int, n_sections: int) -> np.ndarray:
+    """Section of every stage (0 = bottom) for a column cut into n_sections
+    contiguous sections of near-equal height: stage n is in section n p // N."""
+    return np.array([(n * n_sections) // n_stages for n in range(n_stages)], dtype=np.int64)
+
+
+def section_weights(n_stages: int, n_sections: int) -> np.ndarray:
+    """Weight of each section diameter in the design cost: its share of the stages
+    (the shell of a section scales with its height times its diameter)."""
+    return np.bincount(sections(n_stages, n_sections), minlength=n_sections) / float(n_stages)
+
+
 def _h(T, href, a, b, Tref):
     """Component molar enthalpy h(T) = href + int_Tref^T (a + b t) dt, for T (...,)."""
     T = T[..., None]
     return href + a * (T - Tref) + 0.5 * b * (T * T - Tref * Tref)
 
 
-def scenario_constraints(Z: torch.Tensor, d: torch.Tensor, feed: torch.Tensor, P: OracleParams) -> torch.Tensor:
+def scenario_constraints(Z: torch.Tensor, d: torch.Tensor, feed: torch.Tensor, P: OracleParams,
+                         sec: torch.Tensor | None = None) -> torch.Tensor:
     """All 22 rows of every stage of one scenario.
 
     Z: (N, 21) free variables, stages bottom (index 0) to top; d: scalar tensor
-    (the diameter); feed: (18,) feed-table row.  Returns (N, 22).
+    (the diameter), or with sec the (p,) section diameters theta and sec (N,)
+    the section of each stage (general design vector of the scenario NLP);
+    feed: (18,) feed-table row.  Returns (N, 22).
     """
     x, y = Z[:, 0:NLIQ], Z[:, NLIQ:NLIQ + NVAP]
     L, V, T, eps = Z[:, IL], Z[:, IV], Z[:, IT], Z[:, IE:IE + 5]
@@ -129,48 +144,68 @@ def scenario_constraints(Z: torch.Tensor, d: torch.Tensor, feed: torch.Tensor, P
     hV = lambda yy, TT: (yy * _h(TT, P.hV_ref, P.cpV_a, P.cpV_b, P.Tref)).sum(dim=-1)  # noqa: E731
     eb = L * hL(x, T) + V * hV(y, T) - L_up * hL(x_up, T_up) - V_dn * hV(y_dn, T_dn)
 
-    # (10b) hydraulic: volumetric gas flow against the velocity limit
-    hyd = V * P.R * T / Pabs - P.u_max * math.pi * d * d / 4.0
+    # (10b) hydraulic: volumetric gas flow against the velocity limit of the
+    # stage's own diameter
+    dn = d if sec is None else d[sec]
+    hyd = V * P.R * T / Pabs - P.u_max * math.pi * dn * dn / 4.0
 
     return torch.cat([mb, rx, sl[:, None], sv[:, None], vle_w[:, None], vle_c[:, None],
                       eb[:, None], hyd[:, None]], dim=1)
 
 
-def _flat(P, feed, N):
+def _design(d):
+    """Design variables as a 1-D float64 array: (1,) for a scalar diameter, (p,) for sections."""
+    return np.atleast_1d(np.asarray(d, dtype=np.float64))
+
+
+def _flat(P, feed, N, p=1):
+    """Rows of one scenario as a function of w = (Z flat, design variables (p))."""
+    sec = None if p == 1 else torch.from_numpy(sections(N, p))
+
     def fn(w):
-        Z = w[:-1].reshape(N, NV)
-        return scenario_constraints(Z, w[-1], feed, P).reshape(-1)
+        Z = w[:-p].reshape(N, NV)
+        d = w[-1] if p == 1 else w[-p:]
+        return scenario_constraints(Z, d, feed, P, sec).reshape(-1)
     return fn
 
 
-def constraints(Zall: np.ndarray, d: float, feeds: np.ndarray, P: OracleParams) -> np.ndarray:
-    """c for all scenarios: Zall (S, N, 21), feeds (S, 18) -> (S, N, 22)."""
+def constraints(Zall: np.ndarray, d, feeds: np.ndarray, P: OracleParams) -> np.ndarray:
+    """c for all scenarios: Zall (S, N, 21), d the diameter or the (p,) section
+    diameters, feeds (S, 18) -> (S, N, 22)."""
     S, N, _ = Zall.shape
+    th = _design(d)
+    p = th.size
     out = np.empty((S, N, NR))
-    dt = torch.tensor(d, dtype=torch.float64)
+    dt = torch.tensor(float(th[0]), dtype=torch.float64) if p == 1 else torch.from_numpy(th)
+    sec = None if p == 1 else torch.from_numpy(sections(N, p))
     for w in range(S):
         out[w] = scenario_constraints(torch.from_numpy(np.ascontiguousarray(Zall[w])), dt,
-                                      torch.from_numpy(feeds[w]), P).numpy()
+                                      torch.from_numpy(feeds[w]), P, sec).numpy()
     return out
 
 
-def jacobian(Zs: np.ndarray, d: float, feed: np.ndarray, P: OracleParams) -> np.ndarray:
-    """Dense Jacobian of one scenario's 22N rows w.r.t. its 21N variables and d.
+def _wvec(Zs, d):
+    return torch.cat([torch.from_numpy(np.ascontiguousarray(Zs)).reshape(-1), torch.from_numpy(_design(d))])
 
-    Returns (22N, 21N + 1); the last column is d/dd.
+
+def jacobian(Zs: np.ndarray, d, feed: np.ndarray, P: OracleParams) -> np.ndarray:
+    """Dense Jacobian of one scenario's 22N rows w.r.t. its 21N variables and the
+    design variables (d, or the p section diameters).
+
+    Returns (22N, 21N + p); the last p columns are the design derivatives.
     """
     N = Zs.shape[0]
-    w = torch.cat([torch.from_numpy(np.ascontiguousarray(Zs)).reshape(-1), torch.tensor([d], dtype=torch.float64)])
-    return torch.func.jacfwd(_flat(P, torch.from_numpy(feed), N))(w).numpy()
+    p = _design(d).size
+    return torch.func.jacfwd(_flat(P, torch.from_numpy(feed), N, p))(_wvec(Zs, d)).numpy()
 
 
-def lagrangian_hessian(Zs: np.ndarray, d: float, feed: np.ndarray, lam: np.ndarray, P: OracleParams) -> np.ndarray:
-    """Dense Hessian of sum_j lam_j c_j (one scenario) w.r.t. (Z, d): (21N+1, 21N+1)."""
+def lagrangian_hessian(Zs: np.ndarray, d, feed: np.ndarray, lam: np.ndarray, P: OracleParams) -> np.ndarray:
+    """Dense Hessian of sum_j lam_j c_j (one scenario) w.r.t. (Z, design): (21N+p, 21N+p)."""
     N = Zs.shape[0]
-    f = _flat(P, torch.from_numpy(feed), N)
+    p = _design(d).size
+    f = _flat(P, torch.from_numpy(feed), N, p)
     lt = torch.from_numpy(np.ascontiguousarray(lam).reshape(-1))
-    w = torch.cat([torch.from_numpy(np.ascontiguousarray(Zs)).reshape(-1), torch.tensor([d], dtype=torch.float64)])
-    H = torch.func.hessian(lambda v: (lt * f(v)).sum())(w).numpy()
+    H = torch.func.hessian(lambda v: (lt * f(v)).sum())(_wvec(Zs, d)).numpy()
     return 0.5 * (H + H.T)  # forward-over-reverse AD is symmetric up to rounding
 
 

@@ -117,3 +117,18 @@ def closed_form_diameter(feeds: np.ndarray, n_stages: int, params: dict, Z0=None
         Zs[w], ok[w] = Z, conv
         ds[w] = hydraulic_diameter(Z, feeds[w], P)
     return float(ds.max()), ds, Zs, ok
+
+
+def closed_form_sections(feeds: np.ndarray, n_stages: int, n_sections: int, params: dict, Z0=None):
+    """theta_k* = the largest hydraulic diameter over the stages of section k of
+    every independently simulated scenario (the optimum of the section-diameter
+    design problem: each section's diameter is bounded below only by its own
+    stages' hydraulic rows, and the design cost increases in each of them).
+    Returns (theta* (p,), states, converged flags)."""
+    P = M.OracleParams(params)
+    _, _, Zs, ok = closed_form_diameter(feeds, n_stages, params, Z0)
+    V, T = Zs[:, :, M.IV], Zs[:, :, M.IT]
+    dh = np.sqrt(4.0 * V * P.R * T / (math.pi * P.u_max * feeds[:, 17][:, None]))  # (S, N)
+    sec = M.sections(n_stages, n_sections)
+    theta = np.array([dh[:, sec == k].max() for k in range(n_sections)])
+    return theta, Zs, ok
