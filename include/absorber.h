@@ -82,7 +82,7 @@ typedef struct {
   int64_t n_ineq;        /* N*S hydraulic inequalities */
   int64_t nnz_jac;       /* entries of the Jacobian structure */
   int64_t nnz_hess;      /* entries of the lower-triangle Hessian structure */
-  int64_t kkt_dim;       /* 43*N*S + 1 */
+  int64_t kkt_dim;       /* 43*N*S + 1 (+ p for a column in p sections) */
 } absorber_dims;
 
 /* Create a problem instance: N stages, S scenarios, feed table feeds_host[S][18].
@@ -241,6 +241,23 @@ int absorber_create_batch(const absorber_params* params, int32_t n_problems, con
 int absorber_batch_solve(absorber_t* h, const absorber_ipm_options* opts, const double* x0_dev,
                          const double* lambda0_dev, double* x_out_dev, double* lambda_out_dev,
                          absorber_ipm_result* results);
+
+/* A column in p sections, each with its own diameter: the general scenario NLP
+ * (eq. 8) with the design vector theta in R^p, p = n_sections in 1..min(4, N).
+ * Stage n (0-based, top to bottom) belongs to section floor(n p / N); its
+ * hydraulic row (eq. 9c) takes that section's diameter.  The design cost is
+ * sum_k c_k theta_k with c_k = (stages in section k) / N, so a column with
+ * equal diameters costs d as in problem (10).  Layout: x = [N S stage
+ * vectors of 21][theta_0 .. theta_{p-1}] (kkt_dim = 43 N S + p).  Accepted by
+ * get_dims, initial_point (every theta_k = d0), eval_cons, eval_obj,
+ * simulate (theta_k = the largest hydraulic minimum of section k),
+ * ipm_solve, kkt_factor and kkt_solve; the Schur complement on theta is a
+ * dense p x p matrix whose inertia comes from its eigenvalues.
+ * absorber_ipm_result.d reports the design cost sum_k c_k theta_k.  The
+ * COO Jacobian/Hessian calls and the warm start return ABS_ERR_ARG.
+ * Blocking; allocates the device state on the current device. */
+int absorber_create_sections(const absorber_params* params, int32_t n_stages, int32_t n_scen, int32_t n_sections,
+                             const double* feeds_host, absorber_t** out);
 
 /* Process simulation: for fixed feeds each scenario's MESH equations are a
  * square system in its stage states (the equilibrium model's degrees of

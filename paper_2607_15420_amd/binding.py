@@ -138,6 +138,8 @@ def lib():
             "absorber_destroy": (None, [vp]),
             "absorber_create_batch": (ctypes.c_int, [ctypes.POINTER(AbsorberParams), i32, ctypes.POINTER(i32),
                                                      ctypes.POINTER(i32), c_double_p, ctypes.POINTER(vp)]),
+            "absorber_create_sections": (ctypes.c_int, [ctypes.POINTER(AbsorberParams), i32, i32, i32, c_double_p,
+                                                        ctypes.POINTER(vp)]),
             "absorber_batch_solve": (ctypes.c_int, [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp,
                                                     ctypes.POINTER(IpmResult)]),
             "absorber_get_dims": (ctypes.c_int, [vp, ctypes.POINTER(Dims)]),
@@ -262,8 +264,29 @@ class Absorber:
                                      feeds.ctypes.data_as(c_double_p), ctypes.byref(h)))
         self.h = h
         self.P = 1
+        self.npar = 1
         self.N, self.S = int(n_stages), int(feeds.shape[0])
         self._sizes()
+
+    @classmethod
+    def sections(cls, params: dict, n_stages: int, feeds: np.ndarray, n_sections: int) -> "Absorber":
+        """One problem whose column has n_sections diameters theta_k (the design
+        vector of eq. 8): stage n belongs to section n * n_sections // n_stages;
+        x ends with the n_sections diameters."""
+        feeds = np.ascontiguousarray(feeds, dtype=np.float64)
+        if feeds.ndim != 2 or feeds.shape[1] != 18:
+            raise ValueError("feeds must be (S, 18)")
+        self = cls.__new__(cls)
+        self._p = params_struct(params)
+        h = ctypes.c_void_p()
+        _check(lib().absorber_create_sections(ctypes.byref(self._p), int(n_stages), int(feeds.shape[0]),
+                                              int(n_sections), feeds.ctypes.data_as(c_double_p), ctypes.byref(h)))
+        self.h = h
+        self.P = 1
+        self.npar = int(n_sections)
+        self.N, self.S = int(n_stages), int(feeds.shape[0])
+        self._sizes()
+        return self
 
     def _sizes(self):
         d = self.dims()
@@ -289,6 +312,7 @@ class Absorber:
                                            ctypes.byref(h)))
         self.h = h
         self.P = len(problems)
+        self.npar = 1
         self.N, self.S = int(Ns.max()), int(Ss.sum())
         self.pN, self.pS = Ns, Ss
         self._sizes()

@@ -292,7 +292,7 @@ static void free_handle(Handle& h) {
   void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
-                  h.seg, h.pseg, h.ctl, h.ipm_work, h.pres, h.rmask};
+                  h.seg, h.pseg, h.ctl, h.ipm_work, h.pres, h.rmask, h.solbk, h.brhs, h.pdots, h.dsc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);
@@ -318,12 +318,30 @@ extern "C" {
 
 const char* absorber_last_error(void) { return g_last_error.c_str(); }
 
+static int create_impl(const absorber_params* prm, int32_t n_problems, const int32_t* n_stages,
+                       const int32_t* n_scen, const double* feeds_host, int npar, absorber_t** out);
+
 int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const int32_t* n_stages,
                           const int32_t* n_scen, const double* feeds_host, absorber_t** out) {
   if (!prm || !feeds_host || !out || !n_stages || !n_scen || n_problems < 1) {
     set_error("absorber_create_batch: bad argument");
     return ABS_ERR_ARG;
   }
+  return create_impl(prm, n_problems, n_stages, n_scen, feeds_host, 1, out);
+}
+
+int absorber_create_sections(const absorber_params* prm, int32_t n_stages, int32_t n_scen, int32_t n_sections,
+                             const double* feeds_host, absorber_t** out) {
+  if (!prm || !feeds_host || !out || n_stages < 1 || n_scen < 1 || n_stages > 4096 || n_sections < 1 ||
+      n_sections > MAX_NPAR || n_sections > n_stages) {
+    set_error("absorber_create_sections: bad argument (1 <= n_sections <= min(4, n_stages))");
+    return ABS_ERR_ARG;
+  }
+  return create_impl(prm, 1, &n_stages, &n_scen, feeds_host, n_sections, out);
+}
+
+static int create_impl(const absorber_params* prm, int32_t n_problems, const int32_t* n_stages,
+                       const int32_t* n_scen, const double* feeds_host, int npar, absorber_t** out) {
   long long nst = 0, W = 0;
   int Nmax = 0;
   for (int p = 0; p < n_problems; ++p) {
@@ -343,14 +361,19 @@ int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const 
   if (!H) return ABS_ERR_OOM;
   Handle& h = H->h;
   h.P = n_problems;
+  h.npar = npar;
+  if (npar > 1) {
+    for (int k = 0; k < MAX_NPAR; ++k) h.cw[k] = 0.0;
+    for (int n = 0; n < n_stages[0]; ++n) h.cw[section_of(n, n_stages[0], npar)] += 1.0 / n_stages[0];
+  }
   h.N = Nmax;
   h.S = (int)W;
   h.nst = nst;
   h.pN.assign(n_stages, n_stages + n_problems);
   h.pS.assign(n_scen, n_scen + n_problems);
-  h.nx = nst * NV + h.P;
+  h.nx = nst * NV + (long long)h.P * npar;
   h.nc = nst * NR;
-  h.nkkt = nst * NK + h.P;
+  h.nkkt = nst * NK + (long long)h.P * npar;
   ModelParams& mp = h.mp;
   memcpy(mp.nu, prm->nu, sizeof(mp.nu));
   for (int k = 0; k < 5; ++k) {
@@ -419,7 +442,7 @@ int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const 
         chain_p[w] = p;
         for (int n = 0; n < h.pN[p]; ++n, ++t) sinfo[(size_t)t] = StageInfo{w, n, h.pN[p], p};
       }
-      for (long long a = ts; a < t; a += SEG) segs.push_back(Seg{(int)a, (int)std::min(t, a + SEG), p, a == ts});
+      for (long long a = ts; a < t; a += SEG) segs.push_back(Seg{(int)a, (int)std::min(t, a + SEG), p, a == ts ? npar : 0});
     }
     chain0[W] = (int)t;
     pchain[h.P] = w;
@@ -455,6 +478,12 @@ int absorber_create_batch(const absorber_params* prm, int32_t n_problems, const 
   ALLOC(h.inert, (size_t)h.S * 4);
   ALLOC(h.part, (size_t)h.S * 4);
   ALLOC(h.scal, h.P);
+  if (npar > 1) {
+    ALLOC(h.solbk, nst * NK * (npar - 1));
+    ALLOC(h.brhs, h.nkkt);
+    ALLOC(h.pdots, (size_t)h.S * PDOT);
+    ALLOC(h.dsc, (size_t)h.P * DSC);
+  }
   ALLOC(h.sinfo, nst);
   ALLOC(h.chain0, W + 1);
   ALLOC(h.chain_p, W);
@@ -530,8 +559,8 @@ int absorber_get_dims(const absorber_t* H, absorber_dims* out) {
   }
   const Handle& h = H->h;
   const long long nst = h.nst;
-  out->n_var_total = 30 * nst + h.P;
-  out->n_var_free = 21 * nst + h.P;
+  out->n_var_total = 30 * nst + (long long)h.P * h.npar;
+  out->n_var_free = 21 * nst + (long long)h.P * h.npar;
   out->n_eq = 21 * nst;
   out->n_fixed = 9 * nst;
   out->n_ineq = nst;
@@ -540,7 +569,7 @@ int absorber_get_dims(const absorber_t* H, absorber_dims* out) {
     nnz += (long long)h.pS[p] * ((long long)h.pN[p] * NJO + (long long)(h.pN[p] - 1) * (NJU + NJD));
   out->nnz_jac = nnz;
   out->nnz_hess = nst * NH + h.P;
-  out->kkt_dim = nst * NK + h.P;
+  out->kkt_dim = nst * NK + (long long)h.P * h.npar;
   return ABS_OK;
 }
 
@@ -628,15 +657,20 @@ int absorber_eval_obj(absorber_t* H, const double* x_dev, double* f_host, double
   }
   Handle& h = H->h;
   hipStream_t st = (hipStream_t)stream;
-  if (f_host) {
-    HIP_TRY(hipMemcpyAsync(f_host, x_dev + h.nx - 1, sizeof(double), hipMemcpyDeviceToHost, st));
-  }
+  // f = sum_k c_k theta_k (c_k: the share of stages in section k; f = d with one diameter)
+  const long long nd = h.npar, nxs = h.nx - nd;
+  double th[MAX_NPAR];
+  if (f_host) HIP_TRY(hipMemcpyAsync(th, x_dev + nxs, sizeof(double) * nd, hipMemcpyDeviceToHost, st));
   if (grad_dev) {
-    HIP_TRY(hipMemsetAsync(grad_dev, 0, sizeof(double) * (h.nx - 1), st));
-    const double one = 1.0;
-    HIP_TRY(hipMemcpyAsync(grad_dev + h.nx - 1, &one, sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(grad_dev, 0, sizeof(double) * nxs, st));
+    HIP_TRY(hipMemcpyAsync(grad_dev + nxs, h.cw, sizeof(double) * nd, hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
+  if (f_host) {
+    double f = 0.0;
+    for (int k = 0; k < nd; ++k) f += h.cw[k] * th[k];
+    *f_host = f;
+  }
   return ABS_OK;
 }
 
@@ -647,6 +681,10 @@ int absorber_jac_structure(const absorber_t* H, int64_t* rows, int64_t* cols) {
   }
   if (H->h.P != 1) {
     set_error("absorber_jac_structure: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
+  if (H->h.npar != 1) {
+    set_error("absorber_jac_structure: handles with one diameter only (a section handle is solved by absorber_ipm_solve)");
     return ABS_ERR_ARG;
   }
   const Handle& h = H->h;
@@ -685,6 +723,10 @@ int absorber_eval_jac(absorber_t* H, const double* x_dev, double* vals_dev, void
     set_error("absorber_eval_jac: single-problem handles only (use absorber_batch_solve for a batch)");
     return ABS_ERR_ARG;
   }
+  if (H->h.npar != 1) {
+    set_error("absorber_eval_jac: handles with one diameter only (a section handle is solved by absorber_ipm_solve)");
+    return ABS_ERR_ARG;
+  }
   HIP_TRY(launch_jac_coo(H->h, x_dev, vals_dev, (hipStream_t)stream));
   return ABS_OK;
 }
@@ -696,6 +738,10 @@ int absorber_hess_structure(const absorber_t* H, int64_t* rows, int64_t* cols) {
   }
   if (H->h.P != 1) {
     set_error("absorber_hess_structure: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
+  if (H->h.npar != 1) {
+    set_error("absorber_hess_structure: handles with one diameter only (a section handle is solved by absorber_ipm_solve)");
     return ABS_ERR_ARG;
   }
   const Handle& h = H->h;
@@ -719,6 +765,10 @@ int absorber_eval_hess(absorber_t* H, const double* x_dev, const double* lambda_
   }
   if (H->h.P != 1) {
     set_error("absorber_eval_hess: single-problem handles only (use absorber_batch_solve for a batch)");
+    return ABS_ERR_ARG;
+  }
+  if (H->h.npar != 1) {
+    set_error("absorber_eval_hess: handles with one diameter only (a section handle is solved by absorber_ipm_solve)");
     return ABS_ERR_ARG;
   }
   HIP_TRY(launch_hess_coo(H->h, x_dev, lambda_dev, vals_dev, (hipStream_t)stream));

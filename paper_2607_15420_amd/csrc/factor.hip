@@ -432,7 +432,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
     const double* __restrict__ diagx, const double* __restrict__ diags, const double* __restrict__ dwv,
     const double* __restrict__ dcv, const int* __restrict__ chain0, const int* __restrict__ chain_p,
-    const int* __restrict__ fmask, const int* __restrict__ chmask, int W, int jd, double* __restrict__ slots,
+    const int* __restrict__ fmask, const int* __restrict__ chmask, int W, int jd, int npar, double* __restrict__ slots,
     double* __restrict__ solr, double* __restrict__ solb, int* __restrict__ inert, double* __restrict__ part) {
   __shared__ WaveLDS L;
   const int w = blockIdx.x;
@@ -466,7 +466,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     if (lane < NK) L.src[SRC_RHS + lane] = rhs ? rhs[t * NK + lane] : 0.0;
     if (lane < NV) L.src[SRC_DIAGX + lane] = diagx[t * NV + lane] + dw;
     if (lane == 0) {
-      L.src[SRC_BRD] = R[jd];
+      // the fused border: the diameter of the stage's section (section 0 when
+      // there are several; the other sections' borders are solved afterwards)
+      L.src[SRC_BRD] = section_of(n, N, npar) == 0 ? R[jd] : 0.0;
       L.src[SRC_DC] = -dc;
       L.src[SRC_DHYD] = -(1.0 / (diags[t] + dw) + dc);
     }
@@ -725,6 +727,227 @@ __global__ void k_combine(const double* __restrict__ solr, const double* __restr
   }
 }
 
+// ---------------------------------------------------------------- design vector (npar > 1)
+// With one diameter per column section the border of a scenario block has one
+// column b_k per section (nonzero at the hydraulic-dual rows of that section's
+// stages).  The factorisation solves with b_0; the other columns are solved
+// with the stored factors; the Schur complement S = K_dd - sum_w B^T K_w^{-1} B
+// is a dense npar x npar matrix per problem.
+
+// right-hand side holding the border column of section k
+__global__ void k_border_rhs(const double* __restrict__ rec, const StageInfo* __restrict__ sinfo, long long nks,
+                             long long nkkt, int jd, int npar, int k, double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nkkt) return;
+  double v = 0.0;
+  if (i < nks && i % NK == NK - 1) {
+    const long long t = i / NK;
+    const StageInfo si = sinfo[t];
+    if (section_of(si.n, si.N, npar) == k) v = rec[t * REC + jd];
+  }
+  out[i] = v;
+}
+
+// per chain (one thread each): mode 0/1: b_k . v_l, b_k . u and W_dd per
+// section; mode 2: b_k . u only (u: the solution with the right-hand side)
+__global__ void k_design_dots(int mode, const double* __restrict__ rec, const int* __restrict__ chain0,
+                              const int* __restrict__ chain_p, int W, int jd, int npar, long long nks,
+                              const double* __restrict__ solr, const double* __restrict__ solb,
+                              const double* __restrict__ solbk, const int* __restrict__ pmask,
+                              double* __restrict__ pdots) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  if (pmask && !pmask[chain_p[w]]) return;
+  const long long t0 = chain0[w];
+  const int N = chain0[w + 1] - (int)t0;
+  double S[MAX_NPAR * MAX_NPAR], r[MAX_NPAR], wd[MAX_NPAR];
+#pragma unroll
+  for (int q = 0; q < MAX_NPAR * MAX_NPAR; ++q) S[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < MAX_NPAR; ++q) r[q] = wd[q] = 0.0;
+  for (int n = 0; n < N; ++n) {
+    const long long t = t0 + n;
+    const int k = section_of(n, N, npar);
+    const double bn = rec[t * REC + jd];
+    const long long hy = t * NK + NK - 1;
+    const double u = bn * solr[hy];
+#pragma unroll
+    for (int q = 0; q < MAX_NPAR; ++q) r[q] += q == k ? u : 0.0;
+    if (mode != 2) {
+      const double wdd = rec[t * REC + REC_WDD];
+#pragma unroll
+      for (int q = 0; q < MAX_NPAR; ++q) wd[q] += q == k ? wdd : 0.0;
+#pragma unroll
+      for (int l = 0; l < MAX_NPAR; ++l) {
+        if (l >= npar) break;
+        const double v = bn * (l == 0 ? solb[hy] : solbk[(long long)(l - 1) * nks + hy]);
+#pragma unroll
+        for (int q = 0; q < MAX_NPAR; ++q) S[q * MAX_NPAR + l] += q == k ? v : 0.0;
+      }
+    }
+  }
+  double* o = pdots + (long long)w * PDOT;
+  if (mode != 2) {
+#pragma unroll
+    for (int q = 0; q < MAX_NPAR * MAX_NPAR; ++q) o[q] = S[q];
+#pragma unroll
+    for (int q = 0; q < MAX_NPAR; ++q) o[MAX_NPAR * MAX_NPAR + MAX_NPAR + q] = wd[q];
+  }
+#pragma unroll
+  for (int q = 0; q < MAX_NPAR; ++q) o[MAX_NPAR * MAX_NPAR + q] = r[q];
+}
+
+// eigenvalues of a symmetric n x n matrix (n <= MAX_NPAR) by cyclic Jacobi
+// rotations (a fixed number of sweeps: deterministic)
+__device__ void sym_eigenvalues(double (&A)[MAX_NPAR][MAX_NPAR], int n, double (&ev)[MAX_NPAR]) {
+  for (int sweep = 0; sweep < 30; ++sweep)
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // rotate columns p, q
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rotate rows p, q
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+      }
+  for (int k = 0; k < n; ++k) ev[k] = A[k][k];
+}
+
+// per problem (one wave each): fixed-order sums of the chains' partials, then
+// mode 0/1: S, its inertia (plus the chains' counts) and the K_dd diagonal;
+// mode 1/2: delta theta = S^{-1} (r_theta - sum b_k . u) by Gaussian
+// elimination with partial pivoting
+__global__ __launch_bounds__(64) void k_design_schur(int mode, const double* __restrict__ pdots,
+                                                     const int* __restrict__ inert, const int* __restrict__ pchain,
+                                                     const double* __restrict__ diagx, long long nxs,
+                                                     const double* __restrict__ dwv, const double* __restrict__ rhs,
+                                                     long long nks, int npar, const int* __restrict__ pmask,
+                                                     DevScalars* __restrict__ scal, double* __restrict__ dsc) {
+  const int pb = blockIdx.x;
+  if (pmask && !pmask[pb]) return;
+  const int lane = threadIdx.x;
+  constexpr int NQ = PDOT + 3;
+  double a[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) a[q] = 0.0;
+  for (int w = pchain[pb] + lane; w < pchain[pb + 1]; w += 64) {
+    const double* o = pdots + (long long)w * PDOT;
+    if (mode != 2) {
+#pragma unroll
+      for (int q = 0; q < PDOT; ++q) a[q] += o[q];
+      a[PDOT] += inert[w * 4];
+      a[PDOT + 1] += inert[w * 4 + 1];
+      a[PDOT + 2] += inert[w * 4 + 2];
+    } else {
+#pragma unroll
+      for (int q = 0; q < MAX_NPAR; ++q) a[MAX_NPAR * MAX_NPAR + q] += o[MAX_NPAR * MAX_NPAR + q];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] += __shfl_down(a[q], off, 64);
+  if (lane != 0) return;
+  double* D = dsc + (long long)pb * DSC;
+  double* Sst = D;                                   // S [MAX_NPAR][MAX_NPAR]
+  double* dth = D + MAX_NPAR * MAX_NPAR;             // delta theta
+  double* wst = dth + MAX_NPAR;                      // W_dd per section
+  double* kdg = wst + MAX_NPAR;                      // K_dd diagonal
+  const long long ib = (long long)pb * npar;
+  if (mode != 2) {
+    const double* wdd = a + MAX_NPAR * MAX_NPAR + MAX_NPAR;
+    double A[MAX_NPAR][MAX_NPAR] = {};
+    double amax = 1.0;
+    for (int k = 0; k < npar; ++k) {
+      wst[k] = wdd[k];
+      kdg[k] = wdd[k] + diagx[nxs + ib + k] + dwv[pb];
+      amax = fmax(amax, fabs(kdg[k]));
+      for (int l = 0; l < npar; ++l) {
+        const double sym = 0.5 * (a[k * MAX_NPAR + l] + a[l * MAX_NPAR + k]);
+        A[k][l] = (k == l ? kdg[k] : 0.0) - sym;
+        Sst[k * MAX_NPAR + l] = A[k][l];
+      }
+    }
+    double ev[MAX_NPAR];
+    sym_eigenvalues(A, npar, ev);
+    long long np = (long long)a[PDOT], nn = (long long)a[PDOT + 1], nz = (long long)a[PDOT + 2];
+    const double tiny = 1e-20 * amax;
+    for (int k = 0; k < npar; ++k) {
+      if (ev[k] > tiny) ++np;
+      else if (ev[k] < -tiny) ++nn;
+      else ++nz;
+    }
+    DevScalars& o = scal[pb];
+    o.npos = np;
+    o.nneg = nn;
+    o.nzero = nz;
+    o.kdd = kdg[0];
+    o.sd = ev[0];
+  }
+  if (mode != 0) {
+    double A[MAX_NPAR][MAX_NPAR], b[MAX_NPAR];
+    for (int k = 0; k < npar; ++k) {
+      b[k] = rhs[nks + ib + k] - a[MAX_NPAR * MAX_NPAR + k];
+      for (int l = 0; l < npar; ++l) A[k][l] = Sst[k * MAX_NPAR + l];
+    }
+    for (int c = 0; c < npar; ++c) {  // elimination with partial pivoting
+      int piv = c;
+      for (int r = c + 1; r < npar; ++r)
+        if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+      if (piv != c) {
+        for (int l = 0; l < npar; ++l) {
+          const double tmp = A[c][l];
+          A[c][l] = A[piv][l];
+          A[piv][l] = tmp;
+        }
+        const double tb = b[c];
+        b[c] = b[piv];
+        b[piv] = tb;
+      }
+      for (int r = c + 1; r < npar; ++r) {
+        const double f = A[r][c] / A[c][c];
+        for (int l = c; l < npar; ++l) A[r][l] -= f * A[c][l];
+        b[r] -= f * b[c];
+      }
+    }
+    for (int c = npar - 1; c >= 0; --c) {
+      double v = b[c];
+      for (int l = c + 1; l < npar; ++l) v -= A[c][l] * dth[l];
+      dth[c] = v / A[c][c];
+    }
+  }
+}
+
+// sol = u - sum_l v_l delta theta_l on the stage entries, delta theta on the design entries
+__global__ void k_design_combine(const double* __restrict__ solr, const double* __restrict__ solb,
+                                 const double* __restrict__ solbk, const double* __restrict__ dsc,
+                                 const StageInfo* __restrict__ sinfo, long long nks, int P, int npar,
+                                 const int* __restrict__ pmask, double* __restrict__ sol) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nks) {
+    const int p = sinfo[i / NK].p;
+    if (pmask && !pmask[p]) return;
+    const double* dth = dsc + (long long)p * DSC + MAX_NPAR * MAX_NPAR;
+    double v = solr[i] - solb[i] * dth[0];
+    for (int l = 1; l < npar; ++l) v -= solbk[(long long)(l - 1) * nks + i] * dth[l];
+    sol[i] = v;
+  } else if (i < nks + (long long)P * npar) {
+    const long long j = i - nks;
+    const int p = (int)(j / npar);
+    if (pmask && !pmask[p]) return;
+    sol[i] = dsc[(long long)p * DSC + MAX_NPAR * MAX_NPAR + (j % npar)];
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launch wrappers
@@ -735,8 +958,8 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
   prof_begin(h, 0, st);
 #define ABS_FACTOR(S, W)                                                                                    \
   hipLaunchKernelGGL((k_factor<S, W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
-                     h.dcv, h.chain0, h.chain_p, fm, h.chmask, nw, h.jac_d_index, h.slots, h.solr, h.solb, h.inert, \
-                     h.part)
+                     h.dcv, h.chain0, h.chain_p, fm, h.chmask, nw, h.jac_d_index, h.npar, h.slots, h.solr, h.solb, \
+                     h.inert, h.part)
   // launch shape: occupancy target (waves per SIMD 2 or 3) and row split of the update
   const int wpe = h.tune.factor_wpe, split = h.tune.factor_split;
   if (wpe == 2) {
@@ -755,13 +978,14 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
   return hipGetLastError();
 }
 
-hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain) {
+hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain, double* out) {
   const int nw = nchain < 0 || nchain > h.S ? h.S : nchain;
+  double* const xo = out ? out : h.solr;
   prof_begin(h, 1, st);
   const int* pa = h.pact_on ? h.pact : nullptr;
 #define ABS_SOLVE(W)                                                                                           \
   hipLaunchKernelGGL((k_solve<W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, \
-                     h.chmask, nw, h.jac_d_index, h.solr, h.part)
+                     h.chmask, nw, h.jac_d_index, xo, h.part)
   if (h.tune.solve_wpe == 2) ABS_SOLVE(2);
   else if (h.tune.solve_wpe == 4) ABS_SOLVE(4);
   else ABS_SOLVE(3);
@@ -771,8 +995,29 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
   return hipGetLastError();
 }
 
+static hipError_t launch_design_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol,
+                                      hipStream_t st, const int* pmask) {
+  const long long nks = h.nst * NK;
+  if (mode != 2)  // the other sections' border columns with the stored factors
+    for (int k = 1; k < h.npar; ++k) {
+      hipLaunchKernelGGL(k_border_rhs, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, h.rec, h.sinfo, nks, h.nkkt,
+                         h.jac_d_index, h.npar, k, h.brhs);
+      const hipError_t e = launch_solve(h, h.brhs, st, -1, h.solbk + (long long)(k - 1) * nks);
+      if (e != hipSuccess) return e;
+    }
+  hipLaunchKernelGGL(k_design_dots, dim3(grid_for(h.S, 64)), dim3(64), 0, st, mode, h.rec, h.chain0, h.chain_p, h.S,
+                     h.jac_d_index, h.npar, nks, h.solr, h.solb, h.solbk, pmask, h.pdots);
+  hipLaunchKernelGGL(k_design_schur, dim3(h.P), dim3(64), 0, st, mode, h.pdots, h.inert, h.pchain, diagx,
+                     h.nst * NV, h.dwv, rhs, nks, h.npar, pmask, h.scal, h.dsc);
+  if (mode != 0 && sol)
+    hipLaunchKernelGGL(k_design_combine, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, h.solr, h.solb, h.solbk,
+                       h.dsc, h.sinfo, nks, h.P, h.npar, pmask, sol);
+  return hipGetLastError();
+}
+
 hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st,
                         const int* pmask) {
+  if (h.npar > 1) return launch_design_schur(h, diagx, rhs, mode, sol, st, pmask);
   const double* rd = rhs ? rhs + h.nst * NK : nullptr;
   hipLaunchKernelGGL(k_schur, dim3(h.P), dim3(SCHUR_BS), 0, st, h.part, h.inert, h.pchain, diagx + h.nst * NV, h.dwv, rd,
                      mode, pmask, h.scal);

@@ -55,6 +55,17 @@ __host__ __device__ constexpr int coupling_index(int a) {
 
 struct JacEntry { int8_t row, blk, col; };
 
+// Design vector: one diameter per column section (npar sections of near-equal
+// height; stage n of an N-stage chain is in section n npar / N).  npar = 1 is
+// the single shared diameter of problem (10).
+constexpr int MAX_NPAR = 4;
+__host__ __device__ __forceinline__ int section_of(int n, int N, int npar) { return (n * npar) / N; }
+// per-problem design data of the Schur complement for npar > 1 (doubles):
+// [S (npar^2)][delta theta (npar)][W_dd per section (npar)][K_dd diagonal (npar)]
+constexpr int DSC = MAX_NPAR * MAX_NPAR + 3 * MAX_NPAR;
+// per-chain partial sums for npar > 1: [b_k . v_l (npar^2)][b_k . u (npar)][W_dd per section (npar)]
+constexpr int PDOT = MAX_NPAR * MAX_NPAR + 2 * MAX_NPAR;
+
 constexpr int CTL_SLOT = 64;  // bytes of solver scalars per problem in the control block
 inline size_t ctl_off_fmask(int P) { return 16 * (size_t)P; }
 inline size_t ctl_off_pact(int P) { return 20 * (size_t)P; }
@@ -71,10 +82,12 @@ struct StageInfo {
 };
 // IPM work unit: at most SEG consecutive stages of one problem, so that one
 // 256-thread block covers their primal (21 SEG), row (22 SEG) and stage entries
+// (the design entries on its last MAX_NPAR threads: 21 SEG + MAX_NPAR <= 256)
 // and the block's partial reductions belong to a single problem
 constexpr int SEG = 11;
+static_assert(NV * SEG + MAX_NPAR <= 256, "a segment block must hold its primal and design entries");
 struct Seg {
-  int t0, t1, p, first;  // stage range, problem, 1 for the problem's first segment (it also owns d)
+  int t0, t1, p, first;  // stage range, problem, npar for the problem's first segment (it also owns the design entries), else 0
 };
 
 // scalars produced by the Schur/inertia reduction (one per problem)
@@ -100,6 +113,8 @@ struct Tune {
 // all per-handle device and host state
 struct Handle {
   int P = 1;                                 // independent problems
+  int npar = 1;                              // design variables per problem (section diameters)
+  double cw[MAX_NPAR] = {1, 0, 0, 0};        // design-cost weight of each section diameter (its share of stages)
   int N = 0, S = 0;                          // P == 1: stages and scenarios; otherwise the largest
                                              // stage count and the number of chains
   long long nst = 0;                         // stages of all problems
@@ -155,7 +170,11 @@ struct Handle {
   double* rec = nullptr;                     // [S][N][REC]
   double* slots = nullptr;                   // [S][N][NK][SLOT] stored pivot columns
   double* solr = nullptr;                    // [S][N][NK] K_w^{-1} r
-  double* solb = nullptr;                    // [S][N][NK] K_w^{-1} b
+  double* solb = nullptr;                    // [S][N][NK] K_w^{-1} b (for npar > 1: the border of section 0)
+  double* solbk = nullptr;                   // npar > 1: [npar - 1][S][N][NK] K_w^{-1} b_k of sections 1..
+  double* brhs = nullptr;                    // npar > 1: [nkkt] border of one section as a right-hand side
+  double* pdots = nullptr;                   // npar > 1: [chains][PDOT] per-chain partial sums
+  double* dsc = nullptr;                     // npar > 1: [P][DSC] Schur complement data per problem
   int* inert = nullptr;                      // [chains][4]
   double* part = nullptr;                    // [chains][4] per-chain partial sums
   DevScalars* scal = nullptr;                // device scalars [P]
@@ -264,8 +283,8 @@ hipError_t launch_hess_coo(Handle& h, const double* x, const double* lam, double
 // limits the launch to the first nchain chains (launch-shape timing only).
 hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
                          hipStream_t st, int nchain = -1);
-// forward/backward with the stored factors: solr <- K_w^{-1} rhs (nchain as above)
-hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain = -1);
+// forward/backward with the stored factors: out (default h.solr) <- K_w^{-1} rhs (nchain as above)
+hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain = -1, double* out = nullptr);
 // Schur complement on each problem's d.  diagx: Sigma_x (its d entries are
 // Sigma_d); rhs: the right-hand side (its d entries are r_d; may be null in
 // mode 0).  mode 0: after launch_factor without a right-hand side (S_d,

@@ -49,6 +49,16 @@ struct Bnd {
   double lo[NV + 1], hi[NV + 1];
 };
 
+// gradient of the scaled objective f~ = sf sum_k c_k D_d theta_k with respect to
+// each scaled design entry (g[k] = sf D_d c_k), and the section weights c_k
+struct Obj {
+  double g[MAX_NPAR], c[MAX_NPAR];
+  int npar;
+};
+__device__ __forceinline__ double obj_g(const Obj& o, long long i, long long nxs) {
+  return i >= nxs ? o.g[(i - nxs) % o.npar] : 0.0;
+}
+
 __device__ __forceinline__ int lidx(long long i, long long nxs) { return i >= nxs ? NV : (int)(i % NV); }
 
 // primal index -> KKT index
@@ -145,10 +155,11 @@ __global__ __launch_bounds__(RS) void k_seg_reduce(const double* __restrict__ pa
 
 // the entries of one segment: thread tid owns primal entry NV t0 + tid (tid <
 // NV ns), row entry NR t0 + tid (tid < NR ns), stage t0 + tid (tid < ns), and
-// the last thread of the problem's first segment owns d
+// the last nd threads of the problem's first segment own its nd design
+// entries (Seg::first holds nd there, 0 elsewhere)
 struct SegView {
   long long t0;
-  int ns, p, tid;
+  int ns, p, tid, nd;
   bool owns_d;
   __device__ SegView(const Seg* seg) {
     const Seg s = seg[blockIdx.x];
@@ -156,12 +167,13 @@ struct SegView {
     ns = s.t1 - s.t0;
     p = s.p;
     tid = threadIdx.x;
-    owns_d = s.first && tid == BS - 1;
+    nd = s.first;
+    owns_d = tid >= BS - nd;
   }
   // primal entry of this thread (or -1)
   __device__ long long xi(long long nxs) const {
     if (tid < NV * ns) return NV * t0 + tid;
-    if (owns_d) return nxs + p;
+    if (owns_d) return nxs + (long long)p * nd + (tid - (BS - nd));
     return -1;
   }
   __device__ long long ci() const { return tid < NR * ns ? NR * t0 + tid : -1; }
@@ -221,8 +233,9 @@ __global__ __launch_bounds__(GBS) void k_lag_grad(const double* __restrict__ rec
 
 // g_d = sf * D_d + the problem's hydraulic-row terms (one block per problem,
 // fixed order over its segments)
-__global__ void k_grad_d(const double* __restrict__ dpart, const int* __restrict__ pseg, double gf, long long nxs,
+__global__ void k_grad_d(const double* __restrict__ dpart, const int* __restrict__ pseg, Obj ob, long long nxs,
                          double* __restrict__ g) {
+  const double gf = ob.g[0];
   __shared__ double sm[BS];
   const int p = blockIdx.x;
   double a = 0.0;
@@ -234,6 +247,35 @@ __global__ void k_grad_d(const double* __restrict__ dpart, const int* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) g[nxs + p] = gf + sm[0];
+}
+
+// the design entries of J^T y for npar > 1 (one block per problem): g_k =
+// sf D_d c_k + the hydraulic rows of section k, summed in a fixed order
+constexpr int DGS = 256;
+__global__ __launch_bounds__(DGS) void k_grad_design(const double* __restrict__ rec, const double* __restrict__ y,
+                                                     const long long* __restrict__ pstage,
+                                                     const StageInfo* __restrict__ sinfo, int jd, Obj ob,
+                                                     long long nxs, double* __restrict__ g) {
+  __shared__ double sm[MAX_NPAR][DGS];
+  const int pb = blockIdx.x;
+  double a[MAX_NPAR] = {0, 0, 0, 0};
+  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += DGS) {
+    const StageInfo si = sinfo[t];
+    const int k = section_of(si.n, si.N, ob.npar);
+    const double v = rec[t * REC + jd] * y[t * NR + NR - 1];
+#pragma unroll
+    for (int q = 0; q < MAX_NPAR; ++q) a[q] += q == k ? v : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < MAX_NPAR; ++q) sm[q][threadIdx.x] = a[q];
+  __syncthreads();
+  for (int h = DGS / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int q = 0; q < MAX_NPAR; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < ob.npar) g[nxs + (long long)pb * ob.npar + threadIdx.x] = ob.g[threadIdx.x] + sm[threadIdx.x][0];
 }
 
 // ---- optimality-error partials per segment
@@ -304,6 +346,7 @@ __global__ void k_sigma(const double* __restrict__ x, const double* __restrict__
 }
 
 // barrier gradient of a primal entry (without J^T y)
+// gf: the objective's gradient at this entry (0 for a stage entry)
 __device__ __forceinline__ double barrier_grad(double xi, int k, const Bnd& b, double mu, double kd, double gf) {
   double v = (k == NV) ? gf : 0.0;
   const bool hl = isfinite(b.lo[k]), hu = isfinite(b.hi[k]);
@@ -319,7 +362,7 @@ __device__ __forceinline__ double barrier_grad(double xi, int k, const Bnd& b, d
 __global__ void k_rhs(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ dwv,
                       const double* __restrict__ x, const double* __restrict__ g, const double* __restrict__ y,
                       const double* __restrict__ c, const double* __restrict__ s, const double* __restrict__ ds,
-                      Bnd b, double kd, double gf, long long nxs, long long nks, double* __restrict__ rhs) {
+                      Bnd b, double kd, Obj ob, long long nxs, long long nks, double* __restrict__ rhs) {
   const SegView V(seg);
   const PS q = ps[V.p];
   const double mu = q.mu, dw = dwv[V.p];
@@ -327,6 +370,7 @@ __global__ void k_rhs(const Seg* __restrict__ seg, const PS* __restrict__ ps, co
   if (i >= 0) {
     const int k = lidx(i, nxs);
     // g holds grad f~ + J~^T y; remove grad f~ for d since barrier_grad adds it
+    const double gf = obj_g(ob, i, nxs);
     const double gl = (k == NV) ? g[i] - gf : g[i];
     rhs[kkt_of_primal(i, nxs, nks)] = q.active ? -(gl + barrier_grad(x[i], k, b, mu, kd, gf)) : 0.0;
   }
@@ -347,7 +391,7 @@ __global__ void k_direction(const Seg* __restrict__ seg, const PS* __restrict__ 
                             const double* __restrict__ x, const double* __restrict__ zL,
                             const double* __restrict__ zU, const double* __restrict__ y, const double* __restrict__ s,
                             const double* __restrict__ vU, const double* __restrict__ dss,
-                            const double* __restrict__ sol, Bnd b, double kd, double gf, long long nxs, long long nks,
+                            const double* __restrict__ sol, Bnd b, double kd, Obj ob, long long nxs, long long nks,
                             double* __restrict__ dx, double* __restrict__ dy, double* __restrict__ dzL,
                             double* __restrict__ dzU, double* __restrict__ dsl, double* __restrict__ dvU,
                             double* __restrict__ out) {
@@ -364,7 +408,8 @@ __global__ void k_direction(const Seg* __restrict__ seg, const PS* __restrict__ 
     const int k = lidx(i, nxs);
     const double d = sol[kkt_of_primal(i, nxs, nks)];
     dx[i] = d;
-    if (i >= nxs) p.v[3] = d;  // the problem's diameter step (its owner thread only)
+    // the problem's design-cost step sum_k c_k d theta_k (its owner threads only)
+    if (i >= nxs) p.v[3] = ob.c[(i - nxs) % ob.npar] * d;
     const double xi = x[i];
     double a = 0.0, bz = 0.0;
     if (isfinite(b.lo[k])) {
@@ -381,7 +426,7 @@ __global__ void k_direction(const Seg* __restrict__ seg, const PS* __restrict__ 
     }
     dzL[i] = a;
     dzU[i] = bz;
-    p.v[2] += barrier_grad(xi, k, b, mu, kd, gf) * d;
+    p.v[2] += barrier_grad(xi, k, b, mu, kd, obj_g(ob, i, nxs)) * d;
   }
   const long long j = V.ci();
   if (j >= 0) dy[j] = sol[kkt_of_row(j)];
@@ -549,10 +594,10 @@ __global__ void k_init_slack(const double* __restrict__ c, double* __restrict__ 
 
 // rhs of the least-squares multiplier system [[I, J^T], [J, 0]] (slack block eliminated)
 __global__ void k_ls_rhs(const double* __restrict__ zL, const double* __restrict__ zU, const double* __restrict__ vU,
-                         double gf, long long nx, long long nxs, long long nks, long long nst,
+                         Obj ob, long long nx, long long nxs, long long nks, long long nst,
                          double* __restrict__ rhs) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) rhs[kkt_of_primal(i, nxs, nks)] = -((i >= nxs ? gf : 0.0) - zL[i] + zU[i]);
+  if (i < nx) rhs[kkt_of_primal(i, nxs, nks)] = -(obj_g(ob, i, nxs) - zL[i] + zU[i]);
   if (i < nst) rhs[i * NK + NK - 1] = -vU[i];
 }
 
@@ -1066,7 +1111,7 @@ int capture_graph(hipStream_t st, hipGraphExec_t* out, F body) {
 // another factorisation trial, refinement corrections or further trial points
 // is finished by replaying the graphs of those phases.  Same arithmetic and
 // order of decisions as the host-driven loop.
-int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, const Bnd& b, double gf,
+int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, const Bnd& b, const Obj& ob,
                      Work& W, std::vector<Prob>& pr, hipStream_t st, int& nfact, int& replays) {
   GraphState& gs = *static_cast<GraphState*>(h.ipm_graph);
   const int P = h.P;
@@ -1148,7 +1193,11 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
       HIP_TRY(launch_eval(h, W.xt, 1, W.y, 1, W.c, st));
       hipLaunchKernelGGL(k_lag_grad, dim3(nseg), dim3(GBS), 0, st, h.rec, h.gtab, h.gtab_n, W.y, h.seg, h.sinfo,
                          nst, h.jac_d_index, W.g, W.dpart);
-      hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, gf, nxs, W.g);
+      if (h.npar == 1)
+        hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, ob, nxs, W.g);
+      else
+        hipLaunchKernelGGL(k_grad_design, dim3(P), dim3(DGS), 0, st, h.rec, W.y, h.pstage, h.sinfo, h.jac_d_index,
+                           ob, nxs, W.g);
       hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s,
                          W.vU, b, nxs, h.redbuf);
       hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nxs, nst, h.diagx,
@@ -1161,7 +1210,7 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
     }));
     auto fac_a = [&]() -> int {
       hipLaunchKernelGGL(k_rhs, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.g, W.y, W.c, W.s, h.diags,
-                         b, C.kappa_d, gf, nxs, nks, W.rhs);
+                         b, C.kappa_d, ob, nxs, nks, W.rhs);
       HIP_TRY(hipGetLastError());
       return ABS_OK;
     };
@@ -1211,7 +1260,7 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
     };
     GTRY(capture_graph(st, &gs.ex[G_DIR], [&]() -> int {
       hipLaunchKernelGGL(k_direction, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.zL, W.zU, W.y, W.s,
-                         W.vU, h.diags, W.sol, b, C.kappa_d, gf, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
+                         W.vU, h.diags, W.sol, b, C.kappa_d, ob, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
                          h.redbuf);
       hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
                          h.redbuf + 4LL * nseg);
@@ -1483,7 +1532,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       HIP_TRY(hipMalloc((void**)&h.ipm_work, total * sizeof(double)));
       h.ipm_work_bytes = total * sizeof(double);
     }
-    if (!h.ipm_dd_h) HIP_TRY(hipHostMalloc((void**)&h.ipm_dd_h, sizeof(double) * (size_t)P, 0));
+    if (!h.ipm_dd_h) HIP_TRY(hipHostMalloc((void**)&h.ipm_dd_h, sizeof(double) * (size_t)P * MAX_NPAR, 0));
     HIP_TRY(hipMemsetAsync(h.ipm_work, 0, h.ipm_work_bytes, st));
     for (size_t i = 0; i < sizeof(len) / sizeof(len[0]); ++i) *bufs[i] = h.ipm_work + off[i];
   }
@@ -1529,9 +1578,17 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     Handle& h;
     ~PactGuard() { h.pact_on = false; }
   } pact_guard{h};
-  auto read_d = [&](const double* v) -> int {  // d entries of a primal vector -> W.dd_h
-    HIP_TRY(hipMemcpyAsync(W.dd_h, v + nxs, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+  // design entries of a primal vector -> W.dd_h[p] = sum_k c_k xt_theta_k (the
+  // scaled design cost; the diameter itself with one design entry)
+  auto read_d = [&](const double* v) -> int {
+    HIP_TRY(hipMemcpyAsync(W.dd_h, v + nxs, sizeof(double) * P * h.npar, hipMemcpyDeviceToHost, st));
     HIP_TRY(wait_stream(st));
+    if (h.npar > 1)
+      for (int p = 0; p < P; ++p) {
+        double a = 0.0;
+        for (int k = 0; k < h.npar; ++k) a += h.cw[k] * W.dd_h[(size_t)p * h.npar + k];
+        W.dd_h[p] = a;  // p <= p * npar: no entry still needed is overwritten
+      }
     return ABS_OK;
   };
 #define TRY(expr)            \
@@ -1561,8 +1618,19 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
                      0.0, C.zinit, nx, nxs);
   HIP_TRY(launch_rowmax(h, W.xt, 1, W.rowmax, st));
   hipLaunchKernelGGL(k_rowscale, dim3(gc), dim3(BS), 0, st, W.rowmax, o.nlp_scaling_max_gradient, nc, h.cs);
-  h.sf = std::min(1.0, o.nlp_scaling_max_gradient / h.sc.Dd);
+  // gradient-based objective scaling: f = sum_k c_k theta_k has the gradient
+  // c_k D_d with respect to the scaled design entries (D_d with one diameter)
+  double cmax = 0.0;
+  for (int k = 0; k < h.npar; ++k) cmax = std::max(cmax, h.cw[k]);
+  h.sf = h.npar == 1 ? std::min(1.0, o.nlp_scaling_max_gradient / h.sc.Dd)
+                     : std::min(1.0, o.nlp_scaling_max_gradient / (cmax * h.sc.Dd));
   const double gf = h.sf * h.sc.Dd;  // gradient of f~ = sf * d with respect to xt_d
+  Obj ob{};
+  ob.npar = h.npar;
+  for (int k = 0; k < h.npar; ++k) {
+    ob.c[k] = h.npar == 1 ? 1.0 : h.cw[k];
+    ob.g[k] = h.npar == 1 ? gf : gf * h.cw[k];
+  }
   const double mu0 = warm ? o.warm_mu_init : o.mu_init;
   for (auto& q : pr) {
     q.mu = mu0;
@@ -1589,7 +1657,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     hipLaunchKernelGGL(k_fill, dim3(gx), dim3(BS), 0, st, h.diagx, 0.0, nx);
     hipLaunchKernelGGL(k_fill, dim3(gst), dim3(BS), 0, st, h.diags, 0.0, nst);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(nkkt, BS)), dim3(BS), 0, st, W.rhs, 0.0, nkkt);
-    hipLaunchKernelGGL(k_ls_rhs, dim3(grid_for(std::max(nx, nst), BS)), dim3(BS), 0, st, W.zL, W.zU, W.vU, gf, nx,
+    hipLaunchKernelGGL(k_ls_rhs, dim3(grid_for(std::max(nx, nst), BS)), dim3(BS), 0, st, W.zL, W.zU, W.vU, ob, nx,
                        nxs, nks, nst, W.rhs);
     for (auto& q : pr) {
       q.dw = 1.0;
@@ -1630,9 +1698,10 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     q.theta_min = C.theta_min_fact * std::max(1.0, th0);
     q.xd = W.dd_h[p];
     const double nsp = (double)(h.pstage_h[(size_t)p + 1] - h.pstage_h[(size_t)p]);
-    q.nx_p = NV * nsp + 1;
+    q.nx_p = NV * nsp + h.npar;
     q.nc_p = NR * nsp;
-    const double nbL = nbL1 * nsp + std::isfinite(b.lo[NV]), nbU = nbU1 * nsp + std::isfinite(b.hi[NV]);
+    const double nbL = nbL1 * nsp + h.npar * std::isfinite(b.lo[NV]);
+    const double nbU = nbU1 * nsp + h.npar * std::isfinite(b.hi[NV]);
     q.n_all = q.nc_p + nbL + nbU + nsp;
     q.n_b = nbL + nbU + nsp;
   }
@@ -1647,7 +1716,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   TRY(upload());
   h.pact_on = true;
   int replays = 0;
-  if (o.use_graph) TRY(graph_iterations(h, o, C, b, gf, W, pr, st, nfact, replays));
+  if (o.use_graph) TRY(graph_iterations(h, o, C, b, ob, W, pr, st, nfact, replays));
   auto now = [] { return std::chrono::steady_clock::now(); };
   auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
@@ -1659,7 +1728,11 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     HIP_TRY(launch_eval(h, W.xt, 1, W.y, 1, W.c, st));
     hipLaunchKernelGGL(k_lag_grad, dim3(nseg), dim3(GBS), 0, st, h.rec, h.gtab, h.gtab_n, W.y, h.seg, h.sinfo, nst,
                        h.jac_d_index, W.g, W.dpart);
-    hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, gf, nxs, W.g);
+    if (h.npar == 1)
+      hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, ob, nxs, W.g);
+    else
+      hipLaunchKernelGGL(k_grad_design, dim3(P), dim3(DGS), 0, st, h.rec, W.y, h.pstage, h.sinfo, h.jac_d_index, ob,
+                         nxs, W.g);
     hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s, W.vU,
                        b, nxs, h.redbuf);
     // the barrier Hessian diagonals at x_k need no decision of the host: queue them now
@@ -1714,7 +1787,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     for (bool first = true;; first = false) {
       if (!first) TRY(upload());
       hipLaunchKernelGGL(k_rhs, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.g, W.y, W.c, W.s, h.diags,
-                         b, C.kappa_d, gf, nxs, nks, W.rhs);
+                         b, C.kappa_d, ob, nxs, nks, W.rhs);
       if (o.autotune && !h.tune.done) TRY(autotune(h, W.xt, W.y, W.c, h.diagx, h.diags, W.rhs, st));
       HIP_TRY(launch_factor(h, h.diagx, h.diags, W.rhs, true, st));
       ++nfact;
@@ -1762,7 +1835,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     // ---- step pieces and fraction to the boundary
     // and, reduced together, theta and the barrier function at the current point
     hipLaunchKernelGGL(k_direction, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.zL, W.zU, W.y, W.s,
-                       W.vU, h.diags, W.sol, b, C.kappa_d, gf, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
+                       W.vU, h.diags, W.sol, b, C.kappa_d, ob, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
                        h.redbuf);
     hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
                        h.redbuf + 4LL * nseg);

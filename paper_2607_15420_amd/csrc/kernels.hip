@@ -87,7 +87,7 @@ __device__ __forceinline__ void load_inflow(const double* __restrict__ x, const 
 __global__ __launch_bounds__(256) void k_eval(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ y,
                        const double* __restrict__ cs, const double* __restrict__ feeds, ModelParams p,
                        const StageInfo* __restrict__ sinfo, long long nst, const int* __restrict__ pact, int full,
-                       double* __restrict__ cout, double* __restrict__ rec) {
+                       int npar, double* __restrict__ cout, double* __restrict__ rec) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nst) return;
   const StageInfo si = sinfo[t];
@@ -98,7 +98,8 @@ __global__ __launch_bounds__(256) void k_eval(const double* __restrict__ x, Scal
   load_stage(x, sc, scaled, t, z);
   Inflow f;
   load_inflow(x, sc, scaled, t, n, N, feed, f);
-  const long long xd = nst * NV + si.p;
+  // the diameter of this stage's section
+  const long long xd = nst * NV + (long long)si.p * npar + section_of(n, N, npar);
   const double d = scaled ? x[xd] * sc.Dd : x[xd];
   const double P = feed[17];
   double csr[NR];
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void k_eval(const double* __restrict__ x, Scal
 
 // maximum |d c~_r / d xt| over the whole row (for gradient-based row scaling)
 __global__ __launch_bounds__(128) void k_rowmax(const double* __restrict__ x, Scaling sc, int scaled, const double* __restrict__ feeds,
-                         ModelParams p, const StageInfo* __restrict__ sinfo, long long nst,
+                         ModelParams p, const StageInfo* __restrict__ sinfo, long long nst, int npar,
                          double* __restrict__ rowmax) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nst) return;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(128) void k_rowmax(const double* __restrict__ x, Sc
   load_stage(x, sc, scaled, t, z);
   Inflow f;
   load_inflow(x, sc, scaled, t, n, N, feed, f);
-  const long long xd = nst * NV + si.p;
+  const long long xd = nst * NV + (long long)si.p * npar + section_of(n, N, npar);
   const double d = scaled ? x[xd] * sc.Dd : x[xd];
   double m[NR];
 #pragma unroll
@@ -206,10 +207,11 @@ __global__ void k_hess_dd(const double* __restrict__ lam, ModelParams p, long lo
 struct TileX0 {
   double v[NV + 1];
 };
-__global__ void k_tile_x0(TileX0 x0, long long nst, int P, double* __restrict__ x) {
+// ndes: design entries (problems x sections)
+__global__ void k_tile_x0(TileX0 x0, long long nst, long long ndes, double* __restrict__ x) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nst * NV) x[i] = x0.v[i % NV];
-  else if (i < nst * NV + P) x[i] = x0.v[NV];
+  else if (i < nst * NV + ndes) x[i] = x0.v[NV];
 }
 
 // z = y + a x (z may be y)
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(RBS) void k_residual(
     const double* __restrict__ diags, const double* __restrict__ dwv, const double* __restrict__ dcv,
     const double* __restrict__ sol, const double* __restrict__ rhs, const Seg* __restrict__ segs,
     const StageInfo* __restrict__ sinfo, long long nst, const int* __restrict__ pact, long long nks, int jd,
-    double* __restrict__ res, double* __restrict__ part, double* __restrict__ omb) {
+    int npar, double* __restrict__ res, double* __restrict__ part, double* __restrict__ omb) {
   __shared__ double cf[(SEG + 2) * REC + SEG * RDG];  // records of stages t0-1 .. t1, then diagonals
   __shared__ double sx[(SEG + 2) * NK];               // unknowns of the same stages
   __shared__ int tab[RT_MAX];
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(RBS) void k_residual(
     const long long t = t0 + ls;
     const StageInfo si = sinfo[t];
     const bool has_dn = si.n > 0, has_up = si.n < si.N - 1;
-    const double xd = sol[nks + sg.p];
+    const double xd = sol[nks + (long long)sg.p * npar + section_of(si.n, si.N, npar)];  // its section's diameter
     const int row = tab[j];
     const int s = ls + 1;
     const int cbase = s * REC - RT_COFF, dbase = (SEG + 2) * REC + ls * RDG - RT_DIAG, xbase = s * NK - RT_XOFF;
@@ -385,6 +387,68 @@ __global__ void k_residual_d(const double* __restrict__ part, const int* __restr
   }
 }
 
+// Design rows of each problem's residual for npar > 1 (one block per problem,
+// fixed-order sums per section over its stages): res_k = rhs_k - sum over the
+// section's stages of b u_hyd - K_dd,k u_k (K_dd diagonal from the Schur data);
+// omd[3 p .. 3 p + 2] = the largest backward error, |res| and |rhs| of its rows.
+constexpr int DBS = 256;
+__global__ __launch_bounds__(DBS) void k_residual_design(
+    const double* __restrict__ rec, const long long* __restrict__ pstage, const StageInfo* __restrict__ sinfo,
+    const double* __restrict__ dsc, const double* __restrict__ sol, const double* __restrict__ rhs, long long nks,
+    int jd, int npar, const int* __restrict__ pact, double* __restrict__ res, double* __restrict__ omd) {
+  __shared__ double sm[2 * MAX_NPAR][DBS];
+  const int pb = blockIdx.x;
+  const long long d0 = nks + (long long)pb * npar;
+  if (pact && !pact[pb]) {
+    if (threadIdx.x < npar) res[d0 + threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) omd[3 * pb] = omd[3 * pb + 1] = omd[3 * pb + 2] = 0.0;
+    return;
+  }
+  double a[MAX_NPAR] = {0, 0, 0, 0}, b[MAX_NPAR] = {0, 0, 0, 0};
+  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += DBS) {
+    const StageInfo si = sinfo[t];
+    const int k = section_of(si.n, si.N, npar);
+    const double pr = rec[t * REC + jd] * sol[t * NK + NK - 1];
+#pragma unroll
+    for (int q = 0; q < MAX_NPAR; ++q) {
+      a[q] += q == k ? pr : 0.0;
+      b[q] += q == k ? fabs(pr) : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAX_NPAR; ++q) {
+    sm[q][threadIdx.x] = a[q];
+    sm[MAX_NPAR + q][threadIdx.x] = b[q];
+  }
+  __syncthreads();
+  for (int h = DBS / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int q = 0; q < 2 * MAX_NPAR; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double* D = dsc + (long long)pb * DSC;
+    const double* kdiag = D + MAX_NPAR * MAX_NPAR + 2 * MAX_NPAR;
+    double om = 0.0, rm = 0.0, bm = 0.0;
+    for (int k = 0; k < npar; ++k) {
+      const long long i = d0 + k;
+      const double ku = sm[k][0] + kdiag[k] * sol[i];
+      const double ka = sm[MAX_NPAR + k][0] + fabs(kdiag[k] * sol[i]);
+      const double rr = rhs[i] - ku;
+      res[i] = rr;
+      const double den = ka + fabs(rhs[i]);
+      const bool fin = isfinite(rr);
+      om = fmax(om, !fin ? INFINITY : (den > 0.0 ? fabs(rr) / den : (rr == 0.0 ? 0.0 : INFINITY)));
+      rm = fmax(rm, fin ? fabs(rr) : INFINITY);
+      bm = fmax(bm, isfinite(rhs[i]) ? fabs(rhs[i]) : INFINITY);
+    }
+    omd[3 * pb] = om;
+    omd[3 * pb + 1] = rm;
+    omd[3 * pb + 2] = bm;
+  }
+}
+
 // out[0] = largest backward error over the segments, out[1] over the problems'
 // d rows, out[2] = largest |res_i| and out[3] = largest |rhs_i| over both.  One
 // block of MAX_BS threads, four segments' loads in flight per thread, then a
@@ -469,22 +533,22 @@ __global__ __launch_bounds__(256) void k_residual_pmax(const double* __restrict_
 
 // res_i = 0 on the stage rows and the d row of the problems with mask 0
 __global__ void k_mask_rows(const int* __restrict__ mask, const StageInfo* __restrict__ sinfo, long long nks, int P,
-                            double* __restrict__ res) {
+                            int npar, double* __restrict__ res) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nks) {
     if (!mask[sinfo[i / NK].p]) res[i] = 0.0;
-  } else if (i < nks + P) {
-    if (!mask[i - nks]) res[i] = 0.0;
+  } else if (i < nks + (long long)P * npar) {
+    if (!mask[(i - nks) / npar]) res[i] = 0.0;
   }
 }
 
 __global__ void k_copy_rows(const int* __restrict__ mask, const StageInfo* __restrict__ sinfo, long long nks, int P,
-                            double* __restrict__ dst, const double* __restrict__ src) {
+                            int npar, double* __restrict__ dst, const double* __restrict__ src) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nks) {
     if (mask[sinfo[i / NK].p]) dst[i] = src[i];
-  } else if (i < nks + P) {
-    if (mask[i - nks]) dst[i] = src[i];
+  } else if (i < nks + (long long)P * npar) {
+    if (mask[(i - nks) / npar]) dst[i] = src[i];
   }
 }
 
@@ -503,14 +567,14 @@ hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling
   prof_begin(h, 2, st);
   const int bs = h.tune.eval_bs;
   hipLaunchKernelGGL(k_eval, dim3(grid_for(h.nst, bs)), dim3(bs), 0, st, x, sc, scaled, y, cs, h.feeds, h.mp,
-                     h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, full, c_out, h.rec);
+                     h.sinfo, h.nst, h.pact_on ? h.pact : nullptr, full, h.npar, c_out, h.rec);
   prof_end(h, 2, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rowmax(Handle& h, const double* x, int scaled, double* rowmax, hipStream_t st) {
   hipLaunchKernelGGL(k_rowmax, dim3(grid_for(h.nst, 128)), dim3(128), 0, st, x, h.sc, scaled, h.feeds, h.mp, h.sinfo,
-                     h.nst, rowmax);
+                     h.nst, h.npar, rowmax);
   return hipGetLastError();
 }
 
@@ -604,9 +668,13 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   double* omd = omb + 3LL * nb;     // 3 per problem
   prof_begin(h, 3, st);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RBS), 0, st, h.rec, h.rtab, h.rtab_n, diagx, diags, h.dwv, h.dcv, sol,
-                     rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, res, part, omb);
+                     rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, h.npar, res, part, omb);
   prof_end(h, 3, st);
-  hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pseg, h.scal, sol, rhs, nks, pa, res, omd);
+  if (h.npar == 1)
+    hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pseg, h.scal, sol, rhs, nks, pa, res, omd);
+  else
+    hipLaunchKernelGGL(k_residual_design, dim3(h.P), dim3(DBS), 0, st, h.rec, h.pstage, h.sinfo, h.dsc, sol, rhs,
+                       nks, h.jac_d_index, h.npar, pa, res, omd);
   hipLaunchKernelGGL(k_residual_max, dim3(1), dim3(MAX_BS), 0, st, omb, nb, omd, h.P, omega_out);
   return hipGetLastError();
 }
@@ -621,21 +689,22 @@ hipError_t launch_residual_pmax(Handle& h, hipStream_t st) {
 
 hipError_t launch_mask_rows(Handle& h, const int* mask, double* res, hipStream_t st) {
   const long long nks = h.nst * NK;
-  hipLaunchKernelGGL(k_mask_rows, dim3(grid_for(nks + h.P, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, res);
+  hipLaunchKernelGGL(k_mask_rows, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, h.npar,
+                     res);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_rows(Handle& h, const int* mask, double* dst, const double* src, hipStream_t st) {
   const long long nks = h.nst * NK;
-  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for(nks + h.P, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, dst,
-                     src);
+  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, h.npar,
+                     dst, src);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_x0(Handle& h, double* x, hipStream_t st) {
   TileX0 a;
   for (int k = 0; k <= NV; ++k) a.v[k] = h.x0[k];
-  hipLaunchKernelGGL(k_tile_x0, dim3(grid_for(h.nx, 256)), dim3(256), 0, st, a, h.nst, h.P, x);
+  hipLaunchKernelGGL(k_tile_x0, dim3(grid_for(h.nx, 256)), dim3(256), 0, st, a, h.nst, (long long)h.P * h.npar, x);
   return hipGetLastError();
 }
 

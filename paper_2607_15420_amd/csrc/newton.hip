@@ -135,20 +135,22 @@ __global__ void k_stage_diam(const double* __restrict__ x, const double* __restr
   dh[t] = a > 0.0 ? sqrt(a) : 0.0;
 }
 
-// d_p = (1 + margin) max over the problem's stages (one block per problem)
-__global__ void k_problem_max(const double* __restrict__ dh, const long long* __restrict__ pstage, double margin,
-                              double* __restrict__ d) {
+// design entry k of problem p = (1 + margin) max over the problem's stages in
+// section k (one block per entry; one section: d_p over all of its stages)
+__global__ void k_problem_max(const double* __restrict__ dh, const long long* __restrict__ pstage,
+                              const StageInfo* __restrict__ sinfo, int npar, double margin, double* __restrict__ d) {
   __shared__ double sm[BS];
-  const int pb = blockIdx.x;
+  const int pb = blockIdx.x / npar, k = blockIdx.x % npar;
   double m = 0.0;
-  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += BS) m = fmax(m, dh[t]);
+  for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += BS)
+    if (npar == 1 || section_of(sinfo[t].n, sinfo[t].N, npar) == k) m = fmax(m, dh[t]);
   sm[threadIdx.x] = m;
   __syncthreads();
   for (int s = BS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) d[pb] = (1.0 + margin) * sm[0];
+  if (threadIdx.x == 0) d[blockIdx.x] = (1.0 + margin) * sm[0];
 }
 
 struct Buf {
@@ -344,7 +346,8 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
 int set_hydraulic_diameters(Handle& h, double* x_dev, double margin, hipStream_t st) {
   double* dh = h.kden;  // per-stage scratch
   hipLaunchKernelGGL(k_stage_diam, dim3(nblk(h.nst, BS)), dim3(BS), 0, st, x_dev, h.feeds, h.mp, h.sinfo, h.nst, dh);
-  hipLaunchKernelGGL(k_problem_max, dim3(h.P), dim3(BS), 0, st, dh, h.pstage, margin, x_dev + h.nst * NV);
+  hipLaunchKernelGGL(k_problem_max, dim3(h.P * h.npar), dim3(BS), 0, st, dh, h.pstage, h.sinfo, h.npar, margin,
+                     x_dev + h.nst * NV);
   HIP_TRY(hipGetLastError());
   return ABS_OK;
 }

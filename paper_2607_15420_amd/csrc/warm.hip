@@ -158,6 +158,10 @@ inline size_t al256(size_t n) { return (n + 255) / 256 * 256; }
 // decode Y into x0 (and lambda0) with the per-problem index buffer wmax [P]
 static int warm_point(Handle& h, const float* Y_dev, int32_t n_out, double d_margin, double* x0_dev,
                       double* lambda0_dev, int* wmax, hipStream_t st) {
+  if (h.npar != 1) {
+    set_error("warm start: handles with one diameter only (the network predicts one d per problem)");
+    return ABS_ERR_ARG;
+  }
   const long long nst = h.nst;
   double* dh = h.kden;  // per-stage scratch
   hipLaunchKernelGGL(k_decode, dim3(nblk(nst, WB)), dim3(WB), 0, st, Y_dev, n_out, h.feeds, h.mp, h.sinfo, nst, x0_dev,
