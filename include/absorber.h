@@ -72,6 +72,9 @@ typedef struct {
   double x_lo, x_hi, y_lo, y_hi, L_lo, L_hi, V_lo, V_hi, T_lo, T_hi, d_lo, d_hi;
   double x0[21];                          /* cold-start value of every stage */
   double d0;                              /* cold-start diameter */
+  double dp_stage;                        /* pressure relations (eq. 7) with a specified drop per stage [Pa]:
+                                             the top stage is at the feed table's pressure, each stage below
+                                             dp_stage higher; >= 0 (0 in the case study) */
 } absorber_params;
 
 typedef struct {

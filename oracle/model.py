@@ -70,6 +70,8 @@ class OracleParams:
         self.hV_ref, self.cpV_a, self.cpV_b = f(p["hV_ref"]), f(p["cpV_a"]), f(p["cpV_b"])
         self.R = float(p["R"])
         self.u_max = float(p["u_max"])
+        # specified pressure drop per stage of the pressure relations (eq. 7); 0 in the case study
+        self.dp = float(p.get("dp_stage", 0.0))
         self.raw = p
 
 
@@ -83,6 +85,17 @@ def section_weights(n_stages: int, n_sections: int) -> np.ndarray:
     """Weight of each section diameter in the design cost: its share of the stages
     (the shell of a section scales with its height times its diameter)."""
     return np.bincount(sections(n_stages, n_sections), minlength=n_sections) / float(n_stages)
+
+
+def stage_pressures(p_top, n_stages: int, P: OracleParams):
+    """Stage pressures of the pressure relations (7) with a specified drop per
+    stage: the top stage (index N-1) is at p_top (the feed table's absorber
+    pressure) and each stage below is dp higher, P_n = P_{n+1} + dp.  Returns
+    (N,) bottom to top (a tensor when p_top is one, else an array)."""
+    k = np.arange(n_stages - 1, -1, -1, dtype=np.float64)  # stages above stage n
+    if isinstance(p_top, torch.Tensor):
+        return p_top + torch.from_numpy(k) * P.dp
+    return float(p_top) + k * P.dp
 
 
 def _h(T, href, a, b, Tref):
@@ -102,7 +115,7 @@ def scenario_constraints(Z: torch.Tensor, d: torch.Tensor, feed: torch.Tensor, P
     """
     x, y = Z[:, 0:NLIQ], Z[:, NLIQ:NLIQ + NVAP]
     L, V, T, eps = Z[:, IL], Z[:, IV], Z[:, IT], Z[:, IE:IE + 5]
-    Pabs = feed[17]
+    Pabs = stage_pressures(feed[17], Z.shape[0], P)
 
     # stream entering each stage from above (liquid) and from below (vapour)
     L_up = torch.cat([L[1:], feed[6:7]])

@@ -92,7 +92,8 @@ def simulate_scenario(Z0: np.ndarray, feed: np.ndarray, P: M.OracleParams, tol: 
 def hydraulic_diameter(Z: np.ndarray, feed: np.ndarray, P: M.OracleParams) -> float:
     """Smallest d meeting (10b) on every stage of one simulated scenario."""
     V, T = Z[:, M.IV], Z[:, M.IT]
-    return float(np.sqrt(4.0 * V * P.R * T / (math.pi * P.u_max * feed[17])).max())
+    Pn = M.stage_pressures(feed[17], Z.shape[0], P)
+    return float(np.sqrt(4.0 * V * P.R * T / (math.pi * P.u_max * Pn)).max())
 
 
 def closed_form_diameter(feeds: np.ndarray, n_stages: int, params: dict, Z0=None):
@@ -128,7 +129,8 @@ def closed_form_sections(feeds: np.ndarray, n_stages: int, n_sections: int, para
     P = M.OracleParams(params)
     _, _, Zs, ok = closed_form_diameter(feeds, n_stages, params, Z0)
     V, T = Zs[:, :, M.IV], Zs[:, :, M.IT]
-    dh = np.sqrt(4.0 * V * P.R * T / (math.pi * P.u_max * feeds[:, 17][:, None]))  # (S, N)
+    Pn = np.stack([M.stage_pressures(f[17], n_stages, P) for f in feeds])  # (S, N)
+    dh = np.sqrt(4.0 * V * P.R * T / (math.pi * P.u_max * Pn))  # (S, N)
     sec = M.sections(n_stages, n_sections)
     theta = np.array([dh[:, sec == k].max() for k in range(n_sections)])
     return theta, Zs, ok

@@ -47,7 +47,7 @@ class AbsorberParams(ctypes.Structure):
         ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double), ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
         ("L_lo", ctypes.c_double), ("L_hi", ctypes.c_double), ("V_lo", ctypes.c_double), ("V_hi", ctypes.c_double),
         ("T_lo", ctypes.c_double), ("T_hi", ctypes.c_double), ("d_lo", ctypes.c_double), ("d_hi", ctypes.c_double),
-        ("x0", ctypes.c_double * 21), ("d0", ctypes.c_double),
+        ("x0", ctypes.c_double * 21), ("d0", ctypes.c_double), ("dp_stage", ctypes.c_double),
     ]
 
 
@@ -232,6 +232,7 @@ def params_struct(p: dict) -> AbsorberParams:
     for k in range(21):
         s.x0[k] = float(z[k])
     s.d0 = float(ip["d"])
+    s.dp_stage = float(p.get("dp_stage", 0.0))
     return s
 
 

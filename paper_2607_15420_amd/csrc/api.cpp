@@ -357,6 +357,10 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
     set_error("absorber_create_batch: too many stages");
     return ABS_ERR_ARG;
   }
+  if (!(prm->dp_stage >= 0.0) || !std::isfinite(prm->dp_stage)) {
+    set_error("absorber_create: dp_stage must be finite and >= 0");
+    return ABS_ERR_ARG;
+  }
   auto* H = new (std::nothrow) absorber_handle();
   if (!H) return ABS_ERR_OOM;
   Handle& h = H->h;
@@ -401,6 +405,7 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
   }
   mp.R = prm->R;
   mp.u_max = prm->u_max;
+  mp.dp = prm->dp_stage;
   for (int k = 0; k < NV; ++k) {
     h.xL[k] = -INFINITY;
     h.xU[k] = INFINITY;

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_eval(const double* __restrict__ x, Scal
   // the diameter of this stage's section
   const long long xd = nst * NV + (long long)si.p * npar + section_of(n, N, npar);
   const double d = scaled ? x[xd] * sc.Dd : x[xd];
-  const double P = feed[17];
+  const double P = stage_pressure(p, feed[17], n, N);
   double csr[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) csr[r] = cs ? cs[t * NR + r] : 1.0;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(128) void k_rowmax(const double* __restrict__ x, Sc
 #pragma unroll
   for (int r = 0; r < NR; ++r) m[r] = 0.0;
   RowMaxSink sink{m, sc.D, sc.Dd};
-  stage_jacobian(p, z, f, feed[17], d, n < N - 1, n > 0, sink);
+  stage_jacobian(p, z, f, stage_pressure(p, feed[17], n, N), d, n < N - 1, n > 0, sink);
 #pragma unroll
   for (int r = 0; r < NR; ++r) rowmax[t * NR + r] = m[r];
 }
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(128) void k_jac_coo(const double* __restrict__ x, c
   const long long per_scen = (long long)N * NJO + (long long)(N - 1) * (NJU + NJD);
   const long long off = (long long)w * per_scen + (long long)n * (NJO + NJU) + (long long)(n > 0 ? n - 1 : 0) * NJD;
   CooSink sink{vals + off};
-  stage_jacobian(p, z, f, feed[17], x[nx], n < N - 1, n > 0, sink);
+  stage_jacobian(p, z, f, stage_pressure(p, feed[17], n, N), x[nx], n < N - 1, n > 0, sink);
 }
 
 // unscaled Lagrangian Hessian block values (48 per stage) of the public ABI
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(128) void k_hess_coo(const double* __restrict__ x, 
   double z[NV];
   load_stage(x, sc, 0, t, z);
   double H[NH];
-  stage_hessian(p, z, feed[17], n > 0 ? lam + (t - 1) * NR : nullptr, lam + t * NR,
+  stage_hessian(p, z, stage_pressure(p, feed[17], n, N), n > 0 ? lam + (t - 1) * NR : nullptr, lam + t * NR,
                 n < N - 1 ? lam + (t + 1) * NR : nullptr, H);
 #pragma unroll
   for (int e = 0; e < NH; ++e) vals[t * NH + e] = H[e];

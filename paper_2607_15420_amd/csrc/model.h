@@ -51,7 +51,14 @@ struct ModelParams {
   double hL_ref[9], cpL_a[9], cpL_b[9];
   double hV_ref[4], cpV_a[4], cpV_b[4];
   double R, u_max;
+  double dp;  // specified pressure drop per stage (pressure relations, eq. 7)
 };
+
+// pressure of stage n (0 = bottom) of an N-stage column whose top stage is at
+// P_top: eq. (7) with a specified drop, P_n = P_{n+1} + dp
+ABS_HD double stage_pressure(const ModelParams& p, double P_top, int n, int N) {
+  return P_top + (double)(N - 1 - n) * p.dp;
+}
 
 // inflow of a stage: liquid from above (L, x, T) and vapour from below (V, y, T)
 struct Inflow {

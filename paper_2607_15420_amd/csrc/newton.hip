@@ -130,7 +130,8 @@ __global__ void k_stage_diam(const double* __restrict__ x, const double* __restr
                              const StageInfo* __restrict__ sinfo, long long nst, double* __restrict__ dh) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nst) return;
-  const double P = feeds[(long long)sinfo[t].w * NF + 17];
+  const StageInfo si = sinfo[t];
+  const double P = stage_pressure(p, feeds[(long long)si.w * NF + 17], si.n, si.N);
   const double a = 4.0 * x[t * NV + IV] * p.R * x[t * NV + IT] / (M_PI * p.u_max * P);
   dh[t] = a > 0.0 ? sqrt(a) : 0.0;
 }

@@ -65,7 +65,7 @@ __global__ void k_decode(const float* __restrict__ Y, int ld, const double* __re
   double* z = x0 + t * NV;
 #pragma unroll
   for (int k = 0; k < NV; ++k) z[k] = k < NLOG ? exp((double)y[k]) : (double)y[k];
-  const double P = feeds[(long long)si.w * NF + 17];
+  const double P = stage_pressure(p, feeds[(long long)si.w * NF + 17], si.n, si.N);
   const double V = z[IV], T = z[IT];
   const double a = 4.0 * V * p.R * T / (M_PI * p.u_max * P);
   dh[t] = a > 0.0 ? sqrt(a) : 0.0;
