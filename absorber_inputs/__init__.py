@@ -21,9 +21,12 @@ Feed table layout (one row per scenario, ``NF = 18`` doubles, row-major):
 from .scenarios import (  # noqa: F401
     NF,
     CONFIGS,
+    N_BASE_CASES,
+    base_cases,
+    batch_problems,
+    convex_combinations,
     dims,
     feed_table,
     load_params,
     perturbations,
-    batch_problems,
 )

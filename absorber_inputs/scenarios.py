@@ -2,10 +2,19 @@
 
 The paper samples its scenarios as random convex combinations of seven measured
 operating cases (Case study, problem setup); those measurements are not
-published with the text.  The synthetic stand-in used here perturbs the
-nominal flue-gas flow, CO2 mole fraction and inlet temperature by iid uniform
-relative amounts, drawn from a NumPy PCG64 generator with a fixed seed.  N2
-absorbs the change of the CO2 fraction so the gas fractions still sum to one.
+published with the text.  Two synthetic stand-ins are provided, both drawn
+from NumPy PCG64 generators with fixed seeds:
+
+* iid uniform relative perturbations of the nominal flue-gas flow, CO2 mole
+  fraction and inlet temperature (the benchmarked workloads);
+* the paper's sampling scheme applied to seven synthetic base cases (relative
+  perturbations drawn once from their own seed in place of the measurements):
+  each scenario is a convex combination of the seven cases with weights drawn
+  uniformly from the simplex (Dirichlet(1, ..., 1)).
+
+N2 absorbs the change of the CO2 fraction so the gas fractions still sum to
+one.  The feed table is affine in the perturbations, so a convex combination
+of perturbations gives the same convex combination of the cases' feed rows.
 """
 
 from __future__ import annotations
@@ -37,6 +46,26 @@ def perturbations(n_scen: int, amplitude: float, seed: int) -> np.ndarray:
     return rng.uniform(-amplitude, amplitude, (n_scen, 3))
 
 
+N_BASE_CASES = 7
+
+
+def base_cases(seed: int = 6, amplitude: float = 0.20) -> np.ndarray:
+    """Seven synthetic operating cases standing in for the paper's measured ones:
+    relative perturbations (gas flow, y_CO2, T_gas), shape (7, 3)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amplitude, amplitude, (N_BASE_CASES, 3))
+
+
+def convex_combinations(cases: np.ndarray, n_scen: int, seed: int):
+    """Scenarios as random convex combinations of the base cases: weights w
+    (S, K) uniform on the simplex (Dirichlet(1, ..., 1)), perturbations w @ cases.
+    Returns (perturbations (S, 3), weights (S, K))."""
+    cases = np.asarray(cases, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    w = rng.dirichlet(np.ones(cases.shape[0]), n_scen)
+    return w @ cases, w
+
+
 def feed_table(pert: np.ndarray, params: dict | None = None) -> np.ndarray:
     """Build the (S, NF) feed table from relative perturbations (S, 3)."""
     p = params or load_params()
@@ -66,8 +95,11 @@ class Workload:
     amplitude: float
     seed: int
     description: str
+    sampler: str = "uniform"  # "uniform": iid perturbations; "convex": combinations of the base cases
 
     def pert(self) -> np.ndarray:
+        if self.sampler == "convex":
+            return convex_combinations(base_cases(amplitude=self.amplitude), self.n_scen, self.seed)[0]
         return perturbations(self.n_scen, self.amplitude, self.seed)
 
     def feeds(self, params: dict | None = None) -> np.ndarray:
@@ -81,6 +113,8 @@ CONFIGS = {
     "C2": Workload("C2", 10, 500, 0.10, 1, "10 stages x 500 scenarios, +-10%, seed 1"),
     "C3": Workload("C3", 10, 5000, 0.20, 2, "10 stages x 5000 scenarios, +-20%, seed 2"),
     "C4": Workload("C4", 10, 5000, 0.20, 3, "warm-start test instance, 10 x 5000, +-20%, seed 3"),
+    # the paper's sampling scheme on synthetic base cases (seed 6, +-20%)
+    "C6": Workload("C6", 10, 5000, 0.20, 7, "10 x 5000, convex combinations of 7 base cases, seed 7", "convex"),
 }
 
 # warm-start training data: 20000 single-scenario problems, +-20%, seed 4

@@ -103,6 +103,14 @@ def test_c3_full_size(params):
     assert r.iterations <= 60
 
 
+def test_c6_convex_combination_scenarios_full_size(params):
+    """10 stages x 5000 scenarios drawn as convex combinations of seven base
+    cases (the paper's sampling scheme on synthetic cases): the same checks as
+    the benchmarked workload."""
+    r = check_full_size(params, CONFIGS["C6"], 8, 6, mesh_sample=20)
+    assert r.iterations <= 60
+
+
 def test_autotune_keeps_the_result(params):
     """Launch shapes chosen by measurement change the speed, not the arithmetic:
     the solve with the tuned shapes is bit-identical to the default shapes."""
