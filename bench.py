@@ -271,7 +271,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-scen", type=int, default=4)
+    ap.add_argument("--cpu-scen", type=int, default=16)
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--batch-problems", type=int, default=64)
