@@ -122,6 +122,8 @@ class Problem:
         self.S, self.N = self.feeds.shape[0], int(n_stages)
         self.npar = int(n_sections)
         self.c = M.section_weights(self.N, self.npar)  # design-cost weight of each diameter
+        # the expected operating cost sum_k a_k theta_k^-4 (zero weight: the case study's objective)
+        self.a = M.operating_coefficients(self.feeds, self.N, self.npar, self.P)
         self.nz = self.S * self.N * M.NV
         self.n = self.nz + self.npar
         self.mI = self.S * self.N
@@ -201,10 +203,12 @@ class OracleIPM:
             g = np.abs(J).max(axis=1).reshape(pr.N, M.NR)
             cs[w] = np.minimum(1.0, o.nlp_scaling_max_gradient / np.maximum(g, 1e-300))
         self.cs = cs
-        if pr.npar == 1:
-            self.sf = min(1.0, o.nlp_scaling_max_gradient / self.D[-1])  # grad f = e_d
-        else:  # grad f = the section weights c in the original variables
-            self.sf = min(1.0, o.nlp_scaling_max_gradient / float(np.max(pr.c * self.D[-pr.npar:])))
+        # gradient-based objective scaling: grad f = c - 4 a theta^-5 in the original
+        # design variables (c = 1, a = 0 for problem (10)), at the cold point
+        q = pr.npar
+        th0 = self.D[-q:] * x0[-q:]
+        gmax = float(np.max(np.abs(pr.c - 4.0 * pr.a * th0 ** -5.0) * self.D[-q:]))
+        self.sf = min(1.0, o.nlp_scaling_max_gradient / gmax)
 
     def push_into_bounds(self, x, push, frac):
         """A-1 bound push: move x strictly inside [xL, xU] (Ipopt's kappa_1, kappa_2 rule)."""
@@ -225,13 +229,26 @@ class OracleIPM:
         c = self.pr.cons(self.D * x) * self.cs
         return c[:, :, :M.NR - 1], c[:, :, M.NR - 1]  # cE (S,N,21), dI (S,N)
 
-    def grad_f(self):
+    def grad_f(self, x):
+        """Gradient of the scaled objective sf (sum_k c_k theta_k + a_k theta_k^-4)
+        with respect to the scaled variables (theta = D x on the design entries)."""
+        q = self.pr.npar
         g = np.zeros(self.pr.n)
-        if self.pr.npar == 1:
-            g[-1] = self.sf * self.D[-1]
-        else:
-            g[-self.pr.npar:] = self.sf * self.D[-self.pr.npar:] * self.pr.c
+        th = self.D[-q:] * x[-q:]
+        g[-q:] = self.sf * self.D[-q:] * (self.pr.c - 4.0 * self.pr.a * th ** -5.0)
         return g
+
+    def hess_f(self, x):
+        """Diagonal of the scaled objective's Hessian on the design entries, (p,)."""
+        q = self.pr.npar
+        th = self.D[-q:] * x[-q:]
+        return self.sf * self.D[-q:] ** 2 * 20.0 * self.pr.a * th ** -6.0
+
+    def f_nonlinear(self, x):
+        """The operating-cost part of the scaled objective, sf sum_k a_k theta_k^-4."""
+        q = self.pr.npar
+        th = self.D[-q:] * x[-q:]
+        return self.sf * float(np.sum(self.pr.a * th ** -4.0))
 
     def block_scale(self, w):
         nzs = self.pr.N * M.NV
@@ -277,13 +294,14 @@ class OracleIPM:
             return np.inf
         q = self.pr.npar
         phi = self.sf * x[-1] if q == 1 else self.sf * float((self.pr.c * self.D[-q:]) @ x[-q:])
+        phi += self.f_nonlinear(x)
         phi -= mu * (np.log(sL[self.hasL]).sum() + np.log(sU[self.hasU]).sum() + np.log(-s).sum())
         phi += self.o.kappa_d * mu * (sL[self.onlyL].sum() + sU[self.onlyU].sum() + (-s).sum())
         return phi
 
     def grad_phi(self, x, s, mu):
         sL, sU = self.slacks(x)
-        g = self.grad_f()
+        g = self.grad_f(x)
         g = g - np.where(self.hasL, mu / sL, 0.0) + np.where(self.hasU, mu / sU, 0.0)
         g = g + self.o.kappa_d * mu * (self.onlyL.astype(float) - self.onlyU.astype(float))
         gs = mu / (-s) - self.o.kappa_d * mu
@@ -297,7 +315,7 @@ class OracleIPM:
     def opt_error(self, x, s, yc, yd, zL, zU, vU, Jb, cE, dI, mu):
         o = self.o
         sL, sU = self.slacks(x)
-        gl = self.grad_f() + self.JT_times(Jb, yc, yd) - zL + zU
+        gl = self.grad_f(x) + self.JT_times(Jb, yc, yd) - zL + zU
         gls = -yd + vU
         dual = max(np.abs(gl).max(), np.abs(gls).max())
         primal = max(np.abs(cE).max(), np.abs(dI - s).max())
@@ -312,7 +330,9 @@ class OracleIPM:
         return max(dual / sd, primal, comp / sc), dual, primal, comp
 
     # ---- KKT ----
-    def factor(self, x, yc, yd, sig_x, sig_s, dw, dc, Jb):
+    def factor(self, x, yc, yd, sig_x, sig_s, dw, dc, Jb, objective=True):
+        """The bordered KKT at x; objective=False leaves out the objective's
+        curvature (the least-squares multiplier system has the identity block)."""
         pr = self.pr
         lam = np.concatenate([yc, yd[:, :, None]], axis=2) * self.cs  # unscaled-row weights
         Hb = pr.hess_blocks(self.D * x, lam)
@@ -326,10 +346,11 @@ class OracleIPM:
             blocks.append(K)
             borders.append(b)
             kdd = kdd + hdd
+        hf = self.hess_f(x) if objective else np.zeros(q)  # the objective's curvature in the design entries
         if q == 1:
-            kdd += sig_x[-1] + dw
+            kdd += sig_x[-1] + dw + float(hf[0])
         else:
-            kdd = kdd + np.diag(sig_x[-q:] + dw)
+            kdd = kdd + np.diag(sig_x[-q:] + dw + hf)
         return BorderedKKT(blocks, borders, kdd)
 
     def kkt_solve(self, F, rx, rc, rd):
@@ -420,8 +441,8 @@ class OracleIPM:
             sig0x = np.zeros(pr.n)
             sig0s = np.zeros((pr.S, pr.N))
             F = self.factor(x, np.zeros((pr.S, pr.N, M.NR - 1)), np.zeros((pr.S, pr.N)),
-                            sig0x, sig0s, 1.0, 0.0, Jb)
-            rx = -(self.grad_f() - zL + zU)
+                            sig0x, sig0s, 1.0, 0.0, Jb, objective=False)
+            rx = -(self.grad_f(x) - zL + zU)
             _, yc, yd = self.kkt_solve(F, rx, np.zeros((pr.S, pr.N, M.NR - 1)), -vU)
             if max(np.abs(yc).max(), np.abs(yd).max()) > o.constr_mult_init_max:
                 yc = np.zeros_like(yc)

@@ -72,6 +72,11 @@ class OracleParams:
         self.u_max = float(p["u_max"])
         # specified pressure drop per stage of the pressure relations (eq. 7); 0 in the case study
         self.dp = float(p.get("dp_stage", 0.0))
+        # expected blower cost of the scenario NLP's operating term (eq. 8a); weight 0 in the case study
+        op = p.get("operating_cost", {})
+        self.op_weight = float(op.get("weight", 0.0))
+        self.op_loss = float(op.get("loss_coef", 0.0))
+        self.op_M = np.asarray(op.get("molar_mass", [0.0, 0.0, 0.0, 0.0]), dtype=np.float64)
         self.raw = p
 
 
@@ -96,6 +101,24 @@ def stage_pressures(p_top, n_stages: int, P: OracleParams):
     if isinstance(p_top, torch.Tensor):
         return p_top + torch.from_numpy(k) * P.dp
     return float(p_top) + k * P.dp
+
+
+def operating_coefficients(feeds: np.ndarray, n_stages: int, n_sections: int, P: OracleParams) -> np.ndarray:
+    """Coefficients a_k of the expected operating cost sum_w p_w C^op_w = sum_k a_k theta_k^-4 (eq. 8a).
+
+    C^op_w is the weight times the blower power of scenario w: the inlet gas (flow
+    V_0, temperature T_gas, molar mass M_w of its composition) enters at the
+    bottom stage's pressure P_in (eq. 7), with volume flow Q = V_0 R T_gas / P_in
+    and density rho = P_in M_w / (R T_gas); each stage of section k loses
+    loss_coef rho u^2 / 2 at the superficial velocity u = Q / (pi theta_k^2 / 4),
+    so the power is sum_k N_k (8 loss_coef / pi^2) rho Q^3 / theta_k^4.  The
+    scenarios are equally likely (p_w = 1 / S).  Returns (p,)."""
+    feeds = np.asarray(feeds, dtype=np.float64)
+    Nk = np.bincount(sections(n_stages, n_sections), minlength=n_sections).astype(np.float64)
+    p_in = np.array([stage_pressures(f[17], n_stages, P)[0] for f in feeds])
+    Q = feeds[:, 0] * P.R * feeds[:, 5] / p_in
+    rho = p_in * (feeds[:, 1:5] @ P.op_M) / (P.R * feeds[:, 5])
+    return P.op_weight * 8.0 * P.op_loss * Nk / math.pi ** 2 * float(np.mean(rho * Q ** 3))
 
 
 def _h(T, href, a, b, Tref):

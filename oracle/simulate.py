@@ -134,3 +134,18 @@ def closed_form_sections(feeds: np.ndarray, n_stages: int, n_sections: int, para
     sec = M.sections(n_stages, n_sections)
     theta = np.array([dh[:, sec == k].max() for k in range(n_sections)])
     return theta, Zs, ok
+
+
+def closed_form_design(feeds: np.ndarray, n_stages: int, n_sections: int, params: dict, Z0=None):
+    """Optimum of the design problem with the operating cost of eq. (8a): each
+    section's objective term c_k theta_k + a_k theta_k^-4 is convex and its
+    only lower bound is the section's hydraulic minimum, so theta_k* =
+    max(theta_hyd,k, (4 a_k / c_k)^(1/5)), clipped to the diameter bounds.
+    Returns (theta* (p,), states, converged flags)."""
+    P = M.OracleParams(params)
+    th_h, Zs, ok = closed_form_sections(feeds, n_stages, n_sections, params, Z0)
+    a = M.operating_coefficients(feeds, n_stages, n_sections, P)
+    c = M.section_weights(n_stages, n_sections)
+    th = np.maximum(th_h, (4.0 * a / c) ** 0.2)
+    lo, hi = params["bounds"]["d"]
+    return np.clip(th, lo, hi), Zs, ok
