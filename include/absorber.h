@@ -75,6 +75,15 @@ typedef struct {
   double dp_stage;                        /* pressure relations (eq. 7) with a specified drop per stage [Pa]:
                                              the top stage is at the feed table's pressure, each stage below
                                              dp_stage higher; >= 0 (0 in the case study) */
+  /* Expected operating cost of the scenario NLP's objective (eq. 8a), a blower
+   * cost: op_weight x the power of each equally likely scenario, whose inlet gas
+   * (flow, temperature, molar mass from op_molar_mass of CO2, H2O, N2, O2 [kg/mol])
+   * enters at the bottom stage's pressure and loses op_loss_coef rho u^2 / 2 in
+   * each stage at the superficial velocity u of its (section's) diameter; the
+   * objective becomes sum_k c_k theta_k + a_k theta_k^-4.  op_weight = 0 (the
+   * case study) leaves the objective d; op_weight > 0 only for single-problem
+   * handles (ABS_ERR_ARG for a batch).  Both >= 0. */
+  double op_weight, op_loss_coef, op_molar_mass[4];
 } absorber_params;
 
 typedef struct {

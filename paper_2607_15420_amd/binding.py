@@ -48,6 +48,7 @@ class AbsorberParams(ctypes.Structure):
         ("L_lo", ctypes.c_double), ("L_hi", ctypes.c_double), ("V_lo", ctypes.c_double), ("V_hi", ctypes.c_double),
         ("T_lo", ctypes.c_double), ("T_hi", ctypes.c_double), ("d_lo", ctypes.c_double), ("d_hi", ctypes.c_double),
         ("x0", ctypes.c_double * 21), ("d0", ctypes.c_double), ("dp_stage", ctypes.c_double),
+        ("op_weight", ctypes.c_double), ("op_loss_coef", ctypes.c_double), ("op_molar_mass", ctypes.c_double * 4),
     ]
 
 
@@ -233,6 +234,11 @@ def params_struct(p: dict) -> AbsorberParams:
         s.x0[k] = float(z[k])
     s.d0 = float(ip["d"])
     s.dp_stage = float(p.get("dp_stage", 0.0))
+    op = p.get("operating_cost", {})
+    s.op_weight = float(op.get("weight", 0.0))
+    s.op_loss_coef = float(op.get("loss_coef", 0.0))
+    for j, m in enumerate(op.get("molar_mass", [0.0] * 4)):
+        s.op_molar_mass[j] = float(m)
     return s
 
 

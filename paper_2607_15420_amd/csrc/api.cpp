@@ -292,7 +292,7 @@ static void free_handle(Handle& h) {
   void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
-                  h.seg, h.pseg, h.ctl, h.ipm_work, h.pres, h.rmask, h.solbk, h.brhs, h.pdots, h.dsc};
+                  h.seg, h.pseg, h.ctl, h.ipm_work, h.pres, h.rmask, h.solbk, h.brhs, h.pdots, h.dsc, h.opa};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h.scal_h) (void)hipHostFree(h.scal_h);
@@ -359,6 +359,15 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
   }
   if (!(prm->dp_stage >= 0.0) || !std::isfinite(prm->dp_stage)) {
     set_error("absorber_create: dp_stage must be finite and >= 0");
+    return ABS_ERR_ARG;
+  }
+  if (!(prm->op_weight >= 0.0) || !std::isfinite(prm->op_weight) || !(prm->op_loss_coef >= 0.0) ||
+      !std::isfinite(prm->op_loss_coef)) {
+    set_error("absorber_create: op_weight and op_loss_coef must be finite and >= 0");
+    return ABS_ERR_ARG;
+  }
+  if (prm->op_weight > 0.0 && n_problems > 1) {
+    set_error("absorber_create_batch: the operating cost is for single-problem handles (one objective scaling)");
     return ABS_ERR_ARG;
   }
   auto* H = new (std::nothrow) absorber_handle();
@@ -489,6 +498,7 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
     ALLOC(h.pdots, (size_t)h.S * PDOT);
     ALLOC(h.dsc, (size_t)h.P * DSC);
   }
+  ALLOC(h.opa, (size_t)h.P * npar);
   ALLOC(h.sinfo, nst);
   ALLOC(h.chain0, W + 1);
   ALLOC(h.chain_p, W);
@@ -534,6 +544,36 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
       hipMemcpy(h.pseg, pseg.data(), sizeof(int) * pseg.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(h.dwv, 0, sizeof(double) * h.P) != hipSuccess ||
       hipMemset(h.dcv, 0, sizeof(double) * h.P) != hipSuccess)
+    return fail(ABS_ERR_HIP);
+  // coefficients a_k of the expected operating cost sum_k a_k theta_k^-4 (eq. 8a):
+  // the weight times the blower power of each equally likely scenario, whose
+  // inlet gas (flow V0, temperature T, molar mass of its composition) enters at
+  // the bottom stage's pressure and loses loss_coef rho u^2 / 2 in each stage of
+  // section k at the superficial velocity u = Q / (pi theta_k^2 / 4)
+  h.opa_h.assign((size_t)h.P * npar, 0.0);
+  h.has_op = prm->op_weight > 0.0;
+  if (h.has_op) {
+    long long w0 = 0;
+    for (int p = 0; p < n_problems; ++p) {
+      const int N = n_stages[p];
+      double acc = 0.0;
+      for (int s = 0; s < n_scen[p]; ++s) {
+        const double* f = feeds_host + (size_t)(w0 + s) * NF;
+        const double p_in = stage_pressure(h.mp, f[17], 0, N);
+        const double Q = f[0] * prm->R * f[5] / p_in;
+        double Mg = 0.0;
+        for (int j = 0; j < 4; ++j) Mg += f[1 + j] * prm->op_molar_mass[j];
+        const double rho = p_in * Mg / (prm->R * f[5]);
+        acc += rho * Q * Q * Q;
+      }
+      acc /= n_scen[p];
+      for (int n = 0; n < N; ++n)
+        h.opa_h[(size_t)p * npar + section_of(n, N, npar)] +=
+            prm->op_weight * 8.0 * prm->op_loss_coef / (M_PI * M_PI) * acc;
+      w0 += n_scen[p];
+    }
+  }
+  if (hipMemcpy(h.opa, h.opa_h.data(), sizeof(double) * h.opa_h.size(), hipMemcpyHostToDevice) != hipSuccess)
     return fail(ABS_ERR_HIP);
   if ((rc = build_tables(h)) != ABS_OK) return fail(rc);
   if ((rc = reset_row_scale(h)) != ABS_OK) return fail(rc);
@@ -662,20 +702,24 @@ int absorber_eval_obj(absorber_t* H, const double* x_dev, double* f_host, double
   }
   Handle& h = H->h;
   hipStream_t st = (hipStream_t)stream;
-  // f = sum_k c_k theta_k (c_k: the share of stages in section k; f = d with one diameter)
+  // f = sum_k c_k theta_k + a_k theta_k^-4 (c_k: the share of stages in section k,
+  // a_k: the expected operating cost's coefficients; f = d for problem (10))
   const long long nd = h.npar, nxs = h.nx - nd;
-  double th[MAX_NPAR];
-  if (f_host) HIP_TRY(hipMemcpyAsync(th, x_dev + nxs, sizeof(double) * nd, hipMemcpyDeviceToHost, st));
+  double th[MAX_NPAR], g[MAX_NPAR];
+  HIP_TRY(hipMemcpyAsync(th, x_dev + nxs, sizeof(double) * nd, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double f = 0.0;
+  for (int k = 0; k < nd; ++k) {
+    const double a = h.opa_h[(size_t)k], t4 = th[k] * th[k] * th[k] * th[k];
+    f += h.cw[k] * th[k] + (a != 0.0 ? a / t4 : 0.0);
+    g[k] = h.cw[k] - (a != 0.0 ? 4.0 * a / (t4 * th[k]) : 0.0);
+  }
   if (grad_dev) {
     HIP_TRY(hipMemsetAsync(grad_dev, 0, sizeof(double) * nxs, st));
-    HIP_TRY(hipMemcpyAsync(grad_dev + nxs, h.cw, sizeof(double) * nd, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(grad_dev + nxs, g, sizeof(double) * nd, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
   }
-  HIP_TRY(hipStreamSynchronize(st));
-  if (f_host) {
-    double f = 0.0;
-    for (int k = 0; k < nd; ++k) f += h.cw[k] * th[k];
-    *f_host = f;
-  }
+  if (f_host) *f_host = f;
   return ABS_OK;
 }
 

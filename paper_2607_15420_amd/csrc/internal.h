@@ -115,6 +115,9 @@ struct Handle {
   int P = 1;                                 // independent problems
   int npar = 1;                              // design variables per problem (section diameters)
   double cw[MAX_NPAR] = {1, 0, 0, 0};        // design-cost weight of each section diameter (its share of stages)
+  bool has_op = false;                       // the objective carries the expected operating cost sum a theta^-4
+  std::vector<double> opa_h;                 // [P * npar] its coefficients a_k (host)
+  double* opa = nullptr;                     // device copy
   int N = 0, S = 0;                          // P == 1: stages and scenarios; otherwise the largest
                                              // stage count and the number of chains
   long long nst = 0;                         // stages of all problems

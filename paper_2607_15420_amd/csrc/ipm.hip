@@ -49,14 +49,36 @@ struct Bnd {
   double lo[NV + 1], hi[NV + 1];
 };
 
-// gradient of the scaled objective f~ = sf sum_k c_k D_d theta_k with respect to
-// each scaled design entry (g[k] = sf D_d c_k), and the section weights c_k
+// The scaled objective f~ = sf sum_k (c_k theta_k + a_k theta_k^-4), theta_k =
+// D_d xt_k: the design cost and the expected operating cost of eq. (8a) (a = 0
+// without it).  g[k] = sf D_d c_k is the gradient of the linear part; a holds
+// a_k per design entry (problem-major), null when there is no operating cost.
 struct Obj {
   double g[MAX_NPAR], c[MAX_NPAR];
+  const double* a;
+  double sf, Dd;
   int npar;
 };
-__device__ __forceinline__ double obj_g(const Obj& o, long long i, long long nxs) {
-  return i >= nxs ? o.g[(i - nxs) % o.npar] : 0.0;
+// gradient with respect to design entry i (0 for a stage entry) at its value xi
+__device__ __forceinline__ double obj_g(const Obj& o, long long i, long long nxs, double xi) {
+  if (i < nxs) return 0.0;
+  const long long j = i - nxs;
+  const double g = o.g[j % o.npar];
+  if (!o.a) return g;
+  const double th = o.Dd * xi, t2 = th * th;
+  return g - o.sf * o.Dd * 4.0 * o.a[j] / (t2 * t2 * th);
+}
+// curvature of the operating cost at design entry i (0 without it)
+__device__ __forceinline__ double obj_h(const Obj& o, long long i, long long nxs, double xi) {
+  if (i < nxs || !o.a) return 0.0;
+  const double th = o.Dd * xi, t2 = th * th;
+  return o.sf * o.Dd * o.Dd * 20.0 * o.a[i - nxs] / (t2 * t2 * t2);
+}
+// the operating-cost part of f~ contributed by design entry i
+__device__ __forceinline__ double obj_fnl(const Obj& o, long long i, long long nxs, double xi) {
+  if (i < nxs || !o.a) return 0.0;
+  const double th = o.Dd * xi, t2 = th * th;
+  return o.sf * o.a[i - nxs] / (t2 * t2);
 }
 
 __device__ __forceinline__ int lidx(long long i, long long nxs) { return i >= nxs ? NV : (int)(i % NV); }
@@ -233,9 +255,10 @@ __global__ __launch_bounds__(GBS) void k_lag_grad(const double* __restrict__ rec
 
 // g_d = sf * D_d + the problem's hydraulic-row terms (one block per problem,
 // fixed order over its segments)
-__global__ void k_grad_d(const double* __restrict__ dpart, const int* __restrict__ pseg, Obj ob, long long nxs,
-                         double* __restrict__ g) {
-  const double gf = ob.g[0];
+__global__ void k_grad_d(const double* __restrict__ dpart, const int* __restrict__ pseg, Obj ob,
+                         const double* __restrict__ x, long long nxs, double* __restrict__ g) {
+  const int pd = blockIdx.x;
+  const double gf = obj_g(ob, nxs + pd, nxs, x[nxs + pd]);
   __shared__ double sm[BS];
   const int p = blockIdx.x;
   double a = 0.0;
@@ -255,7 +278,8 @@ constexpr int DGS = 256;
 __global__ __launch_bounds__(DGS) void k_grad_design(const double* __restrict__ rec, const double* __restrict__ y,
                                                      const long long* __restrict__ pstage,
                                                      const StageInfo* __restrict__ sinfo, int jd, Obj ob,
-                                                     long long nxs, double* __restrict__ g) {
+                                                     const double* __restrict__ x, long long nxs,
+                                                     double* __restrict__ g) {
   __shared__ double sm[MAX_NPAR][DGS];
   const int pb = blockIdx.x;
   double a[MAX_NPAR] = {0, 0, 0, 0};
@@ -275,7 +299,10 @@ __global__ __launch_bounds__(DGS) void k_grad_design(const double* __restrict__ 
       for (int q = 0; q < MAX_NPAR; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + h];
     __syncthreads();
   }
-  if ((int)threadIdx.x < ob.npar) g[nxs + (long long)pb * ob.npar + threadIdx.x] = ob.g[threadIdx.x] + sm[threadIdx.x][0];
+  if ((int)threadIdx.x < ob.npar) {
+    const long long i = nxs + (long long)pb * ob.npar + threadIdx.x;
+    g[i] = obj_g(ob, i, nxs, x[i]) + sm[threadIdx.x][0];
+  }
 }
 
 // ---- optimality-error partials per segment
@@ -331,8 +358,9 @@ __global__ void k_opt_parts(const Seg* __restrict__ seg, const double* __restric
 }
 
 // ---- barrier diagonals
+// (the design entries also carry the operating cost's curvature)
 __global__ void k_sigma(const double* __restrict__ x, const double* __restrict__ zL, const double* __restrict__ zU,
-                        const double* __restrict__ s, const double* __restrict__ vU, Bnd b, long long nx,
+                        const double* __restrict__ s, const double* __restrict__ vU, Bnd b, Obj ob, long long nx,
                         long long nxs, long long nst, double* __restrict__ dx, double* __restrict__ ds) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
   if (i < nx) {
@@ -340,7 +368,7 @@ __global__ void k_sigma(const double* __restrict__ x, const double* __restrict__
     double sg = 0.0;
     if (isfinite(b.lo[k])) sg += zL[i] / (x[i] - b.lo[k]);
     if (isfinite(b.hi[k])) sg += zU[i] / (b.hi[k] - x[i]);
-    dx[i] = sg;
+    dx[i] = sg + obj_h(ob, i, nxs, x[i]);
   }
   if (i < nst) ds[i] = vU[i] / (-s[i]);
 }
@@ -370,7 +398,7 @@ __global__ void k_rhs(const Seg* __restrict__ seg, const PS* __restrict__ ps, co
   if (i >= 0) {
     const int k = lidx(i, nxs);
     // g holds grad f~ + J~^T y; remove grad f~ for d since barrier_grad adds it
-    const double gf = obj_g(ob, i, nxs);
+    const double gf = obj_g(ob, i, nxs, x[i]);
     const double gl = (k == NV) ? g[i] - gf : g[i];
     rhs[kkt_of_primal(i, nxs, nks)] = q.active ? -(gl + barrier_grad(x[i], k, b, mu, kd, gf)) : 0.0;
   }
@@ -426,7 +454,7 @@ __global__ void k_direction(const Seg* __restrict__ seg, const PS* __restrict__ 
     }
     dzL[i] = a;
     dzU[i] = bz;
-    p.v[2] += barrier_grad(xi, k, b, mu, kd, obj_g(ob, i, nxs)) * d;
+    p.v[2] += barrier_grad(xi, k, b, mu, kd, obj_g(ob, i, nxs, xi)) * d;
   }
   const long long j = V.ci();
   if (j >= 0) dy[j] = sol[kkt_of_row(j)];
@@ -479,7 +507,7 @@ __global__ void k_trial_first(const Seg* __restrict__ seg, const PS* __restrict_
 
 // line-search partials at a point: 0 theta (1-norm), 1 barrier sum, 2 infeasible count
 __global__ void k_ls_parts(const Seg* __restrict__ seg, const PS* __restrict__ ps, const double* __restrict__ xt,
-                           const double* __restrict__ st, const double* __restrict__ c, Bnd b, double kd,
+                           const double* __restrict__ st, const double* __restrict__ c, Bnd b, double kd, Obj ob,
                            long long nxs, double* __restrict__ out) {
   const SegView V(seg);
   const double mu = ps[V.p].mu;
@@ -501,6 +529,7 @@ __global__ void k_ls_parts(const Seg* __restrict__ seg, const PS* __restrict__ p
       else p.v[1] -= mu * log(su);
       if (!hl) p.v[1] += kd * mu * su;
     }
+    if (i >= nxs && xt[i] > 0.0) p.v[1] += obj_fnl(ob, i, nxs, xt[i]);  // operating cost at this point
   }
   const long long j = V.ci();
   if (j >= 0) {
@@ -593,11 +622,11 @@ __global__ void k_init_slack(const double* __restrict__ c, double* __restrict__ 
 }
 
 // rhs of the least-squares multiplier system [[I, J^T], [J, 0]] (slack block eliminated)
-__global__ void k_ls_rhs(const double* __restrict__ zL, const double* __restrict__ zU, const double* __restrict__ vU,
-                         Obj ob, long long nx, long long nxs, long long nks, long long nst,
-                         double* __restrict__ rhs) {
+__global__ void k_ls_rhs(const double* __restrict__ x, const double* __restrict__ zL, const double* __restrict__ zU,
+                         const double* __restrict__ vU, Obj ob, long long nx, long long nxs, long long nks,
+                         long long nst, double* __restrict__ rhs) {
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
-  if (i < nx) rhs[kkt_of_primal(i, nxs, nks)] = -(obj_g(ob, i, nxs) - zL[i] + zU[i]);
+  if (i < nx) rhs[kkt_of_primal(i, nxs, nks)] = -(obj_g(ob, i, nxs, x[i]) - zL[i] + zU[i]);
   if (i < nst) rhs[i * NK + NK - 1] = -vU[i];
 }
 
@@ -1194,13 +1223,13 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
       hipLaunchKernelGGL(k_lag_grad, dim3(nseg), dim3(GBS), 0, st, h.rec, h.gtab, h.gtab_n, W.y, h.seg, h.sinfo,
                          nst, h.jac_d_index, W.g, W.dpart);
       if (h.npar == 1)
-        hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, ob, nxs, W.g);
+        hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, ob, W.xt, nxs, W.g);
       else
         hipLaunchKernelGGL(k_grad_design, dim3(P), dim3(DGS), 0, st, h.rec, W.y, h.pstage, h.sinfo, h.jac_d_index,
-                           ob, nxs, W.g);
+                           ob, W.xt, nxs, W.g);
       hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s,
                          W.vU, b, nxs, h.redbuf);
-      hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nxs, nst, h.diagx,
+      hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, ob, nx, nxs, nst, h.diagx,
                          h.diags);
       hipLaunchKernelGGL(k_seg_reduce<9>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg,
                          Ops<9>{{1, 1, 1, 1, 2, 1, 0, 0, 0}}, h.redbuf + 9LL * nseg);
@@ -1251,7 +1280,7 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
                          W.st);
       HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
       hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d,
-                         nxs, h.redbuf);
+                         ob, nxs, h.redbuf);
       hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg, Ops<3>{{0, 0, 0}},
                          out + 7LL * P);
       hipLaunchKernelGGL(k_ctl_ls, dim3(gp), dim3(64), 0, st, g, out + 7LL * P, C, phi_d);
@@ -1262,7 +1291,7 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
       hipLaunchKernelGGL(k_direction, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.zL, W.zU, W.y, W.s,
                          W.vU, h.diags, W.sol, b, C.kappa_d, ob, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
                          h.redbuf);
-      hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
+      hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, ob, nxs,
                          h.redbuf + 4LL * nseg);
       hipLaunchKernelGGL(k_seg_reduce<4>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg, Ops<4>{{2, 2, 0, 0}}, out);
       hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(RS), 0, st, h.redbuf + 4LL * nseg, h.pseg,
@@ -1618,15 +1647,26 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
                      0.0, C.zinit, nx, nxs);
   HIP_TRY(launch_rowmax(h, W.xt, 1, W.rowmax, st));
   hipLaunchKernelGGL(k_rowscale, dim3(gc), dim3(BS), 0, st, W.rowmax, o.nlp_scaling_max_gradient, nc, h.cs);
-  // gradient-based objective scaling: f = sum_k c_k theta_k has the gradient
-  // c_k D_d with respect to the scaled design entries (D_d with one diameter)
-  double cmax = 0.0;
-  for (int k = 0; k < h.npar; ++k) cmax = std::max(cmax, h.cw[k]);
-  h.sf = h.npar == 1 ? std::min(1.0, o.nlp_scaling_max_gradient / h.sc.Dd)
-                     : std::min(1.0, o.nlp_scaling_max_gradient / (cmax * h.sc.Dd));
+  // gradient-based objective scaling at the cold point: f = sum_k c_k theta_k +
+  // a_k theta_k^-4 has the gradient (c_k - 4 a_k theta_k^-5) D_d with respect to
+  // the scaled design entries (c = 1 and a = 0 for problem (10))
+  double gmax = 0.0;
+  {
+    const double th0 = zc[NV], t5 = th0 * th0 * th0 * th0 * th0;
+    for (int p = 0; p < P; ++p)
+      for (int k = 0; k < h.npar; ++k) {
+        const double c = h.npar == 1 ? 1.0 : h.cw[k];
+        const double a = h.has_op ? h.opa_h[(size_t)p * h.npar + k] : 0.0;
+        gmax = std::max(gmax, a == 0.0 ? c : fabs(c - 4.0 * a / t5));
+      }
+  }
+  h.sf = std::min(1.0, o.nlp_scaling_max_gradient / (gmax * h.sc.Dd));
   const double gf = h.sf * h.sc.Dd;  // gradient of f~ = sf * d with respect to xt_d
   Obj ob{};
   ob.npar = h.npar;
+  ob.a = h.has_op ? h.opa : nullptr;
+  ob.sf = h.sf;
+  ob.Dd = h.sc.Dd;
   for (int k = 0; k < h.npar; ++k) {
     ob.c[k] = h.npar == 1 ? 1.0 : h.cw[k];
     ob.g[k] = h.npar == 1 ? gf : gf * h.cw[k];
@@ -1657,7 +1697,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     hipLaunchKernelGGL(k_fill, dim3(gx), dim3(BS), 0, st, h.diagx, 0.0, nx);
     hipLaunchKernelGGL(k_fill, dim3(gst), dim3(BS), 0, st, h.diags, 0.0, nst);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(nkkt, BS)), dim3(BS), 0, st, W.rhs, 0.0, nkkt);
-    hipLaunchKernelGGL(k_ls_rhs, dim3(grid_for(std::max(nx, nst), BS)), dim3(BS), 0, st, W.zL, W.zU, W.vU, ob, nx,
+    hipLaunchKernelGGL(k_ls_rhs, dim3(grid_for(std::max(nx, nst), BS)), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.vU, ob, nx,
                        nxs, nks, nst, W.rhs);
     for (auto& q : pr) {
       q.dw = 1.0;
@@ -1683,7 +1723,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   }
   TRY(read_d(W.xt));
   // ---- per-problem filter bounds from theta(x0) and multiplier counts
-  hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
+  hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, ob, nxs,
                      h.redbuf);
   TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
   long long nbL1 = 0, nbU1 = 0;  // finite bounds per stage
@@ -1729,14 +1769,14 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     hipLaunchKernelGGL(k_lag_grad, dim3(nseg), dim3(GBS), 0, st, h.rec, h.gtab, h.gtab_n, W.y, h.seg, h.sinfo, nst,
                        h.jac_d_index, W.g, W.dpart);
     if (h.npar == 1)
-      hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, ob, nxs, W.g);
+      hipLaunchKernelGGL(k_grad_d, dim3(P), dim3(BS), 0, st, W.dpart, h.pseg, ob, W.xt, nxs, W.g);
     else
       hipLaunchKernelGGL(k_grad_design, dim3(P), dim3(DGS), 0, st, h.rec, W.y, h.pstage, h.sinfo, h.jac_d_index, ob,
-                         nxs, W.g);
+                         W.xt, nxs, W.g);
     hipLaunchKernelGGL(k_opt_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.xt, W.zL, W.zU, W.g, W.y, W.c, W.s, W.vU,
                        b, nxs, h.redbuf);
     // the barrier Hessian diagonals at x_k need no decision of the host: queue them now
-    hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, nx, nxs, nst, h.diagx,
+    hipLaunchKernelGGL(k_sigma, dim3(gm), dim3(BS), 0, st, W.xt, W.zL, W.zU, W.s, W.vU, b, ob, nx, nxs, nst, h.diagx,
                        h.diags);
     TRY(seg_reduce<9>(h, Ops<9>{{1, 1, 1, 1, 2, 1, 0, 0, 0}}, st));
     for (int p = 0; p < P; ++p) {
@@ -1837,7 +1877,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
     hipLaunchKernelGGL(k_direction, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, h.dwv, W.xt, W.zL, W.zU, W.y, W.s,
                        W.vU, h.diags, W.sol, b, C.kappa_d, ob, nxs, nks, W.dx, W.dy, W.dzL, W.dzU, W.ds, W.dvU,
                        h.redbuf);
-    hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, nxs,
+    hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xt, W.s, W.c, b, C.kappa_d, ob, nxs,
                        h.redbuf + 4LL * nseg);
     {
       // per problem: [4] direction values, [3] the current point's theta/phi parts, then
@@ -1850,7 +1890,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
                          W.xtt, W.st);
       HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
       hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d,
-                         nxs, h.redbuf);
+                         ob, nxs, h.redbuf);
       hipLaunchKernelGGL(k_seg_reduce<3>, dim3(P), dim3(RS), 0, st, h.redbuf, h.pseg, Ops<3>{{0, 0, 0}},
                          out + 7LL * P);
       HIP_TRY(hipGetLastError());
@@ -1891,7 +1931,7 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
                            W.st);
         HIP_TRY(launch_eval(h, W.xtt, 1, nullptr, 0, W.ct, st));
         hipLaunchKernelGGL(k_ls_parts, dim3(nseg), dim3(BS), 0, st, h.seg, W.ps, W.xtt, W.st, W.ct, b, C.kappa_d,
-                           nxs, h.redbuf);
+                           ob, nxs, h.redbuf);
         TRY(seg_reduce<3>(h, Ops<3>{{0, 0, 0}}, st));
       }
       const double* tvs = first ? h.redbuf_h + 7 * P : h.redbuf_h;
