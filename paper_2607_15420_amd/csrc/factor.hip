@@ -162,10 +162,13 @@ __device__ __forceinline__ void eliminate_phase(double (&v)[FR], double* __restr
         d = rdl(rk, p0);
         dinv = d == 0.0 ? 0.0 : 1.0 / d;
       }
+      // stored column: the active entries, then the pivot code, d and 1/d (selects,
+      // not branches: the code is uniform and formed before the lane selects)
+      const double code = (double)(p0 + 64 * (d == 0.0 ? 0 : 1));
       double sv = ca ? rk : 0.0;
-      if (lane == FR) sv = (double)(p0 + 64 * (d == 0.0 ? 0 : 1));
-      else if (lane == FR + 1) sv = d;
-      else if (lane > FR + 1) sv = dinv;
+      sv = lane == FR ? code : sv;
+      sv = lane == FR + 1 ? d : sv;
+      sv = lane > FR + 1 ? dinv : sv;
       sb[slot * SLOT + lane] = sv;
       slot += 1;
       if (d == 0.0) {
