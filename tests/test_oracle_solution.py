@@ -53,7 +53,8 @@ def test_c1_min_hydraulic_margin_is_zero(c1, params):
 
 def test_c1_column_closure(c1, params):
     # summing (1) over stages telescopes to in = out for every reaction
-    # invariant a (a^T nu = 0); summing (6) gives enthalpy in = out (Q = 0)
+    # invariant a (a^T nu = 0); the enthalpy closure of (6) is pinned in
+    # test_oracle_rows.py (test_column_enthalpy_closure)
     w, F, res, *_ = c1
     P = M.OracleParams(params)
     nu = P.nu.numpy()
