@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import re
 import json
+import math
 import os
 import sys
 import time
@@ -264,6 +265,69 @@ def batch_leg(params, n_problems: int, sequential: bool):
     return out
 
 
+def extensions_leg(params, steps: int):
+    """The model extensions at the benchmarked size (10 stages x 5000 scenarios,
+    cold start, default options), each timed over `steps` solves after one
+    warm-up: one diameter per column section (p = 4), the expected operating cost
+    at a weight that puts the optimum 30% above the hydraulic bound, a specified
+    pressure drop of 2000 Pa per stage, and scenarios drawn as convex
+    combinations of seven base cases (C6)."""
+    import copy
+    import torch
+    from absorber_inputs import CONFIGS
+    from paper_2607_15420_amd import Absorber
+
+    dev = "cuda:0"
+    c3 = CONFIGS["C3"]
+    F3 = c3.feeds(params)
+    N = c3.n_stages
+
+    def run(make, label):
+        h = make()
+        x = torch.empty(h.nx, dtype=torch.float64, device=dev)
+        opts = Absorber.default_options()
+        h.ipm_solve(opts, x_out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [h.ipm_solve(opts, x_out=x) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        design = x[h.nx - h.npar:].cpu().tolist()
+        h.close()
+        r = rs[-1]
+        print(f"bench: extension {label}: {1000 * dt:.1f} ms", file=sys.stderr, flush=True)
+        return {"s": dt, "converged": all(q.status == 0 and q.E0 <= 1e-8 for q in rs), "iterations": r.iterations,
+                "E0": r.E0, "max_lin_resid": r.max_lin_resid, "design": design}
+
+    out = {"workload": "10 stages x 5000 scenarios (C3 feeds unless stated), cold start"}
+    out["sections_p4"] = run(lambda: Absorber.sections(params, N, F3, 4), "4 sections")
+    # operating cost: the weight at which the blower optimum sits 30% above the
+    # hydraulic bound of the C3 solve (a single diameter)
+    h = Absorber(params, N, F3)
+    x = torch.empty(h.nx, dtype=torch.float64, device=dev)
+    h.ipm_solve(Absorber.default_options(), x_out=x)
+    d_hyd = float(x[-1])
+    h.close()
+    Mg = params["operating_cost"]["molar_mass"]
+    K = params["operating_cost"]["loss_coef"]
+    R = params["R"]
+    p_in = F3[:, 17]
+    Q = F3[:, 0] * R * F3[:, 5] / p_in
+    rho = p_in * (F3[:, 1:5] @ Mg) / (R * F3[:, 5])
+    a1 = 8.0 * K * N / math.pi ** 2 * float((rho * Q ** 3).mean())
+    pop = copy.deepcopy(params)
+    pop["operating_cost"]["weight"] = (1.3 * d_hyd) ** 5 / (4.0 * a1)
+    out["operating_cost"] = run(lambda: Absorber(pop, N, F3), "operating cost")
+    out["operating_cost"]["hydraulic_d"] = d_hyd
+    out["operating_cost"]["blower_optimum"] = (4.0 * a1 * pop["operating_cost"]["weight"]) ** 0.2
+    pdp = copy.deepcopy(params)
+    pdp["dp_stage"] = 2000.0
+    out["pressure_drop_2000Pa"] = run(lambda: Absorber(pdp, N, c3.feeds(pdp)), "pressure drop")
+    c6 = CONFIGS["C6"]
+    out["convex_scenarios_C6"] = run(lambda: Absorber(params, c6.n_stages, c6.feeds(params)), "C6")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +338,7 @@ def main():
     ap.add_argument("--cpu-scen", type=int, default=16)
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
+    ap.add_argument("--no-ext", action="store_true", help="skip the model-extensions leg")
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--no-sequential", action="store_true", help="batched leg without the sequential comparison")
     ap.add_argument("--warm-epochs", type=int, default=300)
@@ -381,6 +446,8 @@ def main():
         print("bench: warm-start leg done", file=sys.stderr, flush=True)
     if not args.no_batch:
         out["batch"] = batch_leg(params, args.batch_problems, not args.no_sequential)
+    if not args.no_ext:
+        out["extensions"] = extensions_leg(params, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, feeds, N, r.iterations, args.cpu_scen)
     print(json.dumps(out), flush=True)

@@ -494,7 +494,7 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
   ALLOC(h.scal, h.P);
   if (npar > 1) {
     ALLOC(h.solbk, nst * NK * (npar - 1));
-    ALLOC(h.brhs, h.nkkt);
+    ALLOC(h.brhs, nst * NK * (npar - 1));
     ALLOC(h.pdots, (size_t)h.S * PDOT);
     ALLOC(h.dsc, (size_t)h.P * DSC);
   }

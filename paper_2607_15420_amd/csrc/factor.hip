@@ -542,35 +542,48 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
   }
 }
 
-// Forward and backward substitution with stored pivot columns: solr <- K_w^{-1} rhs.
-template <int WPE>
+// Forward and backward substitution with stored pivot columns for R right-hand
+// sides at once (each stage's pivot columns are read once for all of them):
+// solr[j] <- K_w^{-1} rhs[j], rhs[j] = rhs + j * stride, solr[j] likewise.
+// With one right-hand side the border dot b . x goes to part (Schur on d).
+template <int WPE, int R>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
                                                 const double* __restrict__ rhs, const int* __restrict__ chain0,
                                                 const int* __restrict__ chain_p, const int* __restrict__ pact,
-                                                const int* __restrict__ chmask, int W, int jd,
+                                                const int* __restrict__ chmask, int W, int jd, long long stride,
                                                 double* __restrict__ solr, double* __restrict__ part) {
-  __shared__ double sh[WAVE];
+  __shared__ double sh[R][WAVE];
   const int w = blockIdx.x;
   if (w >= W) return;
   if ((pact && !pact[chain_p[w]]) || (chmask && !chmask[w])) {  // not worked on: zero solution
-    if (threadIdx.x == 0) part[(long long)w * 4 + 1] = 0.0;
-    for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE)
-      solr[i] = 0.0;
+    if (R == 1 && threadIdx.x == 0) part[(long long)w * 4 + 1] = 0.0;
+    for (int j = 0; j < R; ++j)
+      for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE)
+        solr[j * stride + i] = 0.0;
     return;
   }
   const long long t0 = chain0[w];
   const int N = chain0[w + 1] - (int)t0;
   const int lane = lane_id();
-  double ctb = 0.0;  // contribution carried by coupling lane 43+a to stage n+1's index R[a]
+  double ctb[R];  // contribution carried by coupling lane 43+a to stage n+1's index R[a]
+#pragma unroll
+  for (int j = 0; j < R; ++j) ctb[j] = 0.0;
   for (int n = 0; n < N; ++n) {
     const long long t = t0 + n;
     const double* sb = slots + t * NK * SLOT;
-    sh[lane] = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) sh[j][lane] = 0.0;
     __syncthreads();
-    if (lane >= NK && lane < NK + NC) sh[coupling_index(lane - NK)] = ctb;
+    if (lane >= NK && lane < NK + NC)
+#pragma unroll
+      for (int j = 0; j < R; ++j) sh[j][coupling_index(lane - NK)] = ctb[j];
     __syncthreads();
-    double r = (lane < NK ? rhs[t * NK + lane] + sh[lane] : 0.0);
-    double ys = 0.0;  // lane s keeps the forward value of slot s
+    double r[R], ys[R];  // lane s keeps the forward value of slot s
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      r[j] = lane < NK ? rhs[j * stride + t * NK + lane] + sh[j][lane] : 0.0;
+      ys[j] = 0.0;
+    }
     // the stage's 43 pivot columns, all loads in flight at once (lane = row)
     double col[NK];
 #pragma unroll
@@ -590,44 +603,61 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
         const double cn = col[q + 1 < NK ? q + 1 : q];
         const int pq = ((int)rdl(cn, FR)) & 63;
         const double e11 = rdl(c, FR + 1), e12 = rdl(c, FR + 2), e22 = rdl(cn, FR + 1);
-        const double yk = rdl(r, p), yq = rdl(r, pq);
-        if (lane == q) ys = yk;
-        if (lane == q + 1) ys = yq;
         const double idet = 1.0 / (e11 * e22 - e12 * e12);
-        const double t1 = (e22 * yk - e12 * yq) * idet, t2 = (e11 * yq - e12 * yk) * idet;
         const double c1r = lane < FR_R ? cn : 0.0;
-        r = fma(-cr, t1, fma(-c1r, t2, r));
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const double yk = rdl(r[j], p), yq = rdl(r[j], pq);
+          if (lane == q) ys[j] = yk;
+          if (lane == q + 1) ys[j] = yq;
+          const double t1 = (e22 * yk - e12 * yq) * idet, t2 = (e11 * yq - e12 * yk) * idet;
+          r[j] = fma(-cr, t1, fma(-c1r, t2, r[j]));
+        }
         skip = true;
         continue;
       }
-      const double yp = rdl(r, p);
-      if (lane == q) ys = yp;
-      if (type == 1) r = fma(-cr, yp * rdl(c, FR + 2), r);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const double yp = rdl(r[j], p);
+        if (lane == q) ys[j] = yp;
+        if (type == 1) r[j] = fma(-cr, yp * rdl(c, FR + 2), r[j]);
+      }
     }
-    if (lane < NK) solr[t * NK + lane] = ys;  // forward values in slot order
-    ctb = (lane >= NK && lane < NK + NC) ? r : 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (lane < NK) solr[j * stride + t * NK + lane] = ys[j];  // forward values in slot order
+      ctb[j] = (lane >= NK && lane < NK + NC) ? r[j] : 0.0;
+    }
     __syncthreads();
   }
   // backward sweep
-  sh[lane] = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) sh[j][lane] = 0.0;
   __syncthreads();
   double sig = 0.0;
   for (int n = N - 1; n >= 0; --n) {
     const long long t = t0 + n;
     const double* sb = slots + t * NK * SLOT;
-    const double y[1] = {lane < NK ? solr[t * NK + lane] : 0.0};
-    const double* const xc[1] = {sh};
-    double x[1];
-    backward_rows<1>(sb, y, xc, x);
-    __syncthreads();
-    if (lane < NK) {
-      solr[t * NK + lane] = x[0];
-      sh[lane] = x[0];
+    double y[R];
+    const double* xc[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      y[j] = lane < NK ? solr[j * stride + t * NK + lane] : 0.0;
+      xc[j] = sh[j];
     }
+    double x[R];
+    backward_rows<R>(sb, y, xc, x);
     __syncthreads();
-    if (lane == NK - 1) sig += rec[t * REC + jd] * sh[NK - 1];
+    if (lane < NK)
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        solr[j * stride + t * NK + lane] = x[j];
+        sh[j][lane] = x[j];
+      }
+    __syncthreads();
+    if (R == 1 && lane == NK - 1) sig += rec[t * REC + jd] * sh[0][NK - 1];
   }
-  if (lane == NK - 1) part[(long long)w * 4 + 1] = sig;
+  if (R == 1 && lane == NK - 1) part[(long long)w * 4 + 1] = sig;
 }
 
 // Schur complement on d.  Fixed-order reduction of the per-scenario partials:
@@ -802,47 +832,61 @@ __global__ void k_design_dots(int mode, const double* __restrict__ rec, const in
 
 // eigenvalues of a symmetric n x n matrix (n <= MAX_NPAR) by cyclic Jacobi
 // rotations (a fixed number of sweeps: deterministic)
+// (loops over the static bound MAX_NPAR with guards, so that every index is a
+// compile-time constant and the matrix stays in registers)
 __device__ void sym_eigenvalues(double (&A)[MAX_NPAR][MAX_NPAR], int n, double (&ev)[MAX_NPAR]) {
   for (int sweep = 0; sweep < 30; ++sweep)
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
+#pragma unroll
+    for (int p = 0; p < MAX_NPAR - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < MAX_NPAR; ++q) {
+        if (q >= n) continue;
         const double apq = A[p][q];
         if (apq == 0.0) continue;
         const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
         const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
         const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < n; ++k) {  // rotate columns p, q
+#pragma unroll
+        for (int k = 0; k < MAX_NPAR; ++k) {  // rotate columns p, q (entries past n stay 0)
           const double akp = A[k][p], akq = A[k][q];
           A[k][p] = c * akp - s * akq;
           A[k][q] = s * akp + c * akq;
         }
-        for (int k = 0; k < n; ++k) {  // rotate rows p, q
+#pragma unroll
+        for (int k = 0; k < MAX_NPAR; ++k) {  // rotate rows p, q
           const double apk = A[p][k], aqk = A[q][k];
           A[p][k] = c * apk - s * aqk;
           A[q][k] = s * apk + c * aqk;
         }
       }
-  for (int k = 0; k < n; ++k) ev[k] = A[k][k];
+#pragma unroll
+  for (int k = 0; k < MAX_NPAR; ++k) ev[k] = A[k][k];
 }
 
 // per problem (one wave each): fixed-order sums of the chains' partials, then
 // mode 0/1: S, its inertia (plus the chains' counts) and the K_dd diagonal;
 // mode 1/2: delta theta = S^{-1} (r_theta - sum b_k . u) by Gaussian
 // elimination with partial pivoting
-__global__ __launch_bounds__(64) void k_design_schur(int mode, const double* __restrict__ pdots,
-                                                     const int* __restrict__ inert, const int* __restrict__ pchain,
-                                                     const double* __restrict__ diagx, long long nxs,
-                                                     const double* __restrict__ dwv, const double* __restrict__ rhs,
-                                                     long long nks, int npar, const int* __restrict__ pmask,
-                                                     DevScalars* __restrict__ scal, double* __restrict__ dsc) {
+constexpr int DSCH_BS = 256;
+__global__ __launch_bounds__(DSCH_BS) void k_design_schur(int mode, const double* __restrict__ pdots,
+                                                          const int* __restrict__ inert,
+                                                          const int* __restrict__ pchain,
+                                                          const double* __restrict__ diagx, long long nxs,
+                                                          const double* __restrict__ dwv,
+                                                          const double* __restrict__ rhs, long long nks, int npar,
+                                                          const int* __restrict__ pmask,
+                                                          DevScalars* __restrict__ scal, double* __restrict__ dsc) {
+  constexpr int NQ = PDOT + 3;
+  __shared__ double sm[NQ][DSCH_BS / 64];
   const int pb = blockIdx.x;
   if (pmask && !pmask[pb]) return;
-  const int lane = threadIdx.x;
-  constexpr int NQ = PDOT + 3;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double a[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) a[q] = 0.0;
-  for (int w = pchain[pb] + lane; w < pchain[pb + 1]; w += 64) {
+  // thread i takes chains i, i + DSCH_BS, ...; then a fixed shuffle tree in each
+  // wave and across the waves
+  for (int w = pchain[pb] + (int)threadIdx.x; w < pchain[pb + 1]; w += DSCH_BS) {
     const double* o = pdots + (long long)w * PDOT;
     if (mode != 2) {
 #pragma unroll
@@ -859,6 +903,17 @@ __global__ __launch_bounds__(64) void k_design_schur(int mode, const double* __r
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) a[q] += __shfl_down(a[q], off, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sm[q][wv] = a[q];
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    a[q] = lane < DSCH_BS / 64 ? sm[q][lane] : 0.0;
+#pragma unroll
+    for (int off = DSCH_BS / 128; off > 0; off >>= 1) a[q] += __shfl_down(a[q], off, 64);
+  }
   if (lane != 0) return;
   double* D = dsc + (long long)pb * DSC;
   double* Sst = D;                                   // S [MAX_NPAR][MAX_NPAR]
@@ -867,16 +922,22 @@ __global__ __launch_bounds__(64) void k_design_schur(int mode, const double* __r
   double* kdg = wst + MAX_NPAR;                      // K_dd diagonal
   const long long ib = (long long)pb * npar;
   if (mode != 2) {
-    const double* wdd = a + MAX_NPAR * MAX_NPAR + MAX_NPAR;
+    // (static loops with guards: the partial sums stay in registers)
     double A[MAX_NPAR][MAX_NPAR] = {};
     double amax = 1.0;
-    for (int k = 0; k < npar; ++k) {
-      wst[k] = wdd[k];
-      kdg[k] = wdd[k] + diagx[nxs + ib + k] + dwv[pb];
-      amax = fmax(amax, fabs(kdg[k]));
-      for (int l = 0; l < npar; ++l) {
+#pragma unroll
+    for (int k = 0; k < MAX_NPAR; ++k) {
+      if (k >= npar) continue;
+      const double wk = a[MAX_NPAR * MAX_NPAR + MAX_NPAR + k];
+      const double kd = wk + diagx[nxs + ib + k] + dwv[pb];
+      wst[k] = wk;
+      kdg[k] = kd;
+      amax = fmax(amax, fabs(kd));
+#pragma unroll
+      for (int l = 0; l < MAX_NPAR; ++l) {
+        if (l >= npar) continue;
         const double sym = 0.5 * (a[k * MAX_NPAR + l] + a[l * MAX_NPAR + k]);
-        A[k][l] = (k == l ? kdg[k] : 0.0) - sym;
+        A[k][l] = (k == l ? kd : 0.0) - sym;
         Sst[k * MAX_NPAR + l] = A[k][l];
       }
     }
@@ -884,7 +945,9 @@ __global__ __launch_bounds__(64) void k_design_schur(int mode, const double* __r
     sym_eigenvalues(A, npar, ev);
     long long np = (long long)a[PDOT], nn = (long long)a[PDOT + 1], nz = (long long)a[PDOT + 2];
     const double tiny = 1e-20 * amax;
-    for (int k = 0; k < npar; ++k) {
+#pragma unroll
+    for (int k = 0; k < MAX_NPAR; ++k) {
+      if (k >= npar) continue;
       if (ev[k] > tiny) ++np;
       else if (ev[k] < -tiny) ++nn;
       else ++nz;
@@ -897,36 +960,58 @@ __global__ __launch_bounds__(64) void k_design_schur(int mode, const double* __r
     o.sd = ev[0];
   }
   if (mode != 0) {
-    double A[MAX_NPAR][MAX_NPAR], b[MAX_NPAR];
-    for (int k = 0; k < npar; ++k) {
-      b[k] = rhs[nks + ib + k] - a[MAX_NPAR * MAX_NPAR + k];
-      for (int l = 0; l < npar; ++l) A[k][l] = Sst[k * MAX_NPAR + l];
+    // Gaussian elimination with partial pivoting on S padded to MAX_NPAR x
+    // MAX_NPAR with an identity block (block diagonal: the padding neither wins a
+    // pivot search nor changes the solution); static indices keep it in registers
+    double A[MAX_NPAR][MAX_NPAR], b[MAX_NPAR], xs[MAX_NPAR];
+#pragma unroll
+    for (int k = 0; k < MAX_NPAR; ++k) {
+      b[k] = k < npar ? rhs[nks + ib + k] - a[MAX_NPAR * MAX_NPAR + k] : 0.0;
+#pragma unroll
+      for (int l = 0; l < MAX_NPAR; ++l)
+        A[k][l] = (k < npar && l < npar) ? Sst[k * MAX_NPAR + l] : (k == l ? 1.0 : 0.0);
     }
-    for (int c = 0; c < npar; ++c) {  // elimination with partial pivoting
+#pragma unroll
+    for (int c = 0; c < MAX_NPAR; ++c) {
       int piv = c;
-      for (int r = c + 1; r < npar; ++r)
-        if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-      if (piv != c) {
-        for (int l = 0; l < npar; ++l) {
-          const double tmp = A[c][l];
-          A[c][l] = A[piv][l];
-          A[piv][l] = tmp;
+      double best = fabs(A[c][c]);
+#pragma unroll
+      for (int r = c + 1; r < MAX_NPAR; ++r)
+        if (fabs(A[r][c]) > best) {
+          best = fabs(A[r][c]);
+          piv = r;
         }
-        const double tb = b[c];
-        b[c] = b[piv];
-        b[piv] = tb;
-      }
-      for (int r = c + 1; r < npar; ++r) {
+#pragma unroll
+      for (int r = c + 1; r < MAX_NPAR; ++r)
+        if (r == piv) {
+#pragma unroll
+          for (int l = 0; l < MAX_NPAR; ++l) {
+            const double tmp = A[c][l];
+            A[c][l] = A[r][l];
+            A[r][l] = tmp;
+          }
+          const double tb = b[c];
+          b[c] = b[r];
+          b[r] = tb;
+        }
+#pragma unroll
+      for (int r = c + 1; r < MAX_NPAR; ++r) {
         const double f = A[r][c] / A[c][c];
-        for (int l = c; l < npar; ++l) A[r][l] -= f * A[c][l];
+#pragma unroll
+        for (int l = c; l < MAX_NPAR; ++l) A[r][l] -= f * A[c][l];
         b[r] -= f * b[c];
       }
     }
-    for (int c = npar - 1; c >= 0; --c) {
+#pragma unroll
+    for (int c = MAX_NPAR - 1; c >= 0; --c) {
       double v = b[c];
-      for (int l = c + 1; l < npar; ++l) v -= A[c][l] * dth[l];
-      dth[c] = v / A[c][c];
+#pragma unroll
+      for (int l = c + 1; l < MAX_NPAR; ++l) v -= A[c][l] * xs[l];
+      xs[c] = v / A[c][c];
     }
+#pragma unroll
+    for (int k = 0; k < MAX_NPAR; ++k)
+      if (k < npar) dth[k] = xs[k];
   }
 }
 
@@ -981,17 +1066,23 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
   return hipGetLastError();
 }
 
-hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain, double* out) {
+hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain, double* out, int nrhs,
+                        long long stride) {
   const int nw = nchain < 0 || nchain > h.S ? h.S : nchain;
   double* const xo = out ? out : h.solr;
+  if (nrhs < 1 || nrhs > MAX_NPAR - 1 || (nrhs > 1 && !out)) return hipErrorInvalidValue;
   prof_begin(h, 1, st);
   const int* pa = h.pact_on ? h.pact : nullptr;
-#define ABS_SOLVE(W)                                                                                           \
-  hipLaunchKernelGGL((k_solve<W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, \
-                     h.chmask, nw, h.jac_d_index, xo, h.part)
-  if (h.tune.solve_wpe == 2) ABS_SOLVE(2);
-  else if (h.tune.solve_wpe == 4) ABS_SOLVE(4);
-  else ABS_SOLVE(3);
+#define ABS_SOLVE(W, RR)                                                                                          \
+  hipLaunchKernelGGL((k_solve<W, RR>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, \
+                     h.chmask, nw, h.jac_d_index, stride, xo, h.part)
+  // several right-hand sides need about 190-210 VGPRs: 2 waves per SIMD (a
+  // higher target would spill)
+  if (nrhs == 2) ABS_SOLVE(2, 2);
+  else if (nrhs == 3) ABS_SOLVE(2, 3);
+  else if (h.tune.solve_wpe == 2) ABS_SOLVE(2, 1);
+  else if (h.tune.solve_wpe == 4) ABS_SOLVE(4, 1);
+  else ABS_SOLVE(3, 1);
 #undef ABS_SOLVE
   prof_end(h, 1, st);
   ++h.n_solve;
@@ -1001,16 +1092,16 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
 static hipError_t launch_design_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol,
                                       hipStream_t st, const int* pmask) {
   const long long nks = h.nst * NK;
-  if (mode != 2)  // the other sections' border columns with the stored factors
-    for (int k = 1; k < h.npar; ++k) {
-      hipLaunchKernelGGL(k_border_rhs, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, h.rec, h.sinfo, nks, h.nkkt,
-                         h.jac_d_index, h.npar, k, h.brhs);
-      const hipError_t e = launch_solve(h, h.brhs, st, -1, h.solbk + (long long)(k - 1) * nks);
-      if (e != hipSuccess) return e;
-    }
+  if (mode != 2) {  // the other sections' border columns with the stored factors, in one pass
+    for (int k = 1; k < h.npar; ++k)
+      hipLaunchKernelGGL(k_border_rhs, dim3(grid_for(nks, 256)), dim3(256), 0, st, h.rec, h.sinfo, nks, nks,
+                         h.jac_d_index, h.npar, k, h.brhs + (long long)(k - 1) * nks);
+    const hipError_t e = launch_solve(h, h.brhs, st, -1, h.solbk, h.npar - 1, nks);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_design_dots, dim3(grid_for(h.S, 64)), dim3(64), 0, st, mode, h.rec, h.chain0, h.chain_p, h.S,
                      h.jac_d_index, h.npar, nks, h.solr, h.solb, h.solbk, pmask, h.pdots);
-  hipLaunchKernelGGL(k_design_schur, dim3(h.P), dim3(64), 0, st, mode, h.pdots, h.inert, h.pchain, diagx,
+  hipLaunchKernelGGL(k_design_schur, dim3(h.P), dim3(DSCH_BS), 0, st, mode, h.pdots, h.inert, h.pchain, diagx,
                      h.nst * NV, h.dwv, rhs, nks, h.npar, pmask, h.scal, h.dsc);
   if (mode != 0 && sol)
     hipLaunchKernelGGL(k_design_combine, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, h.solr, h.solb, h.solbk,

@@ -175,7 +175,7 @@ struct Handle {
   double* solr = nullptr;                    // [S][N][NK] K_w^{-1} r
   double* solb = nullptr;                    // [S][N][NK] K_w^{-1} b (for npar > 1: the border of section 0)
   double* solbk = nullptr;                   // npar > 1: [npar - 1][S][N][NK] K_w^{-1} b_k of sections 1..
-  double* brhs = nullptr;                    // npar > 1: [nkkt] border of one section as a right-hand side
+  double* brhs = nullptr;                    // npar > 1: [npar - 1][43 nst] borders of sections 1.. as right-hand sides
   double* pdots = nullptr;                   // npar > 1: [chains][PDOT] per-chain partial sums
   double* dsc = nullptr;                     // npar > 1: [P][DSC] Schur complement data per problem
   int* inert = nullptr;                      // [chains][4]
@@ -287,7 +287,10 @@ hipError_t launch_hess_coo(Handle& h, const double* x, const double* lam, double
 hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, const double* rhs, bool mask,
                          hipStream_t st, int nchain = -1);
 // forward/backward with the stored factors: out (default h.solr) <- K_w^{-1} rhs (nchain as above)
-hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain = -1, double* out = nullptr);
+// nrhs right-hand sides (1 to MAX_NPAR - 1) rhs + j * stride into out + j * stride
+// (out required for nrhs > 1; the border dot of part only for nrhs = 1)
+hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain = -1, double* out = nullptr,
+                        int nrhs = 1, long long stride = 0);
 // Schur complement on each problem's d.  diagx: Sigma_x (its d entries are
 // Sigma_d); rhs: the right-hand side (its d entries are r_d; may be null in
 // mode 0).  mode 0: after launch_factor without a right-hand side (S_d,

@@ -272,16 +272,19 @@ __global__ void k_grad_d(const double* __restrict__ dpart, const int* __restrict
   if (threadIdx.x == 0) g[nxs + p] = gf + sm[0];
 }
 
-// the design entries of J^T y for npar > 1 (one block per problem): g_k =
-// sf D_d c_k + the hydraulic rows of section k, summed in a fixed order
-constexpr int DGS = 256;
+// the design entries of J^T y for npar > 1 (one 1024-thread block per problem):
+// g_k = the objective's gradient + the hydraulic rows of section k, summed in a
+// fixed order (thread i takes stages i, i + DGS, ...; a shuffle tree in each wave
+// and across the waves)
+constexpr int DGS = 1024;
 __global__ __launch_bounds__(DGS) void k_grad_design(const double* __restrict__ rec, const double* __restrict__ y,
                                                      const long long* __restrict__ pstage,
                                                      const StageInfo* __restrict__ sinfo, int jd, Obj ob,
                                                      const double* __restrict__ x, long long nxs,
                                                      double* __restrict__ g) {
-  __shared__ double sm[MAX_NPAR][DGS];
+  __shared__ double sm[MAX_NPAR][DGS / 64];
   const int pb = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double a[MAX_NPAR] = {0, 0, 0, 0};
   for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += DGS) {
     const StageInfo si = sinfo[t];
@@ -291,18 +294,26 @@ __global__ __launch_bounds__(DGS) void k_grad_design(const double* __restrict__ 
     for (int q = 0; q < MAX_NPAR; ++q) a[q] += q == k ? v : 0.0;
   }
 #pragma unroll
-  for (int q = 0; q < MAX_NPAR; ++q) sm[q][threadIdx.x] = a[q];
-  __syncthreads();
-  for (int h = DGS / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-      for (int q = 0; q < MAX_NPAR; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + h];
-    __syncthreads();
+    for (int q = 0; q < MAX_NPAR; ++q) a[q] += __shfl_down(a[q], off, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < MAX_NPAR; ++q) sm[q][wv] = a[q];
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int q = 0; q < MAX_NPAR; ++q) {
+    a[q] = lane < DGS / 64 ? sm[q][lane] : 0.0;
+#pragma unroll
+    for (int off = DGS / 128; off > 0; off >>= 1) a[q] += __shfl_down(a[q], off, 64);
   }
-  if ((int)threadIdx.x < ob.npar) {
-    const long long i = nxs + (long long)pb * ob.npar + threadIdx.x;
-    g[i] = obj_g(ob, i, nxs, x[i]) + sm[threadIdx.x][0];
-  }
+#pragma unroll
+  for (int q = 0; q < MAX_NPAR; ++q)
+    if (lane == 0 && q < ob.npar) {
+      const long long i = nxs + (long long)pb * ob.npar + q;
+      g[i] = obj_g(ob, i, nxs, x[i]) + a[q];
+    }
 }
 
 // ---- optimality-error partials per segment

@@ -387,16 +387,18 @@ __global__ void k_residual_d(const double* __restrict__ part, const int* __restr
   }
 }
 
-// Design rows of each problem's residual for npar > 1 (one block per problem,
-// fixed-order sums per section over its stages): res_k = rhs_k - sum over the
-// section's stages of b u_hyd - K_dd,k u_k (K_dd diagonal from the Schur data);
-// omd[3 p .. 3 p + 2] = the largest backward error, |res| and |rhs| of its rows.
-constexpr int DBS = 256;
+// Design rows of each problem's residual for npar > 1 (one 1024-thread block per
+// problem, fixed-order sums per section over its stages: thread i takes stages
+// i, i + DBS, ..., then a shuffle tree in each wave and across the waves):
+// res_k = rhs_k - sum over the section's stages of b u_hyd - K_dd,k u_k (K_dd
+// diagonal from the Schur data); omd[3 p .. 3 p + 2] = the largest backward
+// error, |res| and |rhs| of its rows.
+constexpr int DBS = 1024;
 __global__ __launch_bounds__(DBS) void k_residual_design(
     const double* __restrict__ rec, const long long* __restrict__ pstage, const StageInfo* __restrict__ sinfo,
     const double* __restrict__ dsc, const double* __restrict__ sol, const double* __restrict__ rhs, long long nks,
     int jd, int npar, const int* __restrict__ pact, double* __restrict__ res, double* __restrict__ omd) {
-  __shared__ double sm[2 * MAX_NPAR][DBS];
+  __shared__ double sm[2 * MAX_NPAR][DBS / 64];
   const int pb = blockIdx.x;
   const long long d0 = nks + (long long)pb * npar;
   if (pact && !pact[pb]) {
@@ -404,7 +406,8 @@ __global__ __launch_bounds__(DBS) void k_residual_design(
     if (threadIdx.x == 0) omd[3 * pb] = omd[3 * pb + 1] = omd[3 * pb + 2] = 0.0;
     return;
   }
-  double a[MAX_NPAR] = {0, 0, 0, 0}, b[MAX_NPAR] = {0, 0, 0, 0};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double a[2 * MAX_NPAR] = {0, 0, 0, 0, 0, 0, 0, 0};  // sums of b u and of |b u| per section
   for (long long t = pstage[pb] + threadIdx.x; t < pstage[pb + 1]; t += DBS) {
     const StageInfo si = sinfo[t];
     const int k = section_of(si.n, si.N, npar);
@@ -412,29 +415,34 @@ __global__ __launch_bounds__(DBS) void k_residual_design(
 #pragma unroll
     for (int q = 0; q < MAX_NPAR; ++q) {
       a[q] += q == k ? pr : 0.0;
-      b[q] += q == k ? fabs(pr) : 0.0;
+      a[MAX_NPAR + q] += q == k ? fabs(pr) : 0.0;
     }
   }
 #pragma unroll
-  for (int q = 0; q < MAX_NPAR; ++q) {
-    sm[q][threadIdx.x] = a[q];
-    sm[MAX_NPAR + q][threadIdx.x] = b[q];
-  }
-  __syncthreads();
-  for (int h = DBS / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-      for (int q = 0; q < 2 * MAX_NPAR; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + h];
-    __syncthreads();
+    for (int q = 0; q < 2 * MAX_NPAR; ++q) a[q] += __shfl_down(a[q], off, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 2 * MAX_NPAR; ++q) sm[q][wv] = a[q];
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int q = 0; q < 2 * MAX_NPAR; ++q) {
+    a[q] = lane < DBS / 64 ? sm[q][lane] : 0.0;
+#pragma unroll
+    for (int off = DBS / 128; off > 0; off >>= 1) a[q] += __shfl_down(a[q], off, 64);
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     const double* D = dsc + (long long)pb * DSC;
     const double* kdiag = D + MAX_NPAR * MAX_NPAR + 2 * MAX_NPAR;
     double om = 0.0, rm = 0.0, bm = 0.0;
-    for (int k = 0; k < npar; ++k) {
+#pragma unroll
+    for (int k = 0; k < MAX_NPAR; ++k) {
+      if (k >= npar) break;
       const long long i = d0 + k;
-      const double ku = sm[k][0] + kdiag[k] * sol[i];
-      const double ka = sm[MAX_NPAR + k][0] + fabs(kdiag[k] * sol[i]);
+      const double ku = a[k] + kdiag[k] * sol[i];
+      const double ka = a[MAX_NPAR + k] + fabs(kdiag[k] * sol[i]);
       const double rr = rhs[i] - ku;
       res[i] = rr;
       const double den = ka + fabs(rhs[i]);

@@ -210,3 +210,41 @@ def test_ragged_sections_many_scenarios(params):
         assert np.abs(xs.cpu().numpy()[-p:] - th).max() / th.max() <= 1e-9
     finally:
         h.close()
+
+
+def test_c3_four_sections_full_size(params):
+    """The benchmarked 10 x 5000 workload with four section diameters: each
+    theta_k equals the largest hydraulic diameter of its section over all 5000
+    scenarios' states, and the scenarios that set each theta_k, plus sampled
+    ones, simulated independently by the oracle match the device's states."""
+    from paper_2607_15420_amd import Absorber
+    w = CONFIGS["C3"]
+    F = w.feeds(params)
+    S, N, p = F.shape[0], w.n_stages, 4
+    h = Absorber.sections(params, N, F, p)
+    try:
+        r, x, _ = _solve(h)
+    finally:
+        h.close()
+    assert r.status == 0, r.as_dict()
+    assert r.E0 <= 1e-8 and r.max_lin_resid <= 1e-10
+    P = M.OracleParams(params)
+    Z = x[:-p].reshape(S, N, M.NV)
+    theta = x[-p:]
+    sec = M.sections(N, p)
+    dh = np.sqrt(4.0 * Z[:, :, M.IV] * P.R * Z[:, :, M.IT] / (math.pi * P.u_max * F[:, 17][:, None]))
+    for k in range(p):
+        assert abs(theta[k] - dh[:, sec == k].max()) / theta[k] <= 1e-6
+    ip = params["initial_point"]
+    z0 = np.r_[ip["x"], ip["y"], ip["L"], ip["V"], ip["T"], [0.0] * 5]
+    setters = {int(dh[:, sec == k].max(axis=1).argmax()) for k in range(p)}
+    sample = setters | set(np.random.default_rng(9).choice(S, 6, replace=False).tolist())
+    for s in sorted(sample):
+        Zs, ok, _, _ = simulate.simulate_scenario(np.tile(z0, (N, 1)), F[s], P)
+        assert ok
+        assert np.abs(Zs - Z[s]).max() / np.abs(Zs).max() <= 1e-8
+        if s in setters:
+            dso = np.sqrt(4.0 * Zs[:, M.IV] * P.R * Zs[:, M.IT] / (math.pi * P.u_max * F[s, 17]))
+            for k in range(p):
+                if int(dh[:, sec == k].max(axis=1).argmax()) == s:
+                    assert abs(theta[k] - dso[sec == k].max()) / theta[k] <= 1e-6
