@@ -237,9 +237,20 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
   std::vector<double> nr((size_t)W);
   for (int w = 0; w < W; ++w) nr[(size_t)w] = st_h[2 * w];
   std::vector<char> stalled((size_t)W, 0);  // backtracking exhausted without decrease
-  auto wanted = [&](int w) { return (!pmask || pmask[wp[(size_t)w]]) && !stalled[(size_t)w]; };
+  // Slow chains: in the first two rounds a chain whose residual has not fallen
+  // tenfold over ten steps pauses when its problem already has a converged
+  // chain; the round then ends sooner and the paused chain starts again from
+  // the closest converged neighbour.
+  std::vector<char> slow((size_t)W, 0);
+  std::vector<double> mark((size_t)W);
+  std::vector<char> pconv((size_t)P);
+  auto wanted = [&](int w) {
+    return (!pmask || pmask[wp[(size_t)w]]) && !stalled[(size_t)w] && !slow[(size_t)w];
+  };
   int it = 0, it_total = 0;
-  for (int round = 0; round < 3; ++round) {
+  constexpr int ROUNDS = 3, SLOW_EVERY = 10;
+  for (int round = 0; round < ROUNDS; ++round) {
+    mark = nr;
     for (it = 0; it < max_iter; ++it, ++it_total) {
       bool any = false;
       for (int w = 0; w < W; ++w) any = any || (wanted(w) && !(nr[(size_t)w] <= tol));
@@ -294,6 +305,17 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
       }
       std::swap(xt, xtt);
       HIP_TRY(launch_eval(h, xt, 1, nullptr, 1, c, st));
+      if (round < ROUNDS - 1 && it % SLOW_EVERY == SLOW_EVERY - 1) {
+        std::fill(pconv.begin(), pconv.end(), 0);
+        for (int w = 0; w < W; ++w)
+          if (nr[(size_t)w] <= tol) pconv[(size_t)wp[(size_t)w]] = 1;
+        for (int w = 0; w < W; ++w) {
+          if (wanted(w) && !(nr[(size_t)w] <= tol) && pconv[(size_t)wp[(size_t)w]] &&
+              !(nr[(size_t)w] < 0.1 * mark[(size_t)w]))
+            slow[(size_t)w] = 1;
+          mark[(size_t)w] = nr[(size_t)w];
+        }
+      }
     }
     // chains that did not converge start again from the states of the converged
     // chain of the same problem whose feed is closest (scenarios differ only in
@@ -324,11 +346,13 @@ int simulate(Handle& h, double* x_dev, const unsigned char* pmask, double tol, i
     hipLaunchKernelGGL(k_chain_stats, dim3(nblk(W, 64)), dim3(64), 0, st, c, xt, nullptr, h.chain0, W, stats);
     HIP_TRY(hipMemcpyAsync(st_h, stats, sizeof(double) * 2 * W, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    for (int w = 0; w < W; ++w)
+    for (int w = 0; w < W; ++w) {
       if (src_h[w] >= 0) {
         nr[(size_t)w] = st_h[2 * w];
         stalled[(size_t)w] = 0;
       }
+      slow[(size_t)w] = 0;  // paused chains without a neighbour continue where they were
+    }
   }
   it = it_total;
   hipLaunchKernelGGL(k_scale, dim3(nblk(nx, BS)), dim3(BS), 0, st, xt, h.sc, nx, nxs, 0, x_dev);
