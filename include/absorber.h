@@ -266,7 +266,10 @@ int absorber_batch_solve(absorber_t* h, const absorber_ipm_options* opts, const 
  * ipm_solve, kkt_factor and kkt_solve; the Schur complement on theta is a
  * dense p x p matrix whose inertia comes from its eigenvalues.
  * absorber_ipm_result.d reports the design cost sum_k c_k theta_k.  The
- * COO Jacobian/Hessian calls and the warm start return ABS_ERR_ARG.
+ * warm start takes the predicted states (theta_k = (1 + margin) x the largest
+ * predicted hydraulic diameter of section k) and no multipliers (lambda0 must
+ * be NULL; absorber_warm_solve uses the least-squares estimate).  The COO
+ * Jacobian/Hessian calls return ABS_ERR_ARG.
  * Blocking; allocates the device state on the current device. */
 int absorber_create_sections(const absorber_params* params, int32_t n_stages, int32_t n_scen, int32_t n_sections,
                              const double* feeds_host, absorber_t** out);

@@ -158,14 +158,20 @@ inline size_t al256(size_t n) { return (n + 255) / 256 * 256; }
 // decode Y into x0 (and lambda0) with the per-problem index buffer wmax [P]
 static int warm_point(Handle& h, const float* Y_dev, int32_t n_out, double d_margin, double* x0_dev,
                       double* lambda0_dev, int* wmax, hipStream_t st) {
-  if (h.npar != 1) {
-    set_error("warm start: handles with one diameter only (the network predicts one d per problem)");
+  if (h.npar != 1 && lambda0_dev) {
+    set_error("warm start: a section handle takes the predicted states only (the network's multipliers belong to "
+              "one diameter)");
     return ABS_ERR_ARG;
   }
   const long long nst = h.nst;
   double* dh = h.kden;  // per-stage scratch
   hipLaunchKernelGGL(k_decode, dim3(nblk(nst, WB)), dim3(WB), 0, st, Y_dev, n_out, h.feeds, h.mp, h.sinfo, nst, x0_dev,
                      dh);
+  if (h.npar != 1) {  // each section's diameter: (1 + margin) x its largest predicted hydraulic diameter
+    const int rc = set_hydraulic_diameters(h, x0_dev, d_margin, st);
+    HIP_TRY(hipGetLastError());
+    return rc;
+  }
   hipLaunchKernelGGL(k_decode_d, dim3(h.P), dim3(WB), 0, st, dh, h.pstage, h.sinfo, d_margin, x0_dev + nst * NV, wmax);
   if (lambda0_dev)
     hipLaunchKernelGGL(k_decode_duals, dim3(nblk(nst, WB)), dim3(WB), 0, st, Y_dev, n_out, h.sinfo, nst, wmax,
@@ -305,7 +311,9 @@ int absorber_warm_solve(absorber_t* ah, absorber_mlp* net, const absorber_ipm_op
   absorber_mlp_config cfg;
   int rc = absorber_mlp_get_config(net, &cfg);
   if (rc) return rc;
-  const bool pd = cfg.n_out == (NV + NR) * h.N;  // primal-dual network: predicted multipliers
+  // primal-dual network: predicted multipliers (one diameter only; a section
+  // handle starts from the predicted states with least-squares multipliers)
+  const bool pd = cfg.n_out == (NV + NR) * h.N && h.npar == 1;
   if (!h.warm_X) {
     HIP_TRY(hipMalloc((void**)&h.warm_X, sizeof(float) * 3 * (size_t)h.S));
     HIP_TRY(hipMalloc((void**)&h.warm_Y, sizeof(float) * (size_t)(NV + NR) * h.nst));

@@ -248,3 +248,53 @@ def test_c3_four_sections_full_size(params):
             for k in range(p):
                 if int(dh[:, sec == k].max(axis=1).argmax()) == s:
                     assert abs(theta[k] - dso[sec == k].max()) / theta[k] <= 1e-6
+
+
+def test_warm_start_of_a_section_handle(params):
+    """The network's predicted states start a section handle (each section's
+    diameter from its largest predicted hydraulic diameter, least-squares
+    multipliers); the warm solve reaches the closed form like the cold one.
+    The network is trained on the handle's own single-scenario solutions."""
+    from paper_2607_15420_amd import Absorber, AbsorberError, Mlp
+    from absorber_inputs import feed_table
+    w = CONFIGS["C1"]
+    F = w.feeds(params)
+    N, p = w.n_stages, 2
+    th, _, _ = simulate.closed_form_sections(F, N, p, params)
+    # training data: single-scenario solutions of 64 nearby scenarios, one batch
+    pert = np.random.default_rng(12).uniform(-0.12, 0.12, (64, 3))
+    Ft = feed_table(pert, params)
+    hb = Absorber.batch(params, [(N, Ft[i:i + 1]) for i in range(Ft.shape[0])])
+    xb = torch.empty(hb.nx, dtype=torch.float64, device=DEV)
+    rc, res = hb.batch_solve(x_out=xb)
+    assert all(r.status == 0 for r in res)
+    X = torch.empty((Ft.shape[0], 3), dtype=torch.float32, device=DEV)
+    T = torch.empty((Ft.shape[0], M.NV * N), dtype=torch.float32, device=DEV)
+    hb.warm_features(X)
+    hb.warm_targets(xb, T)
+    hb.close()
+    net = Mlp(n_in=3, n_hidden=64, n_layers=2, n_out=M.NV * N, max_batch=64, seed=5)
+    net.fit_normalization(X, T)
+    net.train(X, T, Mlp.default_train_options(epochs=400, batch=32, lr=3e-3))
+    h = Absorber.sections(params, N, F, p)
+    try:
+        x0 = torch.empty(h.nx, dtype=torch.float64, device=DEV)
+        l0 = torch.empty(h.nc, dtype=torch.float64, device=DEV)
+        with pytest.raises(AbsorberError):
+            h.warm_start_noalloc(net, x0, l0)  # no multipliers for a section handle
+        h.warm_start_noalloc(net, x0)
+        torch.cuda.synchronize()
+        xs = x0.cpu().numpy()
+        Z = xs[:-p].reshape(F.shape[0], N, M.NV)
+        P = M.OracleParams(params)
+        dh = np.sqrt(4.0 * Z[:, :, M.IV] * P.R * Z[:, :, M.IT] / (math.pi * P.u_max * F[:, 17][:, None]))
+        sec = M.sections(N, p)
+        for k in range(p):
+            assert xs[-p + k] == pytest.approx(1.001 * dh[:, sec == k].max(), rel=1e-12)
+        r, used = h.warm_solve(net)
+        assert r.status == 0, r.as_dict()
+        r2, x2, _ = _solve(h)
+        assert r2.status == 0 and np.abs(x2[-p:] - th).max() / th.max() <= 1e-6
+    finally:
+        h.close()
+        net.close()
