@@ -118,6 +118,11 @@ static int build_tables(Handle& h) {
     if (coupling_slot_of(h.jac_up[e].col) < 0) overflow = true;
   for (int e = 0; e < NJD; ++e)
     if (coupling_slot_of(NV + h.jac_down[e].row) < 0) overflow = true;
+  for (int i = 0; i < FR; ++i) {
+    const int cap = 1 + (int)((GATHER2 >> i) & 1ull) + (int)((GATHER3 >> i) & 1ull);
+    for (int j = 0; j < 64; ++j)
+      if (cnt[i * 64 + j] > cap) overflow = true;
+  }
   if (overflow) {
     set_error("internal: frontal gather table does not fit the stage structure");
     return ABS_ERR_ARG;

@@ -48,12 +48,14 @@ __device__ __forceinline__ double rdl(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// register i of this lane for a uniform i < NK
+// register p of this lane for a uniform p in [LO, NK): the cases below LO are
+// left out, so the registers of rows already eliminated are dead in later phases
+template <int LO>
 __device__ __forceinline__ double rowsel(const double (&v)[FR], int p) {
   switch (p) {
 #define ABS_CASE(i) \
   case i:           \
-    return v[i];
+    return (i) >= LO ? v[i] : 0.0;
     ABS_CASE(0) ABS_CASE(1) ABS_CASE(2) ABS_CASE(3) ABS_CASE(4) ABS_CASE(5) ABS_CASE(6) ABS_CASE(7)
     ABS_CASE(8) ABS_CASE(9) ABS_CASE(10) ABS_CASE(11) ABS_CASE(12) ABS_CASE(13) ABS_CASE(14) ABS_CASE(15)
     ABS_CASE(16) ABS_CASE(17) ABS_CASE(18) ABS_CASE(19) ABS_CASE(20) ABS_CASE(21) ABS_CASE(22) ABS_CASE(23)
@@ -129,7 +131,7 @@ __device__ __forceinline__ void eliminate_phase(double (&v)[FR], double* __restr
   while (act && __builtin_ctzll(act) < LIMIT) {
     const int k = __builtin_ctzll(act);
     const bool own_act = lane < NK && ((act >> lane) & 1ull);
-    const double rowk = rowsel(v, k);  // F[k][lane] = F[lane][k]
+    const double rowk = rowsel<8 * C0>(v, k);  // F[k][lane] = F[lane][k]
     const double dkk = rdl(rowk, k);
     // 1/d for the usual 1x1 pivot at k, started before the search so that the
     // two dependency chains overlap
@@ -140,7 +142,7 @@ __device__ __forceinline__ void eliminate_phase(double (&v)[FR], double* __restr
     int ptype = 1;  // 1: 1x1 at k, 2: 1x1 at r, 3: 2x2 (k, r)
     double rowr = 0.0;
     if (!(akk >= alpha * lam) && lam > 0.0) {
-      rowr = rowsel(v, r);
+      rowr = rowsel<8 * C0>(v, r);
       int r2;
       const double sig = wave_max_lane(own_act && lane != r ? fabs(rowr) : 0.0, lane, r2);
       if (akk * sig >= alpha * lam * lam) ptype = 1;
@@ -487,9 +489,16 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       int g[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) g[j] = i0 + j < FR ? gt[(i0 + j) * WAVE + lane] : 0;
+      // only the rows that have them read a second and third source (the
+      // others add exact zeros in the table's layout)
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (i0 + j < FR) v[i0 + j] = L.src[g[j] & 1023] + L.src[(g[j] >> 10) & 1023] + L.src[(g[j] >> 20) & 1023];
+      for (int j = 0; j < 8; ++j) {
+        if (i0 + j >= FR) continue;
+        double a = L.src[g[j] & 1023];
+        if ((GATHER2 >> (i0 + j)) & 1ull) a += L.src[(g[j] >> 10) & 1023];
+        if ((GATHER3 >> (i0 + j)) & 1ull) a += L.src[(g[j] >> 20) & 1023];
+        v[i0 + j] = a;
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();

@@ -38,6 +38,11 @@ constexpr int SRC_DC = SRC_DIAGX + NV;        // -delta_c (1)
 constexpr int SRC_DHYD = SRC_DC + 1;          // -(1/(Sigma_s+delta_w) + delta_c) (1)
 constexpr int SRC_CTB = SRC_DHYD + 1;         // contribution block 16 x 18
 constexpr int NSRC = SRC_CTB + NC * (NC + 2); // 569
+// Frontal rows whose positions take a second (GATHER2) or third (GATHER3)
+// gather source in some column: every other row has at most one.  A property
+// of the stage's KKT structure; the table builder rejects a table that needs more.
+constexpr unsigned long long GATHER2 = 0x8000200f000a1ffull;
+constexpr unsigned long long GATHER3 = 0x81ffull;
 
 // Residual term table (one list of products K_ij x_j per KKT row of a stage):
 // [NK] rows in decreasing term count, [NK + 1] starts of their lists, then per
