@@ -306,6 +306,7 @@ static void free_handle(Handle& h) {
   if (h.ipm_dd_h) (void)hipHostFree(h.ipm_dd_h);
   if (h.pres_h) (void)hipHostFree(h.pres_h);
   if (h.rmask_h) (void)hipHostFree(h.rmask_h);
+  if (h.ctl_ev) (void)hipEventDestroy(h.ctl_ev);
 }
 
 // (re)allocate the scaled row-scale vector as ones
@@ -535,7 +536,8 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
       hipHostMalloc((void**)&h.redbuf_h, sizeof(double) * h.red_cap, 0) != hipSuccess ||
       hipHostMalloc((void**)&h.ctl_h, h.ctl_bytes, 0) != hipSuccess ||
       hipHostMalloc((void**)&h.pres_h, sizeof(double) * 2 * h.P, 0) != hipSuccess ||
-      hipHostMalloc((void**)&h.rmask_h, sizeof(int) * h.P, 0) != hipSuccess) {
+      hipHostMalloc((void**)&h.rmask_h, sizeof(int) * 2 * h.P, 0) != hipSuccess ||
+      hipEventCreateWithFlags(&h.ctl_ev, hipEventDisableTiming) != hipSuccess) {
     set_error("absorber_create: pinned host allocation failed");
     return fail(ABS_ERR_OOM);
   }

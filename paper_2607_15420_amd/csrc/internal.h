@@ -143,6 +143,8 @@ struct Handle {
   // [dwv P doubles][dcv P doubles][fmask P ints][pact P ints][CTL_SLOT bytes per problem]
   char* ctl = nullptr;
   char* ctl_h = nullptr;
+  hipEvent_t ctl_ev = nullptr;  // recorded after each upload of ctl_h; waited on before ctl_h is rewritten
+  bool ctl_ev_rec = false;      // ctl_ev has been recorded
   size_t ctl_bytes = 0;
   double* dwv = nullptr;                     // device [P] delta_w of the stored factorisation
   double* dcv = nullptr;                     // device [P] delta_c
@@ -157,7 +159,8 @@ struct Handle {
   double* pres = nullptr;                    // device [2P]
   double* pres_h = nullptr;                  // pinned [2P]
   int* rmask = nullptr;                      // device [P]
-  int* rmask_h = nullptr;                    // pinned [P]
+  int* rmask_h = nullptr;                    // pinned [2P]: revert mask, then refining mask (an async copy
+                                             // reads its source when it runs, so the two never share memory)
   ModelParams mp{};
   double xL[NV], xU[NV], dL = 0, dU = 0;     // unscaled bounds per local variable
   std::vector<double> feeds_h;

@@ -1500,8 +1500,10 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     }
     if (!any_left || it == 10) break;
     if (per_problem) {
-      for (int p = 0; p < P; ++p) h.rmask_h[p] = refining[(size_t)p] ? 1 : 0;
-      HIP_TRY(hipMemcpyAsync(h.rmask, h.rmask_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+      // second half of the pinned mask: the revert copy above may not have run yet
+      int* const ref_h = h.rmask_h + P;
+      for (int p = 0; p < P; ++p) ref_h[p] = refining[(size_t)p] ? 1 : 0;
+      HIP_TRY(hipMemcpyAsync(h.rmask, ref_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
       HIP_TRY(launch_mask_rows(h, h.rmask, h.kres, st));
       int* const pact = h.pact;
       const bool pact_on = h.pact_on;
@@ -1593,6 +1595,8 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
   // scalars, activity, regularisation and the refactorisation mask of every
   // problem -> device, in one transfer
   auto upload = [&]() -> int {
+    // the previous upload's copy reads ctl_h when it runs: let it finish first
+    if (h.ctl_ev_rec) HIP_TRY(hipEventSynchronize(h.ctl_ev));
     for (int p = 0; p < P; ++p) {
       const Prob& q = pr[(size_t)p];
       PS& d = W.ps_h[p];
@@ -1611,6 +1615,8 @@ int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0_dev, co
       W.fm_h[p] = q.need ? 1 : 0;
     }
     HIP_TRY(hipMemcpyAsync(h.ctl, h.ctl_h, h.ctl_bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(h.ctl_ev, st));
+    h.ctl_ev_rec = true;
     return ABS_OK;
   };
   // the per-stage kernels skip problems that are done (or not asked for)
