@@ -278,7 +278,8 @@ int absorber_create_sections(const absorber_params* params, int32_t n_stages, in
  * square system in its stage states (the equilibrium model's degrees of
  * freedom), solved here by Newton's method for every scenario of every
  * problem at once (mole fractions stepped in their logarithm, log-steps capped
- * at 5, backtracking on each scenario's scaled residual).  x_dev [nx]: start
+ * at 5, backtracking on each scenario's scaled residual; each Newton system is
+ * solved to a relative residual of 1e-6, enough for the step).  x_dev [nx]: start
  * point in, states out; the d entries are set to each problem's hydraulic
  * minimum max sqrt(4 V R T / (pi u_max P)).  Stops when every scenario's
  * scaled MESH residual inf-norm is <= tol or after max_iter steps;

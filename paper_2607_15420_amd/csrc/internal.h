@@ -264,13 +264,15 @@ hipError_t launch_eval_ext(Handle& h, const double* x, int scaled, const Scaling
                            const double* y, int full, double* c_out, hipStream_t st);
 // solve with the stored factors, Schur combine and iterative refinement
 // Solve with the stored factorisation and refine on the bordered system until
-// ||r - K x||_inf <= 1e-10 ||r||_inf (at most 10 corrections, keeping the best).
+// ||r - K x||_inf <= target ||r||_inf (at most 10 corrections, keeping the best).
 // first_residual_read: the residual of the fused solution has been computed and
 // its norms copied to the last four doubles of redbuf_h.
 // rel: the largest of the problems' kept relative residuals; rel_p (host [P],
 // may be null): each problem's own.
+// target: the relative residual at which a problem stops refining (1e-10 for
+// the interior-point solves; the simulation's Newton steps take a looser one).
 int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st,
-                      bool first_residual_read = false, double* rel_p = nullptr);
+                      bool first_residual_read = false, double* rel_p = nullptr, double target = 1e-10);
 // res[P]; active0 (host [P], may be null): only these problems iterate and
 // are written to xout/yout/res
 int ipm_solve(Handle& h, const absorber_ipm_options& o, const double* x0, const double* y0, double* xout,

@@ -1439,7 +1439,7 @@ static int seg_reduce(Handle& h, const Ops<K>& ops, hipStream_t st) {
 }
 
 int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_first, double* rel, hipStream_t st,
-                      bool first_residual_read, double* rel_p) {
+                      bool first_residual_read, double* rel_p, double target) {
   if (!fused_first) {
     HIP_TRY(launch_solve(h, rhs, st));
     HIP_TRY(launch_schur(h, h.diagx, rhs, 2, sol, st));
@@ -1451,7 +1451,6 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
   // chains solve nothing).  Corrections are applied out of place: xn = xb +
   // correction, where xb holds every problem's best iterate so far; a problem
   // whose residual grew takes its entries of xb back into xn.
-  constexpr double target = 1e-10;  // relative residual target of the refinement
   const int P = h.P;
   const bool per_problem = P > 1;
   std::vector<double> best((size_t)P, INFINITY);
