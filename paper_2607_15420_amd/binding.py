@@ -203,6 +203,14 @@ def _check(rc):
     return rc
 
 
+def _check_call(rc):
+    """Raise on a failed call (bad argument, HIP error, allocation, call
+    order); solver outcomes (-10 and below) are returned in the results."""
+    if -10 < rc < ABS_OK:
+        _check(rc)
+    return rc
+
+
 def params_struct(p: dict) -> AbsorberParams:
     """Fill the C parameter struct from the problem-data dict (params.json)."""
     s = AbsorberParams()
@@ -331,6 +339,7 @@ class Absorber:
         res = (IpmResult * self.P)()
         rc = lib().absorber_batch_solve(self.h, ctypes.byref(o), _ptr(x0), _ptr(lam0), _ptr(x_out), _ptr(lam_out),
                                         res)
+        _check_call(rc)
         return rc, list(res)
 
     def close(self):
@@ -493,6 +502,7 @@ class Absorber:
                                       ctypes.byref(r))
         if check:
             _check(rc)
+        _check_call(rc)
         return r
 
 
