@@ -466,16 +466,33 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     const long long t = t0 + n;
     const double* R = rec + t * REC;
     double v[FR];
-    for (int i = lane; i < REC; i += WAVE) L.src[SRC_REC + i] = R[i];
-    if (lane < NJD) L.src[SRC_DOWN1 + lane] = (n < N - 1) ? rec[(t + 1) * REC + REC_DOWN + lane] : 0.0;
-    if (lane < NK) L.src[SRC_RHS + lane] = rhs ? rhs[t * NK + lane] : 0.0;
-    if (lane < NV) L.src[SRC_DIAGX + lane] = diagx[t * NV + lane] + dw;
+    // the stage's inputs: every load is issued before the first LDS write, so
+    // that they cost one memory round trip (indices clamped, entries past the
+    // ends reread and not written)
+    // (the lane index is re-read here so that the compiler forms the per-lane
+    // offsets in each stage instead of keeping them live, or spilled, across it)
+    int ln = lane_id();
+    __asm__ volatile("" : "+v"(ln));
+    constexpr int NREC = (REC + WAVE - 1) / WAVE;
+    double rv[NREC];
+#pragma unroll
+    for (int m = 0; m < NREC; ++m) rv[m] = R[min(ln + WAVE * m, REC - 1)];
+    const double dn = rec[(n < N - 1 ? t + 1 : t) * REC + REC_DOWN + min(ln, NJD - 1)];
+    const double dx = diagx[t * NV + min(ln, NV - 1)];
+    const double ds = diags[t], brd = R[jd];
+    const double rh = rhs ? rhs[t * NK + min(ln, NK - 1)] : 0.0;
+#pragma unroll
+    for (int m = 0; m < NREC; ++m)
+      if (lane + WAVE * m < REC) L.src[SRC_REC + lane + WAVE * m] = rv[m];
+    if (lane < NJD) L.src[SRC_DOWN1 + lane] = n < N - 1 ? dn : 0.0;
+    if (lane < NK) L.src[SRC_RHS + lane] = rh;
+    if (lane < NV) L.src[SRC_DIAGX + lane] = dx + dw;
     if (lane == 0) {
       // the fused border: the diameter of the stage's section (section 0 when
       // there are several; the other sections' borders are solved afterwards)
-      L.src[SRC_BRD] = section_of(n, N, npar) == 0 ? R[jd] : 0.0;
+      L.src[SRC_BRD] = section_of(n, N, npar) == 0 ? brd : 0.0;
       L.src[SRC_DC] = -dc;
-      L.src[SRC_DHYD] = -(1.0 / (diags[t] + dw) + dc);
+      L.src[SRC_DHYD] = -(1.0 / (ds + dw) + dc);
     }
     __syncthreads();
     // keep the table loads inside the stage loop (hoisting them would pin ~120

@@ -65,6 +65,30 @@ struct JacEntry { int8_t row, blk, col; };
 // the single shared diameter of problem (10).
 constexpr int MAX_NPAR = 4;
 __host__ __device__ __forceinline__ int section_of(int n, int N, int npar) { return (n * npar) / N; }
+
+// Block-wide copy of n (1 <= n <= CAP) elements from global memory to LDS in
+// two halves: load() issues every load of the thread (threads past n reread
+// element n - 1), store() writes them.  Issuing the loads of several arrays
+// before their stores costs one memory round trip instead of one per pass.
+template <int BSZ, int CAP, class T>
+struct LdsStage {
+  static constexpr int K = (CAP + BSZ - 1) / BSZ;
+  T v[K];
+  __device__ __forceinline__ void load(const T* __restrict__ src, int n, int tid) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const int i = tid + u * BSZ;
+      v[u] = src[i < n ? i : n - 1];
+    }
+  }
+  __device__ __forceinline__ void store(T* dst, int n, int tid) const {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const int i = tid + u * BSZ;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+};
 // per-problem design data of the Schur complement for npar > 1 (doubles):
 // [S (npar^2)][delta theta (npar)][W_dd per section (npar)][K_dd diagonal (npar)]
 constexpr int DSC = MAX_NPAR * MAX_NPAR + 3 * MAX_NPAR;

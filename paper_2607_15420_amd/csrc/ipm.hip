@@ -223,14 +223,22 @@ __global__ __launch_bounds__(GBS) void k_lag_grad(const double* __restrict__ rec
   const int ns = sg.t1 - sg.t0;
   const long long la = t0 > 0 ? t0 - 1 : 0, lb = sg.t1 + 1 < nst ? sg.t1 + 1 : nst;
   const int s0 = (int)(la - (t0 - 1));  // LDS slot of stage la (slot s holds stage t0 - 1 + s)
-  for (int i = tid; i < (int)(lb - la) * REC; i += GBS) cf[s0 * REC + i] = rec[la * REC + i];
-  for (int i = tid; i < (int)(lb - la) * NR; i += GBS) sy[s0 * NR + i] = y[la * NR + i];
-  for (int i = tid; i < gtab_n; i += GBS) tab[i] = gtab[i];
-  __syncthreads();
+  const int ncf = (int)(lb - la) * REC, nsy = (int)(lb - la) * NR;
+  LdsStage<GBS, (SEG + 2) * REC, double> scf;
+  LdsStage<GBS, (SEG + 2) * NR, double> ssy;
+  LdsStage<GBS, RT_MAX, int> stb;
+  scf.load(rec + la * REC, ncf, tid);
+  ssy.load(y + la * NR, nsy, tid);
+  stb.load(gtab, gtab_n, tid);
   const int k = tid / SEG, ls = tid - k * SEG;
-  if (k < NV && ls < ns) {
+  const bool mine = k < NV && ls < ns;
+  const StageInfo si = sinfo[t0 + min(ls, ns - 1)];  // loaded before the LDS writes as well
+  scf.store(cf + s0 * REC, ncf, tid);
+  ssy.store(sy + s0 * NR, nsy, tid);
+  stb.store(tab, gtab_n, tid);
+  __syncthreads();
+  if (mine) {
     const long long t = t0 + ls;
-    const StageInfo si = sinfo[t];
     const bool has_dn = si.n > 0, has_up = si.n < si.N - 1;
     const int s = ls + 1;
     const int cbase = s * REC - RT_COFF, ybase = s * NR - RT_XOFF;

@@ -263,28 +263,41 @@ __global__ __launch_bounds__(RBS) void k_residual(
   const double dw = dwv[sg.p], dc = dcv[sg.p];
   const long long la = t0 > 0 ? t0 - 1 : 0, lb = sg.t1 + 1 < nst ? sg.t1 + 1 : nst;
   const int s0 = (int)(la - (t0 - 1));  // LDS slot of stage la (slot s holds stage t0 - 1 + s)
-  for (int i = tid; i < (int)(lb - la) * REC; i += RBS) cf[s0 * REC + i] = rec[la * REC + i];
-  for (int i = tid; i < (int)(lb - la) * NK; i += RBS) sx[s0 * NK + i] = sol[la * NK + i];
-  for (int i = tid; i < rtab_n; i += RBS) tab[i] = rtab[i];
-  for (int i = tid; i < ns * RDG; i += RBS) {
-    const int l = i / RDG, k = i - l * RDG;
-    const long long t = t0 + l;
-    double v = 0.0;
-    if (k < NV) v = diagx[t * NV + k] + dw;
-    else if (k == NV) v = -dc;
-    else if (k == NV + 1) v = -(1.0 / (diags[t] + dw) + dc);
-    cf[(SEG + 2) * REC + i] = v;
-  }
+  const int ncf = (int)(lb - la) * REC, nsx = (int)(lb - la) * NK;
+  LdsStage<RBS, (SEG + 2) * REC, double> scf;
+  LdsStage<RBS, (SEG + 2) * NK, double> ssx;
+  LdsStage<RBS, RT_MAX, int> stb;
+  scf.load(rec + la * REC, ncf, tid);
+  ssx.load(sol + la * NK, nsx, tid);
+  stb.load(rtab, rtab_n, tid);
+  // every other load of the block goes out before the first LDS write too: the
+  // diagonal coefficients (one per thread) and each (stage, row) thread's
+  // stage data, diameter, row index and right-hand side
+  // (indices clamped to the segment, so that no load waits behind a branch)
+  static_assert(SEG * RDG <= RBS, "one diagonal coefficient per thread");
+  const int dl = min(tid / RDG, ns - 1), dk = tid % RDG;
+  double dgx = diagx[(t0 + dl) * NV + min(dk, NV - 1)], dgs = diags[t0 + dl];
+  const int j = tid / SEG, ls = tid - j * SEG;
+  const bool mine = j < NK && ls < ns;
+  const long long tm = t0 + min(ls, ns - 1);
+  const StageInfo si = sinfo[tm];
+  const int row = rtab[min(j, NK - 1)];
+  // the loads above complete together here (kept out of the selects below)
+  __asm__ volatile("" : "+v"(dgx), "+v"(dgs));
+  const double xd = sol[nks + (long long)sg.p * npar + section_of(si.n, si.N, npar)];  // its section's diameter
+  const double r = rhs[tm * NK + row];
+  const double dhyd = -(1.0 / (dgs + dw) + dc);
+  const double dgv = dk < NV ? dgx + dw : (dk == NV ? -dc : (dk == NV + 1 ? dhyd : 0.0));
+  scf.store(cf + s0 * REC, ncf, tid);
+  ssx.store(sx + s0 * NK, nsx, tid);
+  stb.store(tab, rtab_n, tid);
+  if (tid < ns * RDG) cf[(SEG + 2) * REC + tid] = dgv;
   if (tid < 2 * SEG) dsum[tid] = 0.0;
   __syncthreads();
-  const int j = tid / SEG, ls = tid - j * SEG;
   double om = 0.0, rmax = 0.0, bmax = 0.0;
-  if (j < NK && ls < ns) {
+  if (mine) {
     const long long t = t0 + ls;
-    const StageInfo si = sinfo[t];
     const bool has_dn = si.n > 0, has_up = si.n < si.N - 1;
-    const double xd = sol[nks + (long long)sg.p * npar + section_of(si.n, si.N, npar)];  // its section's diameter
-    const int row = tab[j];
     const int s = ls + 1;
     const int cbase = s * REC - RT_COFF, dbase = (SEG + 2) * REC + ls * RDG - RT_DIAG, xbase = s * NK - RT_XOFF;
     const int* tl = tab + 2 * NK + 1;
@@ -299,7 +312,6 @@ __global__ __launch_bounds__(RBS) void k_residual(
       y += pr;
       ya += fabs(pr);
     }
-    const double r = rhs[t * NK + row];
     const double rr = r - y;
     res[t * NK + row] = rr;
     const double den = ya + fabs(r);
