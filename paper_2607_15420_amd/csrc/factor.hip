@@ -497,25 +497,31 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     __syncthreads();
     // keep the table loads inside the stage loop (hoisting them would pin ~120
     // registers); the pointer keeps its global address space, so the loads are
-    // global loads issued eight at a time before their LDS gathers
+    // global loads, issued eight at a time one chunk ahead of their LDS gathers
     typedef const __attribute__((address_space(1))) int gint;
     gint* gt = (gint*)gather;
     __asm__ volatile("" : "+s"(gt));
+    int ga[8], gb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ga[j] = gt[j * WAVE + lane];
 #pragma unroll
     for (int i0 = 0; i0 < FR; i0 += 8) {
-      int g[8];
+      if (i0 + 8 < FR) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) g[j] = i0 + j < FR ? gt[(i0 + j) * WAVE + lane] : 0;
+        for (int j = 0; j < 8; ++j) gb[j] = i0 + 8 + j < FR ? gt[(i0 + 8 + j) * WAVE + lane] : 0;
+      }
       // only the rows that have them read a second and third source (the
       // others add exact zeros in the table's layout)
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (i0 + j >= FR) continue;
-        double a = L.src[g[j] & 1023];
-        if ((GATHER2 >> (i0 + j)) & 1ull) a += L.src[(g[j] >> 10) & 1023];
-        if ((GATHER3 >> (i0 + j)) & 1ull) a += L.src[(g[j] >> 20) & 1023];
+        double a = L.src[ga[j] & 1023];
+        if ((GATHER2 >> (i0 + j)) & 1ull) a += L.src[(ga[j] >> 10) & 1023];
+        if ((GATHER3 >> (i0 + j)) & 1ull) a += L.src[(ga[j] >> 20) & 1023];
         v[i0 + j] = a;
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ga[j] = gb[j];
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
