@@ -707,7 +707,7 @@ __global__ __launch_bounds__(SCHUR_BS) void k_schur(const double* __restrict__ p
   // mode 0: factor only; 1: factor with a right-hand side; 2: right-hand side only
   // The six sums (three of them integer counts, exact in double) run in a fixed
   // order: thread i takes chains i, i + SCHUR_BS, ... four at a time, then a
-  // shuffle tree inside each wave and across the waves.
+  // DPP tree inside each wave and across the waves.
   __shared__ double sm[6][SCHUR_BS / 64];
   const int pb = blockIdx.x;
   if (pmask && !pmask[pb]) return;  // this problem keeps its scalars
@@ -743,19 +743,13 @@ __global__ __launch_bounds__(SCHUR_BS) void k_schur(const double* __restrict__ p
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < 6; ++k) a[k] += __shfl_down(a[k], off, 64);
-  if (lane == 0)
+  for (int k = 0; k < 6; ++k) a[k] = wave_reduce(0, a[k]);
+  if (lane == 63)
     for (int k = 0; k < 6; ++k) sm[k][wv] = a[k];
   __syncthreads();
   if (wv != 0) return;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    a[k] = lane < SCHUR_BS / 64 ? sm[k][lane] : 0.0;
-#pragma unroll
-    for (int off = SCHUR_BS / 128; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off, 64);
-  }
+  for (int k = 0; k < 6; ++k) a[k] = rdl(wave_reduce(0, lane < SCHUR_BS / 64 ? sm[k][lane] : 0.0), 63);
   const double sb0 = a[0], sr0 = a[1], sw0 = a[2];
   if (threadIdx.x == 0) {
     if (mode != 2) {

@@ -66,6 +66,34 @@ struct JacEntry { int8_t row, blk, col; };
 constexpr int MAX_NPAR = 4;
 __host__ __device__ __forceinline__ int section_of(int n, int N, int npar) { return (n * npar) / N; }
 
+// reduction operations: 0 sum, 1 maximum, 2 minimum
+__device__ __forceinline__ double red_op(int op, double a, double b) {
+  return op == 0 ? a + b : (op == 1 ? fmax(a, b) : fmin(a, b));
+}
+
+// One step of a wave reduction through DPP: v = v op (v of the lane the
+// control selects); a lane without a source, or in a row the mask leaves out,
+// sees the identity idn.
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_step(int op, double v, double idn) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(idn), __double2loint(v), CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(idn), __double2hiint(v), CTRL, RM, 0xf, false);
+  return red_op(op, v, __hiloint2double(hi, lo));
+}
+
+// Wave reduction in a fixed order (row shifts, then row broadcasts); lane 63
+// ends with the result.
+__device__ __forceinline__ double wave_reduce(int op, double v) {
+  const double idn = op == 0 ? 0.0 : (op == 1 ? -INFINITY : INFINITY);
+  v = dpp_step<0x111, 0xf>(op, v, idn);  // row_shr:1
+  v = dpp_step<0x112, 0xf>(op, v, idn);  // row_shr:2
+  v = dpp_step<0x114, 0xf>(op, v, idn);  // row_shr:4
+  v = dpp_step<0x118, 0xf>(op, v, idn);  // row_shr:8
+  v = dpp_step<0x142, 0xa>(op, v, idn);  // row_bcast:15
+  v = dpp_step<0x143, 0xc>(op, v, idn);  // row_bcast:31
+  return v;
+}
+
 // Block-wide copy of n (1 <= n <= CAP) elements from global memory to LDS in
 // two halves: load() issues every load of the thread (threads past n reread
 // element n - 1), store() writes them.  Issuing the loads of several arrays

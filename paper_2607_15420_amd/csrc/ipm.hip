@@ -103,21 +103,16 @@ struct Ops {
   int op[K];  // 0 sum, 1 max, 2 min
 };
 
-__device__ __forceinline__ double red_op(int op, double a, double b) {
-  return op == 0 ? a + b : (op == 1 ? fmax(a, b) : fmin(a, b));
-}
 
-// block reduction of K values in a fixed order (a shuffle tree inside each
-// wave, then across the BS / 64 waves); per-block partials out[blockIdx.x * K + k]
+// block reduction of K values in a fixed order (a DPP tree inside each wave,
+// then across the BS / 64 waves); per-block partials out[blockIdx.x * K + k]
 template <int K>
 __device__ void block_reduce(Part<K> p, const Ops<K>& ops, double* out) {
   __shared__ double sm[K][BS / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < K; ++k) p.v[k] = red_op(ops.op[k], p.v[k], __shfl_down(p.v[k], off, 64));
-  if (lane == 0)
+  for (int k = 0; k < K; ++k) p.v[k] = wave_reduce(ops.op[k], p.v[k]);
+  if (lane == 63)
     for (int k = 0; k < K; ++k) sm[k][wv] = p.v[k];
   __syncthreads();
   if (threadIdx.x == 0)

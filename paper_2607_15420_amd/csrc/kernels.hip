@@ -326,13 +326,10 @@ __global__ __launch_bounds__(RBS) void k_residual(
       dsum[2 * ls + 1] = fabs(pr);
     }
   }
-#pragma unroll
-  for (int m = 1; m < WAVE; m <<= 1) {
-    om = fmax(om, __shfl_xor(om, m, WAVE));
-    rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
-    bmax = fmax(bmax, __shfl_xor(bmax, m, WAVE));
-  }
-  if ((tid & (WAVE - 1)) == 0) {
+  om = wave_reduce(1, om);
+  rmax = wave_reduce(1, rmax);
+  bmax = wave_reduce(1, bmax);
+  if ((tid & (WAVE - 1)) == WAVE - 1) {
     wred[0][tid / WAVE] = om;
     wred[1][tid / WAVE] = rmax;
     wred[2][tid / WAVE] = bmax;
@@ -505,19 +502,15 @@ __global__ __launch_bounds__(MAX_BS) void k_residual_max(const double* __restric
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], __shfl_down(m[k], off, 64));
-  if (lane == 0)
+  for (int k = 0; k < 4; ++k) m[k] = wave_reduce(1, m[k]);
+  if (lane == 63)
     for (int k = 0; k < 4; ++k) sm[k][wv] = m[k];
   __syncthreads();
   if (wv == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      double v = lane < MAX_BS / 64 ? sm[k][lane] : 0.0;
-#pragma unroll
-      for (int off = MAX_BS / 128; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-      if (lane == 0) out[k] = v;
+      const double v = wave_reduce(1, lane < MAX_BS / 64 ? sm[k][lane] : 0.0);
+      if (lane == 63) out[k] = v;
     }
   }
 }
