@@ -68,6 +68,30 @@ __device__ __forceinline__ double rowsel(const double (&v)[FR], int p) {
   }
 }
 
+// register p of this lane for a uniform p in [LO, LO + W), W = 8 or 16: one
+// indexed register move (s_set_gpr_idx) out of the tuple of rows LO..LO+W-1,
+// which the compiler forms from the frontal registers themselves (no copies).
+// A phase whose lowest remaining pivot stays inside such a window selects it
+// this way instead of through the branch tree above.
+typedef double dvec8 __attribute__((ext_vector_type(8)));
+typedef double dvec16 __attribute__((ext_vector_type(16)));
+template <int LO, int W>
+__device__ __forceinline__ double rowsel_win(const double (&v)[FR], int p) {
+  static_assert(W == 8 || W == 16, "window of 8 or 16 rows");
+  static_assert(LO + W <= FR, "window inside the frontal matrix");
+  if constexpr (W == 8) {
+    dvec8 t;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = v[LO + i];
+    return t[(p - LO) & 7];
+  } else {
+    dvec16 t;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = v[LO + i];
+    return t[(p - LO) & 15];
+  }
+}
+
 // Wave maximum of a non-negative double and its lane.  The key is the high
 // word of the value (sign, exponent, 20 mantissa bits) with its 6 lowest bits
 // replaced by 63 - lane (ties go to the lowest lane); keys are max-reduced with
@@ -131,7 +155,11 @@ __device__ __forceinline__ void eliminate_phase(double (&v)[FR], double* __restr
   while (act && __builtin_ctzll(act) < LIMIT) {
     const int k = __builtin_ctzll(act);
     const bool own_act = lane < NK && ((act >> lane) & 1ull);
-    const double rowk = rowsel<8 * C0>(v, k);  // F[k][lane] = F[lane][k]
+    // F[k][lane] = F[lane][k]; k stays below LIMIT (and NK) in this phase
+    constexpr int KW = (LIMIT < NK ? LIMIT : NK) - 8 * C0;
+    const double rowk = KW <= 8 ? rowsel_win<8 * C0, 8>(v, k)
+                        : KW <= 16 ? rowsel_win<8 * C0, 16>(v, k)
+                                   : rowsel<8 * C0>(v, k);
     const double dkk = rdl(rowk, k);
     // 1/d for the usual 1x1 pivot at k, started before the search so that the
     // two dependency chains overlap
