@@ -25,8 +25,9 @@ inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) /
 // coupling unknowns of stage n+1, 59 the right-hand side r, 60 the border b
 // (both carried as symmetric extra rows and columns).  Eliminating the 43 own
 // pivots leaves in rows/cols 43-60 the contribution to stage n+1's block and
-// right-hand sides.  The candidate pivot row is selected by a uniform switch
-// over the registers (by symmetry it is the candidate column), single entries
+// right-hand sides.  The candidate pivot row is selected from the registers
+// (by symmetry it is the candidate column) by one indexed register move inside
+// a phase's window of rows, or by a uniform switch, single entries
 // reach every lane through v_readlane, and the pivot column of each rank-1
 // update is broadcast through LDS (every lane reads the same address).
 constexpr int TAIL = SLOT - NK;  // rows 43-63 of a stored pivot column: coupling, r, b, code, d, 1/d
@@ -143,8 +144,10 @@ __device__ __forceinline__ void rank1_rows(double (&v)[FR], const double* bc, do
 // Pivots of one stage taken while the lowest remaining pivot is below LIMIT
 // (Bunch-Kaufman inside the stage); stores one pivot column per slot (rows
 // still active, code, d or 2x2 block, 1/d).  The matrix is symmetric, so the
-// pivot candidates' columns are read as rows (register p of every lane) with a
-// uniform switch.  The rank-1 updates start at row 8*C0.
+// pivot candidates' columns are read as rows (register p of every lane): the
+// lowest remaining pivot with an indexed move when the phase's window of
+// possible pivots spans at most 16 rows, the second Bunch-Kaufman candidate
+// (any active row) with a uniform switch.  The rank-1 updates start at row 8*C0.
 template <int C0, int LIMIT>
 __device__ __forceinline__ void eliminate_phase(double (&v)[FR], double* __restrict__ sb, double* bc,
                                                 uint64_t& act, int& slot, int& npos, int& nneg,
