@@ -294,7 +294,7 @@ static void free_handle(Handle& h) {
   }
   for (hipEvent_t e : h.prof_pool) (void)hipEventDestroy(e);
   if (h.prof_open) (void)hipEventDestroy(h.prof_open);
-  void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.solr, h.solb, h.inert, h.part,
+  void* ptrs[] = {h.feeds, h.gather, h.rtab, h.gtab, h.jtab, h.cs, h.rec, h.slots, h.slot_lines, h.solr, h.solb, h.inert, h.part,
                   h.scal, h.diagx, h.diags, h.kres, h.kcor, h.kden, h.omega_d, h.redbuf,
                   h.warm_X, h.warm_Y, h.warm_x0, h.warm_l0, h.warm_w, h.sinfo, h.chain0, h.chain_p, h.pchain, h.pstage,
                   h.seg, h.pseg, h.ctl, h.ipm_work, h.pres, h.rmask, h.solbk, h.brhs, h.pdots, h.dsc, h.opa};
@@ -493,6 +493,7 @@ static int create_impl(const absorber_params* prm, int32_t n_problems, const int
   ALLOC(h.cs, h.nc);
   ALLOC(h.rec, nst * REC);
   ALLOC(h.slots, nst * NK * SLOT);
+  ALLOC(h.slot_lines, nst * 2);
   ALLOC(h.solr, nst * NK);
   ALLOC(h.solb, nst * NK);
   ALLOC(h.inert, (size_t)h.S * 4);

@@ -418,12 +418,12 @@ __device__ __forceinline__ double wave_total(double v) {
 // stage-local index (read at the 16 coupling indices).  On return lane i < 43
 // holds the solution of row i in xl[r].
 template <int R>
-__device__ __forceinline__ void backward_rows(const double* __restrict__ sb, const double (&ys)[R],
+__device__ __forceinline__ void backward_rows(const double* __restrict__ sb, int lim, const double (&ys)[R],
                                               const double* const (&xc)[R], double (&xl)[R]) {
   const int lane = lane_id();
   double col[NK];
 #pragma unroll
-  for (int q = 0; q < NK; ++q) col[q] = sb[q * SLOT + lane];
+  for (int q = 0; q < NK; ++q) col[q] = q < lim ? sb[q * SLOT + lane] : 0.0;
   const bool cpl = lane >= NK && lane < NK + NC;
   const int ci = coupling_index(cpl ? lane - NK : 0);
 #pragma unroll
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     const double* __restrict__ rec, const int* __restrict__ gather, const double* __restrict__ rhs,
     const double* __restrict__ diagx, const double* __restrict__ diags, const double* __restrict__ dwv,
     const double* __restrict__ dcv, const int* __restrict__ chain0, const int* __restrict__ chain_p,
-    const int* __restrict__ fmask, const int* __restrict__ chmask, int W, int jd, int npar, double* __restrict__ slots,
+    const int* __restrict__ fmask, const int* __restrict__ chmask, int W, int jd, int npar, double* __restrict__ slots, int* __restrict__ lines,
     double* __restrict__ solr, double* __restrict__ solb, int* __restrict__ inert, double* __restrict__ part) {
   __shared__ WaveLDS L;
   const int w = blockIdx.x;
@@ -576,6 +576,19 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     double xr_s, xb_s;
     int p_s;
     backward_stage(sb, L.stg, L.xr, L.xb, true, xr_s, xb_s, p_s);
+    // For the stored-factor solve: the entries of pivot column q at rows 0-15
+    // (one 128-byte line) are all zero once every one of those rows has been
+    // eliminated, i.e. for q at or past the last slot whose pivot lies there
+    // (the pivot's own entry is stored as zero).  That slot, and the one for
+    // rows 16-31, bound the columns whose line must be read.
+    {
+      const uint64_t in0 = __ballot(lane < NK && p_s < 16);
+      const uint64_t in1 = __ballot(lane < NK && p_s >= 16 && p_s < 32);
+      if (lane == 0) {
+        lines[2 * t] = in0 ? 63 - __builtin_clzll(in0) : 0;
+        lines[2 * t + 1] = in1 ? 63 - __builtin_clzll(in1) : 0;
+      }
+    }
     __syncthreads();
     if (lane < NK) {
       solr[t * NK + p_s] = xr_s;
@@ -610,7 +623,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
 // solr[j] <- K_w^{-1} rhs[j], rhs[j] = rhs + j * stride, solr[j] likewise.
 // With one right-hand side the border dot b . x goes to part (Schur on d).
 template <int WPE, int R>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) void k_solve(const double* __restrict__ rec, const double* __restrict__ slots, const int* __restrict__ lines,
                                                 const double* __restrict__ rhs, const int* __restrict__ chain0,
                                                 const int* __restrict__ chain_p, const int* __restrict__ pact,
                                                 const int* __restrict__ chmask, int W, int jd, long long stride,
@@ -647,10 +660,14 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       r[j] = lane < NK ? rhs[j * stride + t * NK + lane] + sh[j][lane] : 0.0;
       ys[j] = 0.0;
     }
-    // the stage's 43 pivot columns, all loads in flight at once (lane = row)
+    // the stage's 43 pivot columns, all loads in flight at once (lane = row);
+    // the lines of rows 0-15 and 16-31 only in the columns that can have
+    // nonzeros there (the others are zero)
+    const int l0 = lines[2 * t], l1 = lines[2 * t + 1];
+    const int lim = lane < 16 ? l0 : lane < 32 ? l1 : NK;
     double col[NK];
 #pragma unroll
-    for (int q = 0; q < NK; ++q) col[q] = sb[q * SLOT + lane];
+    for (int q = 0; q < NK; ++q) col[q] = q < lim ? sb[q * SLOT + lane] : 0.0;
     bool skip = false;
 #pragma unroll
     for (int q = 0; q < NK; ++q) {
@@ -709,7 +726,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
       xc[j] = sh[j];
     }
     double x[R];
-    backward_rows<R>(sb, y, xc, x);
+    const int l0 = lines[2 * t], l1 = lines[2 * t + 1];
+    const int lim = lane < 16 ? l0 : lane < 32 ? l1 : NK;
+    backward_rows<R>(sb, lim, y, xc, x);
     __syncthreads();
     if (lane < NK)
 #pragma unroll
@@ -1103,7 +1122,8 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
   prof_begin(h, 0, st);
 #define ABS_FACTOR(S, W)                                                                                    \
   hipLaunchKernelGGL((k_factor<S, W>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.gather, rhs, diagx, diags, h.dwv, \
-                     h.dcv, h.chain0, h.chain_p, fm, h.chmask, nw, h.jac_d_index, h.npar, h.slots, h.solr, h.solb, \
+                     h.dcv, h.chain0, h.chain_p, fm, h.chmask, nw, h.jac_d_index, h.npar, h.slots, h.slot_lines, \
+                     h.solr, h.solb, \
                      h.inert, h.part)
   // launch shape: occupancy target (waves per SIMD 2 or 3) and row split of the update
   const int wpe = h.tune.factor_wpe, split = h.tune.factor_split;
@@ -1131,7 +1151,8 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
   prof_begin(h, 1, st);
   const int* pa = h.pact_on ? h.pact : nullptr;
 #define ABS_SOLVE(W, RR)                                                                                          \
-  hipLaunchKernelGGL((k_solve<W, RR>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, rhs, h.chain0, h.chain_p, pa, \
+  hipLaunchKernelGGL((k_solve<W, RR>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, h.slot_lines, rhs, h.chain0,  \
+                     h.chain_p, pa,                                                                             \
                      h.chmask, nw, h.jac_d_index, stride, xo, h.part)
   // several right-hand sides need about 190-210 VGPRs: 2 waves per SIMD (a
   // higher target would spill)

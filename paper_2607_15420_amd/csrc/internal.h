@@ -232,6 +232,8 @@ struct Handle {
   // work buffers
   double* rec = nullptr;                     // [S][N][REC]
   double* slots = nullptr;                   // [S][N][NK][SLOT] stored pivot columns
+  int* slot_lines = nullptr;                 // [S][N][2] per stage: the pivot columns that may hold nonzeros in
+                                             // rows 0-15 / 16-31 (the leading ones; see k_factor)
   double* solr = nullptr;                    // [S][N][NK] K_w^{-1} r
   double* solb = nullptr;                    // [S][N][NK] K_w^{-1} b (for npar > 1: the border of section 0)
   double* solbk = nullptr;                   // npar > 1: [npar - 1][S][N][NK] K_w^{-1} b_k of sections 1..
