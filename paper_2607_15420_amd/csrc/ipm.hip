@@ -1282,7 +1282,12 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
       HIP_TRY(e);
       HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st, h.rmask));
       HIP_TRY(launch_axpy(h.kcor, W.sol, h.kres, 1.0, nkkt, st));
-      HIP_TRY(launch_residual(h, h.diagx, h.diags, h.kcor, W.rhs, h.kres, h.omega_d, st));
+      // the residual of the corrected iterate only for the refining problems
+      // (the others' rows and partials come out zero and k_ctl_refine skips them)
+      h.pact = h.rmask;
+      const hipError_t er = launch_residual(h, h.diagx, h.diags, h.kcor, W.rhs, h.kres, h.omega_d, st);
+      h.pact = pact;
+      HIP_TRY(er);
       HIP_TRY(launch_residual_pmax(h, st));
       hipLaunchKernelGGL(k_ctl_refine, dim3(gp), dim3(64), 0, st, g, h.pres, 1e-10);
       HIP_TRY(launch_copy_rows(h, gs.cmask, W.sol, h.kcor, st));
@@ -1463,7 +1468,19 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
   double* om = h.redbuf_h + h.red_cap - 4;  // four pinned doubles past the partials
   for (int it = 0; it <= 10; ++it) {
     if (it > 0 || !first_residual_read) {  // else the caller has read the first residual's norms into om
-      HIP_TRY(launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st));
+      // after a correction only the problems that took it need their residual:
+      // the device mask holds the refining problems of the previous step (the
+      // others get zero rows and partials, which are neither read nor used)
+      int* const pact = h.pact;
+      const bool pact_on = h.pact_on;
+      if (per_problem && it > 0) {
+        h.pact = h.rmask;
+        h.pact_on = true;
+      }
+      const hipError_t e = launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st);
+      h.pact = pact;
+      h.pact_on = pact_on;
+      HIP_TRY(e);
       HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       if (!per_problem) HIP_TRY(wait_stream(st));
     }
