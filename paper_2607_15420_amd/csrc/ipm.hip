@@ -1535,7 +1535,9 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
     } else {
       HIP_TRY(launch_solve(h, h.kres, st));
     }
-    HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st));  // correction in place
+    // correction in place (in a batch only for the refining problems: the others'
+    // rows of kres stay zero and their Schur scalars are not read again)
+    HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st, per_problem ? h.rmask : nullptr));
     double* xnew = xn == sol ? h.kcor : sol;
     HIP_TRY(launch_axpy(xnew, xn, h.kres, 1.0, h.nkkt, st));  // xnew = xn + correction
     xb = xn;
