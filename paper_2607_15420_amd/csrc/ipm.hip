@@ -161,12 +161,18 @@ __global__ __launch_bounds__(RS) void k_seg_reduce(const double* __restrict__ pa
     for (int k = 0; k < K; ++k) sm[k][wv] = acc[k];
   __syncthreads();
   if (wv == 0) {
-    for (int k = 0; k < K; ++k) {
-      double v = lane < RS / 64 ? sm[k][lane] : (ops.op[k] == 0 ? 0.0 : (ops.op[k] == 1 ? -INFINITY : INFINITY));
+    // the K trees side by side, so that their shuffle latencies overlap
+    double v[K];
 #pragma unroll
-      for (int off = RS / 128; off > 0; off >>= 1) v = red_op(ops.op[k], v, __shfl_down(v, off, 64));
-      if (lane == 0) out[p * K + k] = v;
-    }
+    for (int k = 0; k < K; ++k)
+      v[k] = lane < RS / 64 ? sm[k][lane] : (ops.op[k] == 0 ? 0.0 : (ops.op[k] == 1 ? -INFINITY : INFINITY));
+#pragma unroll
+    for (int off = RS / 128; off > 0; off >>= 1)
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] = red_op(ops.op[k], v[k], __shfl_down(v[k], off, 64));
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < K; ++k) out[p * K + k] = v[k];
   }
 }
 
