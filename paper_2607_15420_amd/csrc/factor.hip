@@ -627,15 +627,17 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(WPE))) voi
                                                 const double* __restrict__ rhs, const int* __restrict__ chain0,
                                                 const int* __restrict__ chain_p, const int* __restrict__ pact,
                                                 const int* __restrict__ chmask, int W, int jd, long long stride,
-                                                double* __restrict__ solr, double* __restrict__ part) {
+                                                int zero_masked, double* __restrict__ solr, double* __restrict__ part) {
   __shared__ double sh[R][WAVE];
   const int w = blockIdx.x;
   if (w >= W) return;
-  if ((pact && !pact[chain_p[w]]) || (chmask && !chmask[w])) {  // not worked on: zero solution
+  const bool left_out = chmask && !chmask[w];
+  if (left_out || (pact && !pact[chain_p[w]])) {  // not worked on: zero solution (rows on request)
     if (R == 1 && threadIdx.x == 0) part[(long long)w * 4 + 1] = 0.0;
-    for (int j = 0; j < R; ++j)
-      for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE)
-        solr[j * stride + i] = 0.0;
+    if (left_out || zero_masked)
+      for (int j = 0; j < R; ++j)
+        for (long long i = (long long)chain0[w] * NK + threadIdx.x; i < (long long)chain0[w + 1] * NK; i += WAVE)
+          solr[j * stride + i] = 0.0;
     return;
   }
   const long long t0 = chain0[w];
@@ -1144,7 +1146,7 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
 }
 
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain, double* out, int nrhs,
-                        long long stride) {
+                        long long stride, bool zero_masked) {
   const int nw = nchain < 0 || nchain > h.S ? h.S : nchain;
   double* const xo = out ? out : h.solr;
   if (nrhs < 1 || nrhs > MAX_NPAR - 1 || (nrhs > 1 && !out)) return hipErrorInvalidValue;
@@ -1153,7 +1155,7 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
 #define ABS_SOLVE(W, RR)                                                                                          \
   hipLaunchKernelGGL((k_solve<W, RR>), dim3(nw), dim3(WAVE), 0, st, h.rec, h.slots, h.slot_lines, rhs, h.chain0,  \
                      h.chain_p, pa,                                                                             \
-                     h.chmask, nw, h.jac_d_index, stride, xo, h.part)
+                     h.chmask, nw, h.jac_d_index, stride, zero_masked ? 1 : 0, xo, h.part)
   // several right-hand sides need about 190-210 VGPRs: 2 waves per SIMD (a
   // higher target would spill)
   if (nrhs == 2) ABS_SOLVE(2, 2);

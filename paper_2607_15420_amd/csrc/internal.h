@@ -352,9 +352,11 @@ hipError_t launch_factor(Handle& h, const double* diagx, const double* diags, co
                          hipStream_t st, int nchain = -1);
 // forward/backward with the stored factors: out (default h.solr) <- K_w^{-1} rhs (nchain as above)
 // nrhs right-hand sides (1 to MAX_NPAR - 1) rhs + j * stride into out + j * stride
-// (out required for nrhs > 1; the border dot of part only for nrhs = 1)
+// (out required for nrhs > 1; the border dot of part only for nrhs = 1).
+// zero_masked = false leaves the solution rows of problems outside h.pact
+// unwritten (for callers that read only the masked-in problems' rows).
 hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain = -1, double* out = nullptr,
-                        int nrhs = 1, long long stride = 0);
+                        int nrhs = 1, long long stride = 0, bool zero_masked = true);
 // Schur complement on each problem's d.  diagx: Sigma_x (its d entries are
 // Sigma_d); rhs: the right-hand side (its d entries are r_d; may be null in
 // mode 0).  mode 0: after launch_factor without a right-hand side (S_d,
@@ -364,9 +366,12 @@ hipError_t launch_solve(Handle& h, const double* rhs, hipStream_t st, int nchain
 hipError_t launch_schur(Handle& h, const double* diagx, const double* rhs, int mode, double* sol, hipStream_t st,
                         const int* pmask = nullptr);
 // residual res = rhs - K sol of the bordered systems; omega_out[0] = max
-// componentwise backward error over the scenario rows, omega_out[1] over the d rows
+// componentwise backward error over the scenario rows, omega_out[1] over the d rows.
+// zero_masked = false leaves the residual rows of problems outside h.pact
+// unwritten (their partials are still zero).
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
-                           const double* rhs, double* res, double* omega_out, hipStream_t st);
+                           const double* rhs, double* res, double* omega_out, hipStream_t st,
+                           bool zero_masked = true);
 // per problem p: pres[2p] = max |res_i|, pres[2p + 1] = max |rhs_i| over its
 // rows (stage rows and its d row) from the partials of the last launch_residual
 hipError_t launch_residual_pmax(Handle& h, hipStream_t st);

@@ -1283,7 +1283,9 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
       HIP_TRY(launch_mask_rows(h, h.rmask, h.kres, st));
       int* const pact = h.pact;
       h.pact = h.rmask;
-      const hipError_t e = launch_solve(h, h.kres, st);
+      // the rows of the other problems are not read (their Schur step and
+      // combine are masked too; mask_rows clears kres): left unwritten
+      const hipError_t e = launch_solve(h, h.kres, st, -1, nullptr, 1, 0, false);
       h.pact = pact;
       HIP_TRY(e);
       HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st, h.rmask));
@@ -1291,7 +1293,7 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
       // the residual of the corrected iterate only for the refining problems
       // (the others' rows and partials come out zero and k_ctl_refine skips them)
       h.pact = h.rmask;
-      const hipError_t er = launch_residual(h, h.diagx, h.diags, h.kcor, W.rhs, h.kres, h.omega_d, st);
+      const hipError_t er = launch_residual(h, h.diagx, h.diags, h.kcor, W.rhs, h.kres, h.omega_d, st, false);
       h.pact = pact;
       HIP_TRY(er);
       HIP_TRY(launch_residual_pmax(h, st));
@@ -1483,7 +1485,9 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
         h.pact = h.rmask;
         h.pact_on = true;
       }
-      const hipError_t e = launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st);
+      // (rows of the other problems left unwritten: mask_rows clears them below)
+      const hipError_t e =
+          launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st, !(per_problem && it > 0));
       h.pact = pact;
       h.pact_on = pact_on;
       HIP_TRY(e);
@@ -1534,7 +1538,9 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
       const bool pact_on = h.pact_on;
       h.pact = h.rmask;
       h.pact_on = true;
-      const hipError_t e = launch_solve(h, h.kres, st);
+      // the other problems' rows of the solution are not read (masked Schur
+      // step and combine): left unwritten
+      const hipError_t e = launch_solve(h, h.kres, st, -1, nullptr, 1, 0, false);
       h.pact = pact;
       h.pact_on = pact_on;
       HIP_TRY(e);

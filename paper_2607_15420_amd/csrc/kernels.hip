@@ -239,7 +239,7 @@ __global__ __launch_bounds__(RBS) void k_residual(
     const double* __restrict__ diags, const double* __restrict__ dwv, const double* __restrict__ dcv,
     const double* __restrict__ sol, const double* __restrict__ rhs, const Seg* __restrict__ segs,
     const StageInfo* __restrict__ sinfo, long long nst, const int* __restrict__ pact, long long nks, int jd,
-    int npar, double* __restrict__ res, double* __restrict__ part, double* __restrict__ omb) {
+    int npar, int zero_masked, double* __restrict__ res, double* __restrict__ part, double* __restrict__ omb) {
   __shared__ double cf[(SEG + 2) * REC + SEG * RDG];  // records of stages t0-1 .. t1, then diagonals
   __shared__ double sx[(SEG + 2) * NK];               // unknowns of the same stages
   __shared__ int tab[RT_MAX];
@@ -249,8 +249,9 @@ __global__ __launch_bounds__(RBS) void k_residual(
   const Seg sg = segs[blockIdx.x];
   const long long t0 = sg.t0;
   const int ns = sg.t1 - sg.t0;
-  if (pact && !pact[sg.p]) {  // problem not being worked on: zero residual
-    for (long long i = t0 * NK + tid; i < (long long)sg.t1 * NK; i += RBS) res[i] = 0.0;
+  if (pact && !pact[sg.p]) {  // problem not being worked on: zero residual (rows on request)
+    if (zero_masked)
+      for (long long i = t0 * NK + tid; i < (long long)sg.t1 * NK; i += RBS) res[i] = 0.0;
     if (tid == 0) {
       part[2 * blockIdx.x] = 0.0;
       part[2 * blockIdx.x + 1] = 0.0;
@@ -672,7 +673,7 @@ int autotune(Handle& h, const double* x, const double* y, double* c, const doubl
 }
 
 hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, const double* sol,
-                           const double* rhs, double* res, double* omega_out, hipStream_t st) {
+                           const double* rhs, double* res, double* omega_out, hipStream_t st, bool zero_masked) {
   const long long nks = h.nst * NK;
   const int* pa = h.pact_on ? h.pact : nullptr;
   const int nb = h.nseg;
@@ -681,7 +682,7 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
   double* omd = omb + 3LL * nb;     // 3 per problem
   prof_begin(h, 3, st);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RBS), 0, st, h.rec, h.rtab, h.rtab_n, diagx, diags, h.dwv, h.dcv, sol,
-                     rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, h.npar, res, part, omb);
+                     rhs, h.seg, h.sinfo, h.nst, pa, nks, h.jac_d_index, h.npar, zero_masked ? 1 : 0, res, part, omb);
   prof_end(h, 3, st);
   if (h.npar == 1)
     hipLaunchKernelGGL(k_residual_d, dim3(h.P), dim3(256), 0, st, part, h.pseg, h.scal, sol, rhs, nks, pa, res, omd);
