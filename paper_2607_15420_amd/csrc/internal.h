@@ -383,6 +383,9 @@ hipError_t launch_copy_rows(Handle& h, const int* mask, double* dst, const doubl
 hipError_t launch_tile_x0(Handle& h, double* x, hipStream_t st);
 // z = y + a x (z may be y)
 hipError_t launch_axpy(double* z, const double* y, const double* x, double a, long long n, hipStream_t st);
+// the same on the rows (stage and design rows) of the problems in mask only
+hipError_t launch_axpy_rows(Handle& h, const int* mask, double* z, const double* y, const double* x, double a,
+                            hipStream_t st);
 // time the launch-shape candidates on the current data and keep the fastest (h.tune); x, y, c as for
 // launch_eval (scaled, full), diagx/diags/rhs as for launch_factor
 int autotune(Handle& h, const double* x, const double* y, double* c, const double* diagx, const double* diags,

@@ -1279,17 +1279,18 @@ int graph_iterations(Handle& h, const absorber_ipm_options& o, const Consts& C, 
     }));
     GTRY(capture_graph(st, &gs.ex[G_FAC_A], fac_a));
     GTRY(capture_graph(st, &gs.ex[G_FAC_B], fac_b));
+    // W.sol holds every problem's best iterate, h.kcor the corrected candidate
+    // of the refining ones (rmask); every step of a correction reads and
+    // writes only the refining problems' rows, so the others' rows of kres and
+    // kcor are neither cleared nor read
     GTRY(capture_graph(st, &gs.ex[G_REF], [&]() -> int {
-      HIP_TRY(launch_mask_rows(h, h.rmask, h.kres, st));
       int* const pact = h.pact;
       h.pact = h.rmask;
-      // the rows of the other problems are not read (their Schur step and
-      // combine are masked too; mask_rows clears kres): left unwritten
       const hipError_t e = launch_solve(h, h.kres, st, -1, nullptr, 1, 0, false);
       h.pact = pact;
       HIP_TRY(e);
       HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st, h.rmask));
-      HIP_TRY(launch_axpy(h.kcor, W.sol, h.kres, 1.0, nkkt, st));
+      HIP_TRY(launch_axpy_rows(h, h.rmask, h.kcor, W.sol, h.kres, 1.0, st));
       // the residual of the corrected iterate only for the refining problems
       // (the others' rows and partials come out zero and k_ctl_refine skips them)
       h.pact = h.rmask;

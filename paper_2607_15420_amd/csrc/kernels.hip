@@ -566,6 +566,17 @@ __global__ void k_copy_rows(const int* __restrict__ mask, const StageInfo* __res
   }
 }
 
+// z = y + a x on the rows of the problems in mask (stage rows and design rows)
+__global__ void k_axpy_rows(const int* __restrict__ mask, const StageInfo* __restrict__ sinfo, long long nks, int P,
+                            int npar, double* z, const double* y, const double* __restrict__ x, double a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nks) {
+    if (mask[sinfo[i / NK].p]) z[i] = y[i] + a * x[i];
+  } else if (i < nks + (long long)P * npar) {
+    if (mask[(i - nks) / npar]) z[i] = y[i] + a * x[i];
+  }
+}
+
 inline unsigned grid_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -724,6 +735,14 @@ hipError_t launch_tile_x0(Handle& h, double* x, hipStream_t st) {
 
 hipError_t launch_axpy(double* z, const double* y, const double* x, double a, long long n, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n, 256)), dim3(256), 0, st, z, y, x, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_rows(Handle& h, const int* mask, double* z, const double* y, const double* x, double a,
+                            hipStream_t st) {
+  const long long nks = h.nst * NK;
+  hipLaunchKernelGGL(k_axpy_rows, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, h.npar, z,
+                     y, x, a);
   return hipGetLastError();
 }
 
