@@ -211,7 +211,7 @@ struct Handle {
   double* pres = nullptr;                    // device [2P]
   double* pres_h = nullptr;                  // pinned [2P]
   int* rmask = nullptr;                      // device [P]
-  int* rmask_h = nullptr;                    // pinned [2P]: revert mask, then refining mask (an async copy
+  int* rmask_h = nullptr;                    // pinned [2P]: kept-candidate mask, then refining mask (an async copy
                                              // reads its source when it runs, so the two never share memory)
   ModelParams mp{};
   double xL[NV], xU[NV], dL = 0, dU = 0;     // unscaled bounds per local variable

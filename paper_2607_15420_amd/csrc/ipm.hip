@@ -1472,85 +1472,100 @@ int kkt_solve_refined(Handle& h, const double* rhs, double* sol, bool fused_firs
   const bool per_problem = P > 1;
   std::vector<double> best((size_t)P, INFINITY);
   std::vector<char> refining((size_t)P, 1);
+  if (per_problem) {
+    // In a batch, sol holds every problem's best iterate and h.kcor the
+    // corrected candidate of the refining ones; each step reads and writes only
+    // the rows of the problems it concerns (residual, solve, Schur step and
+    // update under the refining mask, the candidates that lowered their
+    // residual copied into sol), so the other rows are neither cleared nor read.
+    // The arithmetic of each problem is that of the single-problem loop below.
+    int* const pact = h.pact;
+    const bool pact_on = h.pact_on;
+    for (int it = 0; it <= 10; ++it) {
+      if (it > 0 || !first_residual_read) {  // else the caller has taken the first residual
+        if (it > 0) {
+          h.pact = h.rmask;  // the problems corrected in the previous step
+          h.pact_on = true;
+        }
+        const hipError_t e = launch_residual(h, h.diagx, h.diags, it > 0 ? h.kcor : sol, rhs, h.kres,
+                                             h.omega_d, st, it == 0);
+        h.pact = pact;
+        h.pact_on = pact_on;
+        HIP_TRY(e);
+      }
+      HIP_TRY(launch_residual_pmax(h, st));
+      HIP_TRY(hipMemcpyAsync(h.pres_h, h.pres, sizeof(double) * 2 * P, hipMemcpyDeviceToHost, st));
+      HIP_TRY(wait_stream(st));
+      // first half of the pinned mask: the candidates kept; second half: the
+      // problems refining on (both copies of the last step have completed)
+      int* const keep_h = h.rmask_h;
+      int* const ref_h = h.rmask_h + P;
+      bool any_keep = false, any_left = false;
+      for (int p = 0; p < P; ++p) {
+        keep_h[p] = 0;
+        if (refining[(size_t)p]) {
+          const double r = h.pres_h[2 * p], b = h.pres_h[2 * p + 1];
+          const double relr = b > 0.0 ? r / b : r;
+          if (relr < best[(size_t)p]) {
+            best[(size_t)p] = relr;
+            if (it > 0) {
+              keep_h[p] = 1;
+              any_keep = true;
+            }
+            if (relr <= target) refining[(size_t)p] = 0;
+          } else {  // no decrease (or not finite): sol keeps its previous iterate
+            refining[(size_t)p] = 0;
+          }
+        }
+        ref_h[p] = refining[(size_t)p] ? 1 : 0;
+        any_left = any_left || refining[(size_t)p];
+      }
+      if (any_keep) {
+        HIP_TRY(hipMemcpyAsync(h.rmask, keep_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_copy_rows(h, h.rmask, sol, h.kcor, st));
+      }
+      if (!any_left || it == 10) break;
+      HIP_TRY(hipMemcpyAsync(h.rmask, ref_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
+      h.pact = h.rmask;
+      h.pact_on = true;
+      const hipError_t e = launch_solve(h, h.kres, st, -1, nullptr, 1, 0, false);
+      h.pact = pact;
+      h.pact_on = pact_on;
+      HIP_TRY(e);
+      HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st, h.rmask));       // the correction
+      HIP_TRY(launch_axpy_rows(h, h.rmask, h.kcor, sol, h.kres, 1.0, st));  // candidate = sol + correction
+    }
+    double worst = 0.0;
+    for (int p = 0; p < P; ++p) {
+      worst = std::max(worst, best[(size_t)p]);
+      if (rel_p) rel_p[p] = best[(size_t)p];
+    }
+    if (rel) *rel = worst;
+    return ABS_OK;
+  }
+  // One problem: corrections are applied out of place, xn = xb + correction,
+  // where xb is the best iterate so far; if the residual grows, xb is kept.
   double* xb = sol;
   double* xn = sol;
   double* om = h.redbuf_h + h.red_cap - 4;  // four pinned doubles past the partials
   for (int it = 0; it <= 10; ++it) {
     if (it > 0 || !first_residual_read) {  // else the caller has read the first residual's norms into om
-      // after a correction only the problems that took it need their residual:
-      // the device mask holds the refining problems of the previous step (the
-      // others get zero rows and partials, which are neither read nor used)
-      int* const pact = h.pact;
-      const bool pact_on = h.pact_on;
-      if (per_problem && it > 0) {
-        h.pact = h.rmask;
-        h.pact_on = true;
-      }
-      // (rows of the other problems left unwritten: mask_rows clears them below)
-      const hipError_t e =
-          launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st, !(per_problem && it > 0));
-      h.pact = pact;
-      h.pact_on = pact_on;
-      HIP_TRY(e);
+      HIP_TRY(launch_residual(h, h.diagx, h.diags, xn, rhs, h.kres, h.omega_d, st));
       HIP_TRY(hipMemcpyAsync(om, h.omega_d, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-      if (!per_problem) HIP_TRY(wait_stream(st));
-    }
-    if (per_problem) {  // per-problem maxima of the same residual
-      HIP_TRY(launch_residual_pmax(h, st));
-      HIP_TRY(hipMemcpyAsync(h.pres_h, h.pres, sizeof(double) * 2 * P, hipMemcpyDeviceToHost, st));
       HIP_TRY(wait_stream(st));
     }
-    bool any_revert = false, any_left = false;
-    for (int p = 0; p < P; ++p) {
-      h.rmask_h[p] = 0;
-      if (!refining[(size_t)p]) continue;
-      const double r = per_problem ? h.pres_h[2 * p] : om[2];
-      const double b = per_problem ? h.pres_h[2 * p + 1] : om[3];
-      const double relr = b > 0.0 ? r / b : r;
-      if (relr < best[(size_t)p]) {
-        best[(size_t)p] = relr;
-        if (!per_problem) h.last_omega = fmax(om[0], om[1]);  // backward error of the kept iterate
-        if (relr <= target) refining[(size_t)p] = 0;
-      } else {  // no decrease (or not finite): this problem keeps its previous iterate
-        refining[(size_t)p] = 0;
-        if (xn != xb) {
-          h.rmask_h[p] = 1;
-          any_revert = true;
-        }
-      }
-      any_left = any_left || refining[(size_t)p];
+    const double relr = om[3] > 0.0 ? om[2] / om[3] : om[2];
+    if (relr < best[0]) {
+      best[0] = relr;
+      h.last_omega = fmax(om[0], om[1]);  // backward error of the kept iterate
+      if (relr <= target) break;
+    } else {  // no decrease (or not finite): the previous iterate is kept
+      xn = xb;
+      break;
     }
-    if (any_revert) {
-      if (per_problem) {
-        HIP_TRY(hipMemcpyAsync(h.rmask, h.rmask_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_copy_rows(h, h.rmask, xn, xb, st));
-      } else {
-        xn = xb;  // the single problem's best iterate is the whole of xb
-      }
-    }
-    if (!any_left || it == 10) break;
-    if (per_problem) {
-      // second half of the pinned mask: the revert copy above may not have run yet
-      int* const ref_h = h.rmask_h + P;
-      for (int p = 0; p < P; ++p) ref_h[p] = refining[(size_t)p] ? 1 : 0;
-      HIP_TRY(hipMemcpyAsync(h.rmask, ref_h, sizeof(int) * P, hipMemcpyHostToDevice, st));
-      HIP_TRY(launch_mask_rows(h, h.rmask, h.kres, st));
-      int* const pact = h.pact;
-      const bool pact_on = h.pact_on;
-      h.pact = h.rmask;
-      h.pact_on = true;
-      // the other problems' rows of the solution are not read (masked Schur
-      // step and combine): left unwritten
-      const hipError_t e = launch_solve(h, h.kres, st, -1, nullptr, 1, 0, false);
-      h.pact = pact;
-      h.pact_on = pact_on;
-      HIP_TRY(e);
-    } else {
-      HIP_TRY(launch_solve(h, h.kres, st));
-    }
-    // correction in place (in a batch only for the refining problems: the others'
-    // rows of kres stay zero and their Schur scalars are not read again)
-    HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st, per_problem ? h.rmask : nullptr));
+    if (it == 10) break;
+    HIP_TRY(launch_solve(h, h.kres, st));
+    HIP_TRY(launch_schur(h, h.diagx, h.kres, 2, h.kres, st));  // the correction, in place
     double* xnew = xn == sol ? h.kcor : sol;
     HIP_TRY(launch_axpy(xnew, xn, h.kres, 1.0, h.nkkt, st));  // xnew = xn + correction
     xb = xn;
