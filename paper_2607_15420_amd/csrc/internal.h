@@ -375,8 +375,6 @@ hipError_t launch_residual(Handle& h, const double* diagx, const double* diags, 
 // per problem p: pres[2p] = max |res_i|, pres[2p + 1] = max |rhs_i| over its
 // rows (stage rows and its d row) from the partials of the last launch_residual
 hipError_t launch_residual_pmax(Handle& h, hipStream_t st);
-// res_i = 0 on the rows of the problems whose mask entry is 0
-hipError_t launch_mask_rows(Handle& h, const int* mask, double* res, hipStream_t st);
 // dst_i = src_i on the KKT rows of the problems whose mask entry is not 0
 hipError_t launch_copy_rows(Handle& h, const int* mask, double* dst, const double* src, hipStream_t st);
 // x <- the cold-start point (h.x0 in every stage, its diameter for every problem)

@@ -546,16 +546,6 @@ __global__ __launch_bounds__(256) void k_residual_pmax(const double* __restrict_
 }
 
 // res_i = 0 on the stage rows and the d row of the problems with mask 0
-__global__ void k_mask_rows(const int* __restrict__ mask, const StageInfo* __restrict__ sinfo, long long nks, int P,
-                            int npar, double* __restrict__ res) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nks) {
-    if (!mask[sinfo[i / NK].p]) res[i] = 0.0;
-  } else if (i < nks + (long long)P * npar) {
-    if (!mask[(i - nks) / npar]) res[i] = 0.0;
-  }
-}
-
 __global__ void k_copy_rows(const int* __restrict__ mask, const StageInfo* __restrict__ sinfo, long long nks, int P,
                             int npar, double* __restrict__ dst, const double* __restrict__ src) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -709,13 +699,6 @@ hipError_t launch_residual_pmax(Handle& h, hipStream_t st) {
   const double* omb = h.kden + 2LL * nb;
   const double* omd = omb + 3LL * nb;
   hipLaunchKernelGGL(k_residual_pmax, dim3(h.P), dim3(256), 0, st, omb, h.pseg, omd, h.pres);
-  return hipGetLastError();
-}
-
-hipError_t launch_mask_rows(Handle& h, const int* mask, double* res, hipStream_t st) {
-  const long long nks = h.nst * NK;
-  hipLaunchKernelGGL(k_mask_rows, dim3(grid_for(h.nkkt, 256)), dim3(256), 0, st, mask, h.sinfo, nks, h.P, h.npar,
-                     res);
   return hipGetLastError();
 }
 
